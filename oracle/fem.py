@@ -1,0 +1,154 @@
+"""Q1 finite element matrices on a uniform tensor grid (oracle; test infrastructure only).
+
+Unknowns are the nodal values at interior nodes of the uniform partition of
+each axis (Section 2.1, the space V_h of eq. (2.4)); Dirichlet nodes are
+dropped.  Arrays of nodal values have shape (n_{d-1}, ..., n_0) with axis 0
+(x) fastest, n_a = N_a - 1, so a flat index is sum_a i_a * prod_{b<a} n_b.
+"""
+import itertools
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def p1_element_matrices(h):
+    """Mass and stiffness matrices of one linear element of length h.
+
+    Entry (a, b) of the mass matrix is the integral of phi_a * phi_b over the
+    element and of the stiffness matrix the integral of phi_a' * phi_b', for
+    the two hat-function pieces phi_0, phi_1 of the element (Section 2.1).
+    """
+    me = (h / 6.0) * np.array([[2.0, 1.0], [1.0, 2.0]])
+    ke = (1.0 / h) * np.array([[1.0, -1.0], [-1.0, 1.0]])
+    return me, ke
+
+
+def assemble_1d(N, h):
+    """1D interior mass matrix A and stiffness matrix B (dense, (N-1)x(N-1)).
+
+    Built by summing element matrices over the N elements of the uniform
+    partition and removing the two boundary nodes (homogeneous Dirichlet
+    data, eq. (2.1)).  Section 4 states the result as A = (h/6) R and
+    B = (1/h) G^D; the tests check that independently.
+    """
+    me, ke = p1_element_matrices(h)
+    full_m = np.zeros((N + 1, N + 1))
+    full_k = np.zeros((N + 1, N + 1))
+    for e in range(N):
+        idx = [e, e + 1]
+        for a in range(2):
+            for b in range(2):
+                full_m[idx[a], idx[b]] += me[a, b]
+                full_k[idx[a], idx[b]] += ke[a, b]
+    return full_m[1:N, 1:N].copy(), full_k[1:N, 1:N].copy()
+
+
+def _kron_list(mats):
+    out = sp.csr_matrix(mats[0])
+    for m in mats[1:]:
+        out = sp.kron(out, sp.csr_matrix(m), format="csr")
+    return out
+
+
+def mass_stiffness(N, h, D):
+    """Global mass M and stiffness K (sparse CSR) of the tensor Q1 space.
+
+    Section 4, eq. (4.1): M = A_z (x) A_y (x) A_x and
+    K = D * sum over axes of the same product with that axis' A replaced by
+    its B.  Kronecker factors are ordered slowest axis first so that x is the
+    fastest index, matching the array layout of this package.
+    """
+    d = len(N)
+    ones = [assemble_1d(N[a], h[a]) for a in range(d)]
+    A = [ones[a][0] for a in range(d)]
+    B = [ones[a][1] for a in range(d)]
+    M = _kron_list([A[a] for a in reversed(range(d))])
+    K = None
+    for ax in range(d):
+        fac = [B[a] if a == ax else A[a] for a in reversed(range(d))]
+        term = _kron_list(fac)
+        K = term if K is None else K + term
+    return M, (D * K).tocsr()
+
+
+def q1_quadrature_assembly(N, h, D, origin=None):
+    """Mass and stiffness by Gauss quadrature over each Q1 element (dense).
+
+    Independent of the Kronecker formula: for every box element, the 2^d
+    multilinear shape functions and their gradients are evaluated at the
+    2-point-per-axis Gauss points (exact for these polynomial integrands),
+    giving (phi_i, phi_j) and a(phi_i, phi_j) = int D grad phi_i . grad phi_j
+    (eq. (2.3)), which are summed into the interior-node numbering.
+    Only meant for tiny grids.
+    """
+    d = len(N)
+    n = [N[a] - 1 for a in range(d)]
+    ndof = int(np.prod(n))
+    strides = [int(np.prod(n[:a])) for a in range(d)]
+    gp = np.array([-1.0, 1.0]) / np.sqrt(3.0)  # on [-1, 1]
+    gw = np.array([1.0, 1.0])
+    M = np.zeros((ndof, ndof))
+    K = np.zeros((ndof, ndof))
+    corners = list(itertools.product([0, 1], repeat=d))
+    # reference element [0,1]^d scaled by h: shape fn of corner c is
+    # prod_a (xi_a if c_a else 1 - xi_a), xi in [0,1]
+    qpts = list(itertools.product(range(2), repeat=d))
+    for elem in itertools.product(*[range(N[a]) for a in range(d)]):
+        gidx = []
+        for c in corners:
+            node = [elem[a] + c[a] for a in range(d)]
+            if any(node[a] == 0 or node[a] == N[a] for a in range(d)):
+                gidx.append(-1)
+            else:
+                gidx.append(sum((node[a] - 1) * strides[a] for a in range(d)))
+        me = np.zeros((len(corners), len(corners)))
+        ke = np.zeros((len(corners), len(corners)))
+        for q in qpts:
+            xi = [(gp[q[a]] + 1.0) / 2.0 for a in range(d)]
+            w = np.prod([gw[q[a]] * h[a] / 2.0 for a in range(d)])
+            val = []
+            grad = []
+            for c in corners:
+                f1 = [xi[a] if c[a] else 1.0 - xi[a] for a in range(d)]
+                df = [(1.0 if c[a] else -1.0) / h[a] for a in range(d)]
+                val.append(np.prod(f1))
+                g = []
+                for a in range(d):
+                    g.append(df[a] * np.prod([f1[b] for b in range(d) if b != a]))
+                grad.append(np.array(g))
+            for i in range(len(corners)):
+                for j in range(len(corners)):
+                    me[i, j] += w * val[i] * val[j]
+                    ke[i, j] += w * D * float(np.dot(grad[i], grad[j]))
+        for i, gi in enumerate(gidx):
+            if gi < 0:
+                continue
+            for j, gj in enumerate(gidx):
+                if gj < 0:
+                    continue
+                M[gi, gj] += me[i, j]
+                K[gi, gj] += ke[i, j]
+    return M, K
+
+
+def node_coords(N, h, origin=None):
+    """Coordinates of the interior nodes, one 1-D array per axis.
+
+    Node j of axis a sits at a_a + j * h_a (Section 2.1); interior nodes are
+    j = 1 .. N_a - 1.
+    """
+    d = len(N)
+    origin = [0.0] * d if origin is None else list(origin)
+    return [origin[a] + h[a] * np.arange(1, N[a]) for a in range(d)]
+
+
+def mesh(N, h, origin=None):
+    """Broadcastable coordinate arrays shaped like a nodal array (x fastest)."""
+    d = len(N)
+    xs = node_coords(N, h, origin)
+    out = []
+    for a in range(d):
+        shape = [1] * d
+        shape[d - 1 - a] = N[a] - 1
+        out.append(xs[a].reshape(shape))
+    return out

@@ -1,0 +1,77 @@
+"""Error norms and energy (oracle; test infrastructure only).
+
+The paper reports ||u(t_n) - u_h^n||_0 and ||u(t_n) - u_h^n||_1 (Section 5.1)
+without naming a quadrature.  Two versions are provided:
+  * discrete: for a nodal error vector e, ||e||_0^2 = e^T M e and
+    ||e||_1^2 = e^T M e + e^T K_1 e with K_1 the stiffness matrix for D = 1
+    (the full H1 norm of the finite element function with those nodal values);
+  * quadrature: the error between an exact solution and the Q1 function with
+    the given nodal values (zero on the boundary), integrated with 4x4 Gauss
+    points per element (2D only).
+"""
+import numpy as np
+
+from . import fem
+
+
+def discrete_norms(N, h, e):
+    """Return (L2, H1, max) of the finite element function with nodal values e."""
+    M, K1 = fem.mass_stiffness(N, h, 1.0)
+    v = np.asarray(e, dtype=np.float64).reshape(-1)
+    m2 = float(v @ (M @ v))
+    k2 = float(v @ (K1 @ v))
+    return np.sqrt(m2), np.sqrt(m2 + k2), float(np.max(np.abs(v))) if v.size else 0.0
+
+
+def allen_cahn_energy(N, h, D, U):
+    """Discrete Allen-Cahn energy (D/2) U^T K_1 U + sum_i prod(h) (U_i^2 - 1)^2 / 4.
+
+    The paper defines an energy only for its Flory-Huggins example; this is
+    the double-well analogue with the gradient term taken from the stiffness
+    matrix and the potential by nodal quadrature over interior nodes.
+    """
+    _, K1 = fem.mass_stiffness(N, h, 1.0)
+    v = np.asarray(U, dtype=np.float64).reshape(-1)
+    grad = 0.5 * D * float(v @ (K1 @ v))
+    pot = float(np.prod(h)) * float(np.sum(0.25 * (v * v - 1.0) ** 2))
+    return grad + pot
+
+
+def quadrature_errors_2d(N, h, origin, U, exact, exact_grad, t, chunk_rows=64):
+    """Continuous L2 and H1 errors between exact(t, .) and the Q1 function of U (2D).
+
+    4x4 Gauss points per rectangle; the Q1 function takes nodal values U at
+    interior nodes and 0 at boundary nodes.
+    """
+    Nx, Ny = N
+    hx, hy = h
+    ax, ay = origin
+    full = np.zeros((Ny + 1, Nx + 1))
+    full[1:Ny, 1:Nx] = np.asarray(U).reshape(Ny - 1, Nx - 1)
+    g, w = np.polynomial.legendre.leggauss(4)
+    g = (g + 1.0) / 2.0
+    w = w / 2.0
+    l2 = 0.0
+    semi = 0.0
+    for r0 in range(0, Ny, chunk_rows):
+        r1 = min(Ny, r0 + chunk_rows)
+        v00 = full[r0:r1, 0:Nx]
+        v10 = full[r0:r1, 1:Nx + 1]
+        v01 = full[r0 + 1:r1 + 1, 0:Nx]
+        v11 = full[r0 + 1:r1 + 1, 1:Nx + 1]
+        x0 = ax + hx * np.arange(Nx)[None, :]
+        y0 = ay + hy * np.arange(r0, r1)[:, None]
+        for i in range(4):
+            for j in range(4):
+                xi, eta = g[i], g[j]
+                wt = w[i] * w[j] * hx * hy
+                uh = ((1 - xi) * (1 - eta) * v00 + xi * (1 - eta) * v10
+                      + (1 - xi) * eta * v01 + xi * eta * v11)
+                dux = ((1 - eta) * (v10 - v00) + eta * (v11 - v01)) / hx
+                duy = ((1 - xi) * (v01 - v00) + xi * (v11 - v10)) / hy
+                X = (x0 + xi * hx, y0 + eta * hy)
+                ue = exact(t, X)
+                gx, gy = exact_grad(t, X)
+                l2 += wt * float(np.sum((ue - uh) ** 2))
+                semi += wt * float(np.sum((gx - dux) ** 2 + (gy - duy) ** 2))
+    return np.sqrt(l2), np.sqrt(l2 + semi)

@@ -1,0 +1,76 @@
+"""Reaction terms and exact solutions of the test problems (oracle; test infrastructure only).
+
+A reaction is a callable f(t, X, U): t the time, X the coordinate arrays of
+the interior nodes (broadcastable to U), U the nodal values.
+"""
+import numpy as np
+
+
+def zero():
+    return lambda t, X, U: np.zeros_like(U)
+
+
+def constant(c0):
+    """u-independent, space- and time-constant forcing."""
+    return lambda t, X, U: np.full_like(U, c0)
+
+
+def affine_t(c0, c1):
+    """u-independent forcing c0 + c1 t."""
+    return lambda t, X, U: np.full_like(U, c0 + c1 * t)
+
+
+def allen_cahn():
+    """Allen-Cahn reaction u - u^3 (double-well potential; with D = eps^2)."""
+    return lambda t, X, U: U - U ** 3
+
+
+def _sine_product(X):
+    s = 1.0
+    for x in X:
+        s = s * np.sin(np.pi * x)
+    return s
+
+
+def mms_u2(D):
+    """Manufactured problem u_t = D Lap u + u^2 + g on (0,1)^d.
+
+    Exact solution u = exp(-t) prod_a sin(pi x_a); substituting it gives
+    g = (d pi^2 D - 1) e^{-t} s - e^{-2t} s^2 with s = prod_a sin(pi x_a).
+    """
+    def f(t, X, U):
+        d = len(X)
+        s = _sine_product(X)
+        g = (d * np.pi ** 2 * D - 1.0) * np.exp(-t) * s - np.exp(-2.0 * t) * s * s
+        return U * U + g
+    return f
+
+
+def mms_u2_exact(t, X):
+    return np.exp(-t) * _sine_product(X)
+
+
+def ex51():
+    """Example 5.1 reaction: -pi^2/2 u + pi^2/2 e^{-pi^2 t} sin(pi x) sin(pi y), D = 1/2."""
+    def f(t, X, U):
+        x, y = X
+        return (-0.5 * np.pi ** 2 * U
+                + 0.5 * np.pi ** 2 * np.exp(-np.pi ** 2 * t) * np.sin(np.pi * x) * np.sin(np.pi * y))
+    return f
+
+
+def ex51_exact(t, X):
+    """Example 5.1 exact solution e^{-pi^2 t} (sin(pi x) - 1) sin(pi y)."""
+    x, y = X
+    return np.exp(-np.pi ** 2 * t) * (np.sin(np.pi * x) - 1.0) * np.sin(np.pi * y)
+
+
+def ex51_exact_grad(t, X):
+    x, y = X
+    e = np.exp(-np.pi ** 2 * t)
+    return (e * np.pi * np.cos(np.pi * x) * np.sin(np.pi * y),
+            e * (np.sin(np.pi * x) - 1.0) * np.pi * np.cos(np.pi * y))
+
+
+EX51_ORIGIN = (0.5, 0.0)
+EX51_D = 0.5

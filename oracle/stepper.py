@@ -1,0 +1,72 @@
+"""EIFE1 and EIFE2 time stepping (oracle; test infrastructure only).
+
+Section 2.2.  With uniform steps tau and t_n = t0 + n tau, the EIFE1 scheme
+(eq. (2.13)) is
+    u^{n+1} = e^{-tau L} u^n + tau phi_1(-tau L) P_h f(t_n, u^n)
+and the EIFE2 scheme (eq. (2.14)), with node c2 in (0, 1], is
+    U2      = e^{-c2 tau L} u^n + c2 tau phi_1(-c2 tau L) P_h f(t_n, u^n)
+    u^{n+1} = e^{-tau L} u^n
+              + tau [ (phi_1(-tau L) - phi_2(-tau L)/c2) P_h f(t_n, u^n)
+                      + (phi_2(-tau L)/c2) P_h f(t_n + c2 tau, U2) ].
+All operator functions act through a basis of `spectral` (z = -tau Lam).
+
+The load P_h f(t, u_h) is read in one of two ways (the paper writes the load
+tensor with entries (f(t, u_ijk), phi_i phi_j phi_k) in Section 4 but the
+projection of f(u_h) in Section 2):
+    "lumped" (default): F_i = f(t, u_i) * int phi_i = f(t, u_i) * prod_a h_a,
+                        so P_h f = M^{-1} F
+    "nodal":            P_h f is the interpolant with nodal values f(t, u_i).
+"""
+import numpy as np
+
+from . import fem
+from .phi import phi
+
+
+def load_spectral(basis, f, t, U, X, load):
+    val = f(t, X, U)
+    val = np.broadcast_to(val, U.shape).astype(np.float64)
+    if load == "lumped":
+        return basis.load_to_spectral(val * float(np.prod(basis.h)))
+    if load == "nodal":
+        return basis.to_spectral(val)
+    raise ValueError(load)
+
+
+def run(basis, u0, f, tau, n_steps, stages, c2=0.5, t0=0.0, load="lumped",
+        origin=None, callback=None):
+    """Advance nodal values u0 by n_steps EIFE steps; returns nodal u^n.
+
+    f(t, X, U) is the reaction, X the coordinate arrays of the interior nodes.
+    callback(n, t_n, U) is called after every step when given.
+    """
+    if stages not in (1, 2):
+        raise ValueError("stages must be 1 or 2")
+    if not (0.0 < c2 <= 1.0):
+        raise ValueError("c2 must lie in (0, 1]")
+    X = fem.mesh(basis.N, basis.h, origin)
+    z = -tau * basis.lam
+    E = phi(0, z)
+    P1 = phi(1, z)
+    if stages == 1:
+        pass
+    else:
+        P2 = phi(2, z)
+        Ec = phi(0, c2 * z)
+        P1c = phi(1, c2 * z)
+    U = np.array(u0, dtype=np.float64).reshape(basis.shape)
+    c = basis.to_spectral(U)
+    for n in range(n_steps):
+        tn = t0 + n * tau
+        G1 = load_spectral(basis, f, tn, U, X, load)
+        if stages == 1:
+            c = E * c + tau * P1 * G1
+        else:
+            c_stage = Ec * c + c2 * tau * P1c * G1
+            U2 = basis.from_spectral(c_stage)
+            G2 = load_spectral(basis, f, tn + c2 * tau, U2, X, load)
+            c = E * c + tau * ((P1 - P2 / c2) * G1 + (P2 / c2) * G2)
+        U = basis.from_spectral(c)
+        if callback is not None:
+            callback(n + 1, t0 + (n + 1) * tau, U)
+    return U
