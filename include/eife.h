@@ -1,0 +1,148 @@
+/*
+ * eife.h -- C ABI of the MI355X (gfx950) exponential-integrator Q1 finite
+ * element library.
+ *
+ * The library advances u_t = D Lap u + f(t, u) on a rectangle
+ * prod_a [a_a, a_a + N_a h_a] (d = 1, 2, 3) with homogeneous Dirichlet data
+ * (Section 1, eq. (1.1); Section 2, eq. (2.1)), discretised in space with
+ * continuous multilinear (Q1) elements on the uniform tensor grid of
+ * Section 2.1 (eq. (2.4)) and in time with the explicit exponential
+ * Runge-Kutta schemes EIFE1 (eq. (2.13)) and EIFE2 (eq. (2.14)).  Each step
+ * uses the simultaneous diagonalisation of the mass and stiffness matrices
+ * by the sine transform (Section 4, eqs. (4.1)-(4.4)): type-I sine transforms
+ * along every axis, a diagonal phi_k(-tau D lambda) scaling, and the
+ * pointwise reaction f evaluated at the nodes.
+ *
+ * Conventions shared by every call
+ *   - Every call returns an int status: EIFE_OK (0) or a negative code.
+ *     Nothing is thrown across the ABI.  eife_last_error() returns a message
+ *     for the calling thread's most recent failure.
+ *   - Nodal arrays ("u") live in device memory owned by the caller: the
+ *     values at interior nodes, (N_{d-1}-1) x ... x (N_0-1) contiguous
+ *     elements of the grid's dtype, axis 0 (x) fastest, boundary nodes not
+ *     stored.  The library keeps no pointer to them after a call returns.
+ *   - The grid owns its device workspaces (spectral state, work array,
+ *     tables), allocated by eife_create_grid and released by
+ *     eife_destroy_grid.  A grid may be used from one host thread at a time.
+ *   - Work is enqueued on the HIP stream passed in (NULL = the default
+ *     stream) and is asynchronous unless stated otherwise.  Argument errors
+ *     are reported synchronously; a failed kernel launch returns EIFE_EHIP.
+ */
+#ifndef EIFE_H
+#define EIFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eife_grid_s* eife_grid;
+
+enum eife_status {
+  EIFE_OK = 0,
+  EIFE_EINVAL = -1,       /* bad argument */
+  EIFE_ENOMEM = -2,       /* device allocation failed */
+  EIFE_EUNSUPPORTED = -3, /* valid request this build does not implement */
+  EIFE_ESTATE = -4,       /* call out of order (e.g. step before set_phi) */
+  EIFE_EHIP = -5,         /* HIP runtime error */
+  EIFE_ENONFINITE = -6    /* a reduction produced a non-finite value */
+};
+
+enum eife_bc { EIFE_BC_DIRICHLET = 0, EIFE_BC_PERIODIC = 1 };
+enum eife_dtype { EIFE_F32 = 0, EIFE_F64 = 1 };
+
+/* Reaction terms f(t, x, u). */
+enum eife_fkind {
+  EIFE_F_ZERO = 0,       /* f = 0 (pure diffusion) */
+  EIFE_F_ALLEN_CAHN = 1, /* f = u - u^3 (with D = eps^2) */
+  EIFE_F_MMS_U2 = 2,     /* f = u^2 + g, g chosen so u = e^{-t} prod_a sin(pi x_a) solves the PDE:
+                            g = (d pi^2 D - 1) e^{-t} s - e^{-2t} s^2, s = prod_a sin(pi x_a) */
+  EIFE_F_EX51 = 3,       /* Section 5.1, Example 5.1 (d = 2):
+                            f = -(pi^2/2) u + (pi^2/2) e^{-pi^2 t} sin(pi x) sin(pi y) */
+  EIFE_F_CONST = 4,      /* f = c0, independent of u, x and t (c0 from eife_set_forcing) */
+  EIFE_F_AFFINE_T = 5    /* f = c0 + c1 t, independent of u and x */
+};
+
+/* How P_h f(t, u_h) is formed from the nodal values of f (the paper's load
+ * tensor has entries (f(t, u_ijk), phi_i phi_j phi_k), Section 4). */
+enum eife_load {
+  EIFE_LOAD_LUMPED = 0, /* default: F_i = f(t, u_i) * prod_a h_a, P_h f = M^{-1} F */
+  EIFE_LOAD_NODAL = 1   /* P_h f replaced by the interpolant of the nodal values f(t, u_i) */
+};
+
+/* Create a grid: d in {1,2,3}; N[a] >= 2 intervals on axis a (N[a]-1 interior
+ * nodes, N[a] <= 4096 and of the form 2^i 3^j); h[a] > 0 the mesh
+ * width; D > 0 the diffusion coefficient (eq. (1.1)); bc must be
+ * EIFE_BC_DIRICHLET (EIFE_BC_PERIODIC returns EIFE_EUNSUPPORTED); dtype is
+ * EIFE_F32 or EIFE_F64, the precision of nodal arrays and transforms
+ * (eigenvalue and phi factors are always formed in double).  The origin
+ * defaults to 0, c2 to 1/2 and the load to EIFE_LOAD_LUMPED.  On success
+ * *out receives the grid.  Errors: EIFE_EINVAL, EIFE_EUNSUPPORTED,
+ * EIFE_ENOMEM, EIFE_EHIP. */
+int eife_create_grid(int d, const int32_t* N, const double* h, double D, int bc, int dtype,
+                     eife_grid* out);
+
+/* Release the grid and its device memory.  Waits for no stream: the caller
+ * must make sure no enqueued step on the grid is still running.  NULL is
+ * accepted and ignored. */
+int eife_destroy_grid(eife_grid g);
+
+/* Fix the step tau > 0 and the number of exponential Runge-Kutta stages:
+ * 1 = EIFE1 (eq. (2.13)), 2 = EIFE2 (eq. (2.14)) with node c2.  Builds the
+ * per-axis double tables of e^{-tau D lambda} and e^{-c2 tau D lambda}.
+ * Must precede eife_step; repeat after eife_set_c2 or to change tau.
+ * Synchronous with respect to the host (tables are uploaded before return). */
+int eife_set_phi(eife_grid g, double tau, int stages);
+
+/* EIFE2 node c2 in (0, 1] (Section 2.2, default 1/2).  Invalidates the phi
+ * tables: call eife_set_phi again before stepping. */
+int eife_set_c2(eife_grid g, double c2);
+
+/* Lower corner a[0..d-1] of the rectangle (default 0); only the reaction
+ * kinds that depend on x use it. */
+int eife_set_origin(eife_grid g, const double* a);
+
+/* Load reading, EIFE_LOAD_LUMPED or EIFE_LOAD_NODAL. */
+int eife_set_load(eife_grid g, int kind);
+
+/* Parameters c0, c1 of EIFE_F_CONST / EIFE_F_AFFINE_T. */
+int eife_set_forcing(eife_grid g, double c0, double c1);
+
+/* Advance the nodal values u (device pointer, in place) by n_steps >= 0
+ * uniform steps of the scheme fixed by eife_set_phi, from time t0: step n
+ * evaluates f at t0 + n tau (and at t0 + (n + c2) tau for the second EIFE2
+ * stage, eq. (2.10)).  u must hold the grid's element count in its dtype.
+ * Enqueued on `stream` (a hipStream_t, NULL = default stream); returns
+ * after enqueueing.  Errors: EIFE_EINVAL (null u, negative n_steps, unknown
+ * f_kind, EX51 with d != 2), EIFE_ESTATE (no eife_set_phi), EIFE_EHIP. */
+int eife_step(eife_grid g, void* u, int64_t n_steps, int f_kind, double t0, void* stream);
+
+/* Double-precision norms of the finite element function with nodal values
+ * e = u - uref (uref may be NULL, then e = u), both device arrays in the
+ * grid's layout and dtype:
+ *   out[0] = sqrt(e^T M e)                  (L2 norm, M the Q1 mass matrix)
+ *   out[1] = sqrt(e^T M e + e^T K_1 e)       (H1 norm, K_1 the stiffness for D = 1)
+ *   out[2] = max_i |e_i|
+ *   out[3] = (D/2) u^T K_1 u + prod(h) sum_i (u_i^2 - 1)^2 / 4   (Allen-Cahn energy of u)
+ * Section 5 reports ||u(t_n) - u_h^n||_0 and ||.||_1; the energy is the
+ * double-well analogue of the Flory-Huggins energy of Section 5.2.
+ * Blocks the host until `stream` has produced the four values (host array
+ * out[4]).  Returns EIFE_ENONFINITE (values still written) if any is not
+ * finite. */
+int eife_norms(eife_grid g, const void* u, const void* uref, double* out, void* stream);
+
+/* Number of interior nodes of the grid (elements of a nodal array). */
+int eife_grid_size(eife_grid g, int64_t* count);
+
+/* Message describing the calling thread's most recent failed call. */
+const char* eife_last_error(void);
+
+/* ABI version of this library. */
+int eife_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EIFE_H */

@@ -1,0 +1,154 @@
+"""ctypes binding of the C ABI declared in include/eife.h (argument marshalling only)."""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+# status codes
+OK, EINVAL, ENOMEM, EUNSUPPORTED, ESTATE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+# enums
+BC_DIRICHLET, BC_PERIODIC = 0, 1
+F32, F64 = 0, 1
+F_ZERO, F_ALLEN_CAHN, F_MMS_U2, F_EX51, F_CONST, F_AFFINE_T = range(6)
+LOAD_LUMPED, LOAD_NODAL = 0, 1
+
+_DTYPES = {"f32": (F32, torch.float32), "f64": (F64, torch.float64),
+           torch.float32: (F32, torch.float32), torch.float64: (F64, torch.float64)}
+
+
+class EIFEError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"eife error {code}: {msg}")
+        self.code = code
+
+
+def library_path():
+    return os.path.join(_PKG, "libeife.so")
+
+
+def load_library():
+    """Load libeife.so from the package directory; raise if it is not built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_2209_11922_amd.build")
+    lib = ctypes.CDLL(path)
+    c_int, c_double, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    lib.eife_create_grid.argtypes = [c_int, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(c_double), c_double,
+                                     c_int, c_int, ctypes.POINTER(c_void_p)]
+    lib.eife_destroy_grid.argtypes = [c_void_p]
+    lib.eife_set_phi.argtypes = [c_void_p, c_double, c_int]
+    lib.eife_set_c2.argtypes = [c_void_p, c_double]
+    lib.eife_set_origin.argtypes = [c_void_p, ctypes.POINTER(c_double)]
+    lib.eife_set_load.argtypes = [c_void_p, c_int]
+    lib.eife_set_forcing.argtypes = [c_void_p, c_double, c_double]
+    lib.eife_step.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_int, c_double, c_void_p]
+    lib.eife_norms.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]
+    lib.eife_grid_size.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_int64)]
+    lib.eife_last_error.restype = ctypes.c_char_p
+    lib.eife_last_error.argtypes = []
+    lib.eife_version.argtypes = []
+    for name in ("eife_create_grid", "eife_destroy_grid", "eife_set_phi", "eife_set_c2", "eife_set_origin",
+                 "eife_set_load", "eife_set_forcing", "eife_step", "eife_norms", "eife_grid_size",
+                 "eife_version"):
+        getattr(lib, name).restype = c_int
+    _LIB = lib
+    return lib
+
+
+def _check(lib, code):
+    if code != OK:
+        raise EIFEError(code, lib.eife_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Grid:
+    """A Q1 grid on prod_a [a_a, a_a + N_a h_a] with homogeneous Dirichlet data.
+
+    Mirrors eife_create_grid / eife_set_phi / eife_step / eife_norms; nodal
+    arrays are torch tensors on the GPU with shape (N_{d-1}-1, ..., N_0-1).
+    """
+
+    def __init__(self, N, h, D, dtype="f64", bc=BC_DIRICHLET):
+        self._lib = load_library()
+        self.d = len(N)
+        self.N = [int(n) for n in N]
+        self.h = [float(x) for x in h]
+        self.D = float(D)
+        self.dtype_code, self.torch_dtype = _DTYPES[dtype]
+        self.shape = tuple(n - 1 for n in reversed(self.N))
+        Na = (ctypes.c_int32 * self.d)(*self.N)
+        ha = (ctypes.c_double * self.d)(*self.h)
+        handle = ctypes.c_void_p()
+        _check(self._lib, self._lib.eife_create_grid(self.d, Na, ha, self.D, int(bc), self.dtype_code,
+                                                     ctypes.byref(handle)))
+        self._g = handle
+
+    def close(self):
+        if getattr(self, "_g", None):
+            self._lib.eife_destroy_grid(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def size(self):
+        n = ctypes.c_int64()
+        _check(self._lib, self._lib.eife_grid_size(self._g, ctypes.byref(n)))
+        return n.value
+
+    def set_phi(self, tau, stages):
+        _check(self._lib, self._lib.eife_set_phi(self._g, float(tau), int(stages)))
+
+    def set_c2(self, c2):
+        _check(self._lib, self._lib.eife_set_c2(self._g, float(c2)))
+
+    def set_origin(self, a):
+        arr = (ctypes.c_double * self.d)(*[float(x) for x in a])
+        _check(self._lib, self._lib.eife_set_origin(self._g, arr))
+
+    def set_load(self, kind):
+        _check(self._lib, self._lib.eife_set_load(self._g, int(kind)))
+
+    def set_forcing(self, c0, c1=0.0):
+        _check(self._lib, self._lib.eife_set_forcing(self._g, float(c0), float(c1)))
+
+    def _check_array(self, u, name):
+        if not isinstance(u, torch.Tensor) or not u.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+        if u.dtype != self.torch_dtype:
+            raise TypeError(f"{name} has dtype {u.dtype}, grid expects {self.torch_dtype}")
+        if not u.is_contiguous() or u.numel() != self.size():
+            raise ValueError(f"{name} must be contiguous with {self.size()} elements")
+
+    def step(self, u, n_steps, f_kind, t0=0.0, stream=None):
+        """Advance u in place by n_steps steps (asynchronous on `stream`)."""
+        self._check_array(u, "u")
+        _check(self._lib, self._lib.eife_step(self._g, ctypes.c_void_p(u.data_ptr()), int(n_steps), int(f_kind),
+                                              float(t0), _stream_ptr(stream)))
+        return u
+
+    def norms(self, u, uref=None, stream=None):
+        """(L2, H1, max, Allen-Cahn energy) in double; blocks until computed."""
+        self._check_array(u, "u")
+        ref = None
+        if uref is not None:
+            self._check_array(uref, "uref")
+            ref = ctypes.c_void_p(uref.data_ptr())
+        out = (ctypes.c_double * 4)()
+        code = self._lib.eife_norms(self._g, ctypes.c_void_p(u.data_ptr()), ref, out, _stream_ptr(stream))
+        _check(self._lib, code)
+        return tuple(out)

@@ -1,0 +1,574 @@
+// Device code of the EIFE library: sine-transform axis passes, the fused
+// reaction and diagonal phi stages, and the norm reductions (gfx950).
+//
+// A type-I sine transform of length n = N - 1 (Section 4: the matrices
+// P_ij = sin(ij pi / N) diagonalise the 1D mass and stiffness matrices) is
+// computed for two real lines at once: c = a + i b is extended oddly to
+// length L = 2N (z_m = c_m, z_{2N-m} = -c_m, z_0 = z_N = 0), a complex FFT of
+// length L gives Z_k = -2i (P a + i P b)_k, so the orthonormal transform
+// S = sqrt(2/N) P is (S a)_k = -Im Z_k / sqrt(2N), (S b)_k = Re Z_k / sqrt(2N).
+// The FFT is a mixed radix-4/2/3 Stockham autosort on lines held in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eife {
+
+template <typename T>
+struct Cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// multiply by -i
+template <typename T>
+__device__ __forceinline__ Cx<T> cmnegi(Cx<T> a) { return {a.im, -a.re}; }
+
+template <typename T, int R>
+struct Dft;
+
+template <typename T>
+struct Dft<T, 2> {
+  static __device__ __forceinline__ void run(Cx<T>* v) {
+    Cx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <typename T>
+struct Dft<T, 3> {
+  static __device__ __forceinline__ void run(Cx<T>* v) {
+    const T c = T(0.86602540378443864676);  // sqrt(3)/2
+    Cx<T> s = cadd(v[1], v[2]);
+    Cx<T> d = csub(v[1], v[2]);
+    Cx<T> m = {v[0].re - T(0.5) * s.re, v[0].im - T(0.5) * s.im};
+    Cx<T> r = {c * d.im, -c * d.re};  // -i * c * d
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+  }
+};
+
+template <typename T>
+struct Dft<T, 4> {
+  static __device__ __forceinline__ void run(Cx<T>* v) {
+    Cx<T> t0 = cadd(v[0], v[2]);
+    Cx<T> t1 = csub(v[0], v[2]);
+    Cx<T> t2 = cadd(v[1], v[3]);
+    Cx<T> t3 = cmnegi(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+// Per-thread element budget of one in-place Stockham stage: P * L <= kMaxElems * blockDim.
+constexpr int kMaxElems = 32;
+
+// One radix-R stage on P lines of length L stored at lds + p * ls.  Ns is the
+// product of the radices already applied; tw[j] = exp(-2 pi i j / L).
+template <typename T, int R>
+__device__ void stockham_stage(Cx<T>* lds, int ls, int L, int P, int Ns, const Cx<T>* __restrict__ tw) {
+  constexpr int MAXB = (kMaxElems + R - 1) / R;
+  const int nbf = L / R;
+  const int total = P * nbf;
+  const int tws = L / (Ns * R);
+  Cx<T> v[MAXB][R];
+#pragma unroll
+  for (int s = 0; s < MAXB; ++s) {
+    const int b = threadIdx.x + s * blockDim.x;
+    if (b < total) {
+      const int p = b / nbf;
+      const int j = b - p * nbf;
+      const Cx<T>* line = lds + p * ls;
+      const int k = j % Ns;
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[s][q] = line[j + q * nbf];
+#pragma unroll
+      for (int q = 1; q < R; ++q) v[s][q] = cmul(v[s][q], tw[q * k * tws]);
+      Dft<T, R>::run(v[s]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < MAXB; ++s) {
+    const int b = threadIdx.x + s * blockDim.x;
+    if (b < total) {
+      const int p = b / nbf;
+      const int j = b - p * nbf;
+      const int k = j % Ns;
+      Cx<T>* line = lds + p * ls;
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) line[base + q * Ns] = v[s][q];
+    }
+  }
+  __syncthreads();
+}
+
+struct FftPlan {
+  int L;      // FFT length (2N)
+  int n4, n2, n3;  // number of radix-4, radix-2, radix-3 stages
+};
+
+// Forward FFT of P lines in LDS (natural order in and out).  Callers must
+// __syncthreads() before (inputs written) -- stages synchronise internally.
+template <typename T>
+__device__ void fft_lines(Cx<T>* lds, int ls, int P, FftPlan pl, const Cx<T>* __restrict__ tw) {
+  int Ns = 1;
+  for (int i = 0; i < pl.n4; ++i) {
+    stockham_stage<T, 4>(lds, ls, pl.L, P, Ns, tw);
+    Ns *= 4;
+  }
+  for (int i = 0; i < pl.n2; ++i) {
+    stockham_stage<T, 2>(lds, ls, pl.L, P, Ns, tw);
+    Ns *= 2;
+  }
+  for (int i = 0; i < pl.n3; ++i) {
+    stockham_stage<T, 3>(lds, ls, pl.L, P, Ns, tw);
+    Ns *= 3;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// phi functions (Section 2.2) of z <= 0 in double: series sum_m z^m/(m+k)!
+// for |z| < 1/2, else phi_1 = (e^z - 1)/z and phi_2 = (phi_1 - 1)/z, which
+// cancel at most a factor of 4 there.  E = e^z is supplied by the caller.
+__device__ __forceinline__ void phi12(double z, double E, double& p1, double& p2) {
+  if (fabs(z) < 0.5) {
+    // Horner on 1/(m+1)! and 1/(m+2)!, m = 0..15 (truncation < 1e-19 at |z| = 1/2)
+    const double c1[16] = {1.0,
+                           0.5,
+                           1.6666666666666666667e-1,
+                           4.1666666666666666667e-2,
+                           8.3333333333333333333e-3,
+                           1.3888888888888888889e-3,
+                           1.9841269841269841270e-4,
+                           2.4801587301587301587e-5,
+                           2.7557319223985890653e-6,
+                           2.7557319223985890653e-7,
+                           2.5052108385441718775e-8,
+                           2.0876756987868098979e-9,
+                           1.6059043836821614599e-10,
+                           1.1470745597729724714e-11,
+                           7.6471637318198164759e-13,
+                           4.7794773323873852974e-14};
+    // phi1 = sum_m z^m / (m+1)!  (coefficients c1[m])
+    double a = c1[15];
+#pragma unroll
+    for (int m = 14; m >= 0; --m) a = a * z + c1[m];
+    // phi2 = sum_m z^m / (m+2)!  (coefficients c1[m+1], last one 1/17!)
+    double b = c1[15] / 17.0;
+#pragma unroll
+    for (int m = 14; m >= 0; --m) b = b * z + c1[m + 1];
+    p1 = a;
+    p2 = b;
+  } else {
+    p1 = (E - 1.0) / z;
+    p2 = (p1 - 1.0) / z;
+  }
+}
+
+__device__ __forceinline__ double phi1_only(double z, double E) {
+  double p1, p2;
+  phi12(z, E, p1, p2);
+  return p1;
+}
+
+// ---------------------------------------------------------------------------
+struct AxisTab {
+  const double* lam;  // D-free eigenvalue lambda_k = lamB/lamA of the 1D pair (B, A)
+  const double* w;    // load weight h/lamA (lumped) or 1 (nodal); 0 on padding
+  const double* E;    // exp(-tau D lambda_k)
+  const double* Ec;   // exp(-c2 tau D lambda_k)
+};
+
+struct Diag {
+  AxisTab ax[3];
+  double D, tau, c2;
+};
+
+// Reaction parameters
+struct Forcing {
+  int kind;
+  int d;
+  double t;
+  double c0, c1;
+  double D;
+  double a[3];
+  double h[3];
+};
+
+enum FKind { FK_ZERO = 0, FK_AC = 1, FK_MMS = 2, FK_EX51 = 3, FK_CONST = 4, FK_AFFINE = 5 };
+
+template <typename T>
+__device__ __forceinline__ T reaction(const Forcing& F, T u, int ix, int iy, int iz) {
+  switch (F.kind) {
+    case FK_AC:
+      return u - u * u * u;
+    case FK_ZERO:
+      return T(0);
+    case FK_CONST:
+      return T(F.c0);
+    case FK_AFFINE:
+      return T(F.c0 + F.c1 * F.t);
+    case FK_MMS: {
+      double s = sinpi(F.a[0] + (ix + 1) * F.h[0]);
+      if (F.d > 1) s *= sinpi(F.a[1] + (iy + 1) * F.h[1]);
+      if (F.d > 2) s *= sinpi(F.a[2] + (iz + 1) * F.h[2]);
+      const double e = exp(-F.t);
+      const double PI2 = 9.8696044010893586188;
+      const double g = (F.d * PI2 * F.D - 1.0) * e * s - e * e * s * s;
+      const double ud = double(u);
+      return T(ud * ud + g);
+    }
+    case FK_EX51: {
+      const double PI2 = 9.8696044010893586188;
+      const double s = sinpi(F.a[0] + (ix + 1) * F.h[0]) * sinpi(F.a[1] + (iy + 1) * F.h[1]);
+      return T(-0.5 * PI2 * double(u) + 0.5 * PI2 * exp(-PI2 * F.t) * s);
+    }
+    default:
+      return T(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row passes: lines along x (contiguous).  A block handles 2P rows, pair p =
+// rows (r0 + 2p, r0 + 2p + 1).
+enum RowMode { ROW_PHYS = 0, ROW_FWD_USER = 1, ROW_INV_USER = 2 };
+
+struct RowGeom {
+  int n;         // line length (interior nodes along x)
+  int nrows;     // number of rows (prod of the other axes)
+  int ny;        // rows per z-slab (interior nodes along y)
+  int64_t ld_src, ld_dst;  // row pitch of source / destination
+  FftPlan pl;
+  int P;         // pairs per block
+  int ls;        // LDS line stride (complex elements)
+};
+
+template <typename T>
+__device__ __forceinline__ void zero_lines(Cx<T>* lds, int ls, int P) {
+  for (int i = threadIdx.x; i < P * ls; i += blockDim.x) lds[i] = Cx<T>{T(0), T(0)};
+}
+
+// Scatter value pairs into the odd extension: position k (1..N-1) and L-k.
+template <typename T>
+__device__ __forceinline__ void put_odd(Cx<T>* line, int L, int k, T a, T b) {
+  line[k] = Cx<T>{a, b};
+  line[L - k] = Cx<T>{-a, -b};
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) row_pass(const T* src, T* dst, T* __restrict__ dst2, RowGeom g,
+                                                const Cx<T>* __restrict__ tw, Forcing F) {
+  extern __shared__ unsigned char smem_raw[];
+  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem_raw);
+  const int n = g.n;
+  const int L = g.pl.L;
+  const int N = L / 2;
+  const int P = g.P;
+  const int r0 = blockIdx.x * 2 * P;
+  const T scale = T(1.0 / sqrt(double(L)));
+
+  zero_lines(lds, g.ls, P);
+  __syncthreads();
+  // load: thread handles (p, m) for both rows of the pair
+  for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+    const int p = i / n;
+    const int m = i - p * n;
+    const int ra = r0 + 2 * p, rb = ra + 1;
+    T a = T(0), b = T(0);
+    if (ra < g.nrows) a = src[ra * g.ld_src + m];
+    if (rb < g.nrows) b = src[rb * g.ld_src + m];
+    put_odd(lds + p * g.ls, L, m + 1, a, b);
+  }
+  __syncthreads();
+  fft_lines(lds, g.ls, P, g.pl, tw);
+
+  if (MODE == ROW_INV_USER) {
+    for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+      const int p = i / n;
+      const int m = i - p * n;
+      const int ra = r0 + 2 * p, rb = ra + 1;
+      const Cx<T> Z = lds[p * g.ls + m + 1];
+      if (ra < g.nrows) dst[ra * g.ld_dst + m] = -Z.im * scale;
+      if (rb < g.nrows) dst[rb * g.ld_dst + m] = Z.re * scale;
+    }
+    return;
+  }
+  if (MODE == ROW_FWD_USER) {
+    for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+      const int p = i / n;
+      const int m = i - p * n;
+      const int ra = r0 + 2 * p, rb = ra + 1;
+      const Cx<T> Z = lds[p * g.ls + m + 1];
+      const T va = -Z.im * scale, vb = Z.re * scale;
+      if (ra < g.nrows) {
+        dst[ra * g.ld_dst + m] = va;
+        dst2[ra * g.ld_dst + m] = va;
+      }
+      if (rb < g.nrows) {
+        dst[rb * g.ld_dst + m] = vb;
+        dst2[rb * g.ld_dst + m] = vb;
+      }
+    }
+    return;
+  }
+  // ROW_PHYS: inverse transform -> reaction -> forward transform
+  for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+    const int p = i / n;
+    const int m = i - p * n;
+    const int ra = r0 + 2 * p, rb = ra + 1;
+    Cx<T>* line = lds + p * g.ls;
+    const Cx<T> Z = line[m + 1];
+    const T ua = -Z.im * scale, ub = Z.re * scale;
+    T fa = T(0), fb = T(0);
+    if (ra < g.nrows) fa = reaction<T>(F, ua, m, ra % g.ny, ra / g.ny);
+    if (rb < g.nrows) fb = reaction<T>(F, ub, m, rb % g.ny, rb / g.ny);
+    put_odd(line, L, m + 1, fa, fb);
+    if (m == 0) {
+      line[0] = Cx<T>{T(0), T(0)};
+      line[N] = Cx<T>{T(0), T(0)};
+    }
+  }
+  __syncthreads();
+  fft_lines(lds, g.ls, P, g.pl, tw);
+  for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+    const int p = i / n;
+    const int m = i - p * n;
+    const int ra = r0 + 2 * p, rb = ra + 1;
+    const Cx<T> Z = lds[p * g.ls + m + 1];
+    if (ra < g.nrows) dst[ra * g.ld_dst + m] = -Z.im * scale;
+    if (rb < g.nrows) dst[rb * g.ld_dst + m] = Z.re * scale;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column passes: lines along a strided axis.  A block handles C = 2P adjacent
+// x-columns c0 .. c0 + C - 1 (pair p = columns c0 + 2p, c0 + 2p + 1) of one
+// "outer" index; element m of column c sits at
+//   base + outer * ld_outer + m * ld_line + c.
+enum ColMode { COL_PLAIN = 0, COL_STAGE_A = 1, COL_STAGE_B = 2, COL_ETD1 = 3 };
+
+struct ColGeom {
+  int n;            // line length
+  int64_t ld_line;  // stride between consecutive elements of a line
+  int64_t ld_outer; // stride between outer indices
+  FftPlan pl;
+  int P;
+  int ls;
+  int last_is_z;    // 1: spectral index (kx, ky, kz) = (c, outer, m); 0: (c, m, 0)
+};
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) col_pass(T* __restrict__ W, T* __restrict__ H, ColGeom g,
+                                                const Cx<T>* __restrict__ tw, Diag dg) {
+  extern __shared__ unsigned char smem_raw[];
+  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem_raw);
+  const int n = g.n;
+  const int L = g.pl.L;
+  const int N = L / 2;
+  const int P = g.P;
+  const int c0 = blockIdx.x * 2 * P;
+  const int outer = blockIdx.y;
+  const int64_t base = int64_t(outer) * g.ld_outer + c0;
+  const T scale = T(1.0 / sqrt(double(L)));
+
+  zero_lines(lds, g.ls, P);
+  __syncthreads();
+  for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+    const int m = i / P;
+    const int p = i - m * P;
+    const Cx<T> v = *reinterpret_cast<const Cx<T>*>(W + base + m * g.ld_line + 2 * p);
+    put_odd(lds + p * g.ls, L, m + 1, v.re, v.im);
+  }
+  __syncthreads();
+  fft_lines(lds, g.ls, P, g.pl, tw);
+
+  if (MODE == COL_PLAIN) {
+    for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+      const int m = i / P;
+      const int p = i - m * P;
+      const Cx<T> Z = lds[p * g.ls + m + 1];
+      *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) = Cx<T>{-Z.im * scale, Z.re * scale};
+    }
+    return;
+  }
+
+  // diagonal stage in spectral space, then the inverse transform
+  const double tau = dg.tau, c2 = dg.c2, D = dg.D;
+  for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+    const int m = i / P;
+    const int p = i - m * P;
+    Cx<T>* line = lds + p * g.ls;
+    const Cx<T> Z = line[m + 1];
+    const T ga = -Z.im * scale, gb = Z.re * scale;
+    const int ky = g.last_is_z ? outer : m;
+    const int kz = g.last_is_z ? m : 0;
+    const double lyz = dg.ax[1].lam[ky] + dg.ax[2].lam[kz];
+    const double wyz = dg.ax[1].w[ky] * dg.ax[2].w[kz];
+    const double Eyz = dg.ax[1].E[ky] * dg.ax[2].E[kz];
+    const double Ecyz = dg.ax[1].Ec[ky] * dg.ax[2].Ec[kz];
+    T* hp = H + base + m * g.ld_line + 2 * p;
+    Cx<T> hv = *reinterpret_cast<Cx<T>*>(hp);
+    T outv[2];
+    T newh[2];
+    const T gin[2] = {ga, gb};
+    const T hin[2] = {hv.re, hv.im};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int kx = c0 + 2 * p + q;
+      const double lam = D * (dg.ax[0].lam[kx] + lyz);
+      const double z = -tau * lam;
+      const double E = dg.ax[0].E[kx] * Eyz;
+      const double G = double(gin[q]) * (dg.ax[0].w[kx] * wyz);
+      const double h = double(hin[q]);
+      if (MODE == COL_ETD1) {
+        const double p1 = phi1_only(z, E);
+        const double un = E * h + tau * p1 * G;
+        newh[q] = T(un);
+        outv[q] = T(un);
+      } else if (MODE == COL_STAGE_A) {
+        double p1, p2;
+        phi12(z, E, p1, p2);
+        const double Ec = dg.ax[0].Ec[kx] * Ecyz;
+        const double p1c = phi1_only(c2 * z, Ec);
+        outv[q] = T(Ec * h + c2 * tau * p1c * G);
+        newh[q] = T(E * h + tau * (p1 - p2 / c2) * G);
+      } else {  // COL_STAGE_B: h holds E u + tau (phi1 - phi2/c2) G1
+        double p1, p2;
+        phi12(z, E, p1, p2);
+        const double un = h + tau * (p2 / c2) * G;
+        newh[q] = T(un);
+        outv[q] = T(un);
+      }
+    }
+    *reinterpret_cast<Cx<T>*>(hp) = Cx<T>{newh[0], newh[1]};
+    put_odd(line, L, m + 1, outv[0], outv[1]);
+    if (m == 0) {
+      line[0] = Cx<T>{T(0), T(0)};
+      line[N] = Cx<T>{T(0), T(0)};
+    }
+  }
+  __syncthreads();
+  fft_lines(lds, g.ls, P, g.pl, tw);
+  for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+    const int m = i / P;
+    const int p = i - m * P;
+    const Cx<T> Z = lds[p * g.ls + m + 1];
+    *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) = Cx<T>{-Z.im * scale, Z.re * scale};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Norm reduction: per node, (M e)_i and (K_1 e)_i by the 3^d tensor stencil of
+// the 1D matrices A = (h/6) tridiag(1,4,1), B = (1/h) tridiag(-1,2,-1)
+// (Section 4, eq. (4.1)), accumulated in double.
+struct NormGeom {
+  int d;
+  int n[3];
+  double ad[3], ao[3];  // A diagonal / off-diagonal
+  double bd[3], bo[3];  // B diagonal / off-diagonal
+  double cellvol;
+};
+
+constexpr int kNormThreads = 256;
+constexpr int kNormAcc = 5;  // eMe, eK1e, max|e|, uK1u, sum (u^2-1)^2/4
+
+template <typename T>
+__device__ __forceinline__ double ld_err(const T* u, const T* ur, int64_t i) {
+  double v = double(u[i]);
+  if (ur) v -= double(ur[i]);
+  return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNormThreads) norm_partial(const T* __restrict__ u, const T* __restrict__ ur,
+                                                             NormGeom g, double* __restrict__ partials) {
+  __shared__ double red[kNormAcc][kNormThreads];
+  const int64_t total = int64_t(g.n[0]) * g.n[1] * g.n[2];
+  double acc[kNormAcc] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int64_t sx = 1, sy = g.n[0], sz = int64_t(g.n[0]) * g.n[1];
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int ix = int(i % g.n[0]);
+    const int iy = int((i / g.n[0]) % g.n[1]);
+    const int iz = int(i / sz);
+    double Me = 0.0, Ke = 0.0, Ku = 0.0;
+    for (int oz = -1; oz <= 1; ++oz) {
+      const int jz = iz + oz;
+      if (jz < 0 || jz >= g.n[2]) continue;
+      const double az = oz ? g.ao[2] : g.ad[2];
+      const double bz = oz ? g.bo[2] : g.bd[2];
+      for (int oy = -1; oy <= 1; ++oy) {
+        const int jy = iy + oy;
+        if (jy < 0 || jy >= g.n[1]) continue;
+        const double ay = oy ? g.ao[1] : g.ad[1];
+        const double by = oy ? g.bo[1] : g.bd[1];
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int jx = ix + ox;
+          if (jx < 0 || jx >= g.n[0]) continue;
+          const double axv = ox ? g.ao[0] : g.ad[0];
+          const double bxv = ox ? g.bo[0] : g.bd[0];
+          const int64_t j = jx * sx + jy * sy + jz * sz;
+          const double ej = ld_err(u, ur, j);
+          const double uj = double(u[j]);
+          const double mw = axv * ay * az;
+          const double kw = bxv * ay * az + axv * by * az + axv * ay * bz;
+          Me += mw * ej;
+          Ke += kw * ej;
+          Ku += kw * uj;
+        }
+      }
+    }
+    const double ei = ld_err(u, ur, i);
+    const double ui = double(u[i]);
+    acc[0] += ei * Me;
+    acc[1] += ei * Ke;
+    acc[2] = fmax(acc[2], fabs(ei));
+    acc[3] += ui * Ku;
+    const double q = ui * ui - 1.0;
+    acc[4] += 0.25 * q * q;
+  }
+#pragma unroll
+  for (int k = 0; k < kNormAcc; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < kNormAcc; ++k) {
+        if (k == 2)
+          red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+        else
+          red[k][threadIdx.x] += red[k][threadIdx.x + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kNormAcc) partials[blockIdx.x * kNormAcc + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(kNormAcc) norm_final(const double* __restrict__ partials, int nblocks,
+                                                       double* __restrict__ out5) {
+  const int k = threadIdx.x;
+  if (k >= kNormAcc) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    const double v = partials[b * kNormAcc + k];
+    s = (k == 2) ? fmax(s, v) : s + v;
+  }
+  out5[k] = s;
+}
+
+}  // namespace eife
