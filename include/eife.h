@@ -132,6 +132,29 @@ int eife_step(eife_grid g, void* u, int64_t n_steps, int f_kind, double t0, void
  * finite. */
 int eife_norms(eife_grid g, const void* u, const void* uref, double* out, void* stream);
 
+/* Pass kinds of eife_step, for per-pass timing. */
+enum eife_pass {
+  EIFE_PASS_ROW_PHYS = 0,   /* inverse x-transform -> f -> forward x-transform */
+  EIFE_PASS_ROW_FWD = 1,    /* prologue: forward x-transform of the caller's u */
+  EIFE_PASS_ROW_INV = 2,    /* epilogue: inverse x-transform into the caller's u */
+  EIFE_PASS_MID = 3,        /* y-transform of a 3D grid */
+  EIFE_PASS_LAST_PLAIN = 4, /* prologue: transform along the last axis */
+  EIFE_PASS_LAST_A = 5,     /* last-axis transform with the first EIFE2 stage (eq. (2.14)) */
+  EIFE_PASS_LAST_B = 6,     /* last-axis transform with the EIFE2 update */
+  EIFE_PASS_LAST_ETD1 = 7,  /* last-axis transform with the EIFE1 update (eq. (2.13)) */
+  EIFE_PASS_COUNT = 8
+};
+
+/* Measurement aid: on != 0 makes later eife_step calls record a pair of HIP
+ * events around every pass on the step's stream (accumulated per pass kind);
+ * on == 0 stops recording.  Either call clears the accumulated totals. */
+int eife_profile(eife_grid g, int on);
+
+/* Wait for the recorded events and return, per pass kind, the summed GPU
+ * time in milliseconds (ms[EIFE_PASS_COUNT]) and the number of launches
+ * (launches[EIFE_PASS_COUNT]) since eife_profile.  Blocks the host. */
+int eife_profile_read(eife_grid g, double* ms, int64_t* launches);
+
 /* Number of interior nodes of the grid (elements of a nodal array). */
 int eife_grid_size(eife_grid g, int64_t* count);
 

@@ -14,6 +14,7 @@ BC_DIRICHLET, BC_PERIODIC = 0, 1
 F32, F64 = 0, 1
 F_ZERO, F_ALLEN_CAHN, F_MMS_U2, F_EX51, F_CONST, F_AFFINE_T = range(6)
 LOAD_LUMPED, LOAD_NODAL = 0, 1
+PASS_NAMES = ["row_phys", "row_fwd", "row_inv", "mid", "last_plain", "last_a", "last_b", "last_etd1"]
 
 _DTYPES = {"f32": (F32, torch.float32), "f64": (F64, torch.float64),
            torch.float32: (F32, torch.float32), torch.float64: (F64, torch.float64)}
@@ -50,12 +51,14 @@ def load_library():
     lib.eife_step.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_int, c_double, c_void_p]
     lib.eife_norms.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]
     lib.eife_grid_size.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_int64)]
+    lib.eife_profile.argtypes = [c_void_p, c_int]
+    lib.eife_profile_read.argtypes = [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.eife_last_error.restype = ctypes.c_char_p
     lib.eife_last_error.argtypes = []
     lib.eife_version.argtypes = []
     for name in ("eife_create_grid", "eife_destroy_grid", "eife_set_phi", "eife_set_c2", "eife_set_origin",
                  "eife_set_load", "eife_set_forcing", "eife_step", "eife_norms", "eife_grid_size",
-                 "eife_version"):
+                 "eife_version", "eife_profile", "eife_profile_read"):
         getattr(lib, name).restype = c_int
     _LIB = lib
     return lib
@@ -140,6 +143,17 @@ class Grid:
         _check(self._lib, self._lib.eife_step(self._g, ctypes.c_void_p(u.data_ptr()), int(n_steps), int(f_kind),
                                               float(t0), _stream_ptr(stream)))
         return u
+
+    def profile(self, on):
+        """Start (on=True) or stop per-pass event timing; clears the totals."""
+        _check(self._lib, self._lib.eife_profile(self._g, 1 if on else 0))
+
+    def profile_read(self):
+        """{pass name: (total ms, launches)} since profile(); blocks."""
+        ms = (ctypes.c_double * len(PASS_NAMES))()
+        cnt = (ctypes.c_int64 * len(PASS_NAMES))()
+        _check(self._lib, self._lib.eife_profile_read(self._g, ms, cnt))
+        return {PASS_NAMES[k]: (ms[k], cnt[k]) for k in range(len(PASS_NAMES))}
 
     def norms(self, u, uref=None, stream=None):
         """(L2, H1, max, Allen-Cahn energy) in double; blocks until computed."""

@@ -106,6 +106,16 @@ struct eife_grid_s {
   int prow = 1;     // pairs per block, row pass
   int pcol[3] = {1, 1, 1};  // pairs per block, column pass along axis 1, 2
   int nlines_total() const { return n[1] * n[2]; }
+  // per-pass timing (eife_profile)
+  bool prof_on = false;
+  struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[EIFE_PASS_COUNT] = {0};
+  int64_t prof_n[EIFE_PASS_COUNT] = {0};
 };
 
 namespace {
@@ -222,8 +232,48 @@ int set_lds_attrs(size_t bytes) {
   return EIFE_OK;
 }
 
+hipEvent_t take_event(eife_grid_s* g) {
+  if (!g->ev_pool.empty()) {
+    hipEvent_t e = g->ev_pool.back();
+    g->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records the start event of a pass when profiling; returns the pending index or -1.
+int prof_begin(eife_grid_s* g, int kind, hipStream_t s) {
+  if (!g->prof_on) return -1;
+  hipEvent_t a = take_event(g), b = take_event(g);
+  if (!a || !b) return -1;
+  if (hipEventRecord(a, s) != hipSuccess) return -1;
+  g->prof_pending.push_back({kind, a, b});
+  return int(g->prof_pending.size()) - 1;
+}
+
+void prof_end(eife_grid_s* g, int idx, hipStream_t s) {
+  if (idx < 0) return;
+  (void)hipEventRecord(g->prof_pending[idx].b, s);
+}
+
+int prof_collect(eife_grid_s* g) {
+  for (auto& r : g->prof_pending) {
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    g->prof_ms[r.kind] += ms;
+    g->prof_n[r.kind] += 1;
+    g->ev_pool.push_back(r.a);
+    g->ev_pool.push_back(r.b);
+  }
+  g->prof_pending.clear();
+  return EIFE_OK;
+}
+
 template <typename T>
-int launch_row(const eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, int64_t ld_dst, T* dst2,
+int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, int64_t ld_dst, T* dst2,
                const Forcing& F, hipStream_t s) {
   RowGeom rg;
   rg.n = g->n[0];
@@ -237,6 +287,8 @@ int launch_row(const eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* 
   const size_t shm = lds_bytes(g, rg.P, rg.pl.L);
   dim3 grid((rg.nrows + 2 * rg.P - 1) / (2 * rg.P));
   const Cx<T>* tw = reinterpret_cast<const Cx<T>*>(g->tw[0]);
+  const int pidx = prof_begin(g, mode == ROW_PHYS ? EIFE_PASS_ROW_PHYS
+                                 : mode == ROW_FWD_USER ? EIFE_PASS_ROW_FWD : EIFE_PASS_ROW_INV, s);
   switch (mode) {
     case ROW_PHYS:
       hipLaunchKernelGGL((row_pass<T, ROW_PHYS>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F);
@@ -249,12 +301,13 @@ int launch_row(const eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* 
       break;
   }
   HIP_TRY(hipGetLastError());
+  prof_end(g, pidx, s);
   return EIFE_OK;
 }
 
 // axis = 1 (y) or 2 (z); `last` selects the diagonal mode
 template <typename T>
-int launch_col(const eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, hipStream_t s) {
+int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, hipStream_t s) {
   ColGeom cg;
   const int64_t pitch = g->pitch;
   int outer;
@@ -277,6 +330,13 @@ int launch_col(const eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag&
   const size_t shm = lds_bytes(g, cg.P, cg.pl.L);
   dim3 grid(g->pitch / (2 * cg.P), outer);
   const Cx<T>* tw = reinterpret_cast<const Cx<T>*>(g->tw[axis]);
+  int kind = EIFE_PASS_MID;
+  if (!(axis == 1 && g->d == 3)) {
+    kind = mode == COL_PLAIN ? EIFE_PASS_LAST_PLAIN
+           : mode == COL_STAGE_A ? EIFE_PASS_LAST_A
+           : mode == COL_STAGE_B ? EIFE_PASS_LAST_B : EIFE_PASS_LAST_ETD1;
+  }
+  const int pidx = prof_begin(g, kind, s);
   switch (mode) {
     case COL_PLAIN:
       hipLaunchKernelGGL((col_pass<T, COL_PLAIN>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
@@ -292,6 +352,7 @@ int launch_col(const eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag&
       break;
   }
   HIP_TRY(hipGetLastError());
+  prof_end(g, pidx, s);
   return EIFE_OK;
 }
 
@@ -382,6 +443,11 @@ void free_grid(eife_grid_s* g) {
     hipFree(g->tw[a]);
     hipFree(g->tab[a]);
   }
+  for (auto& r : g->prof_pending) {
+    g->ev_pool.push_back(r.a);
+    g->ev_pool.push_back(r.b);
+  }
+  for (hipEvent_t e : g->ev_pool) hipEventDestroy(e);
   hipFree(g->partials);
   hipFree(g->out5);
   if (g->host5) hipHostFree(g->host5);
@@ -563,6 +629,28 @@ int eife_set_phi(eife_grid g, double tau, int stages) {
   const int r = upload_tables(g);
   if (r != EIFE_OK) g->phi_ready = false;
   return r;
+}
+
+int eife_profile(eife_grid g, int on) {
+  RET_IF(check_grid(g));
+  RET_IF(prof_collect(g));
+  for (int k = 0; k < EIFE_PASS_COUNT; ++k) {
+    g->prof_ms[k] = 0.0;
+    g->prof_n[k] = 0;
+  }
+  g->prof_on = on != 0;
+  return EIFE_OK;
+}
+
+int eife_profile_read(eife_grid g, double* ms, int64_t* launches) {
+  RET_IF(check_grid(g));
+  if (!ms || !launches) return fail(EIFE_EINVAL, "ms and launches must not be null");
+  RET_IF(prof_collect(g));
+  for (int k = 0; k < EIFE_PASS_COUNT; ++k) {
+    ms[k] = g->prof_ms[k];
+    launches[k] = g->prof_n[k];
+  }
+  return EIFE_OK;
 }
 
 int eife_grid_size(eife_grid g, int64_t* count) {

@@ -1,0 +1,77 @@
+"""GPU parity at the full sizes of the workloads (few steps), against the FP64 oracle.
+
+The oracle here is tier C (library type-I sine transform with closed-form
+eigenvalues), itself pinned to the dense and Kronecker tiers on small grids.
+"""
+import numpy as np
+import pytest
+
+import seeded_inputs
+from oracle import fem, problems, spectral, stepper
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(got, ref):
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def _run_both(N, D, u0, tau, steps, stages, fkind, f, dtype, t0=0.0):
+    import paper_2209_11922_amd as eife
+    h = [1.0 / n for n in N]
+    g = eife.Grid(N, h, D, dtype)
+    g.set_phi(tau, stages)
+    u = torch.tensor(u0, dtype=g.torch_dtype, device="cuda")
+    g.step(u, steps, fkind, t0)
+    torch.cuda.synchronize()
+    got = u.double().cpu().numpy()
+    g.close()
+    del u
+    ref = stepper.run(spectral.SineBasis(N, h, D), u0, f, tau, steps, stages, t0=t0)
+    return got, ref
+
+
+def test_bench_workload_3d_255cubed_f32():
+    """The benchmark's grid and launch shapes: 3D Allen-Cahn 255^3, FP32, EIFE2, tau = 0.005."""
+    N = [256, 256, 256]
+    u0 = seeded_inputs.uniform_field(0, N)
+    got, ref = _run_both(N, 0.02 ** 2, u0, 0.005, 4, 2, 1, problems.allen_cahn(), "f32")
+    err = _rel(got, ref)
+    print(f"255^3 f32 rel err {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_manufactured_4095sq_f64():
+    N = [4096, 4096]
+    h = [1 / 4096] * 2
+    u0 = problems.mms_u2_exact(0.0, fem.mesh(N, h))
+    got, ref = _run_both(N, 1.0, u0, 2.0 ** -6, 3, 2, 2, problems.mms_u2(1.0), "f64")
+    err = _rel(got, ref)
+    print(f"4095^2 f64 rel err {err:.3e}")
+    assert err <= 1e-12
+
+
+def test_manufactured_4095sq_f32_eife1():
+    N = [4096, 4096]
+    h = [1 / 4096] * 2
+    u0 = problems.mms_u2_exact(0.0, fem.mesh(N, h))
+    got, ref = _run_both(N, 1.0, u0, 2.0 ** -6, 3, 1, 2, problems.mms_u2(1.0), "f32")
+    err = _rel(got, ref)
+    print(f"4095^2 f32 rel err {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_mixed_radix_1536x768_f64():
+    N = [1536, 768]
+    u0 = seeded_inputs.uniform_field(4, N)
+    got, ref = _run_both(N, 1e-4, u0, 0.01, 5, 2, 1, problems.allen_cahn(), "f64")
+    assert _rel(got, ref) <= 1e-12
+
+
+def test_3d_384x192x96_f64_eife1():
+    N = [384, 192, 96]
+    u0 = seeded_inputs.uniform_field(6, N)
+    got, ref = _run_both(N, 4e-4, u0, 0.005, 3, 1, 1, problems.allen_cahn(), "f64")
+    assert _rel(got, ref) <= 1e-12
