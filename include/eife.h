@@ -106,6 +106,16 @@ int eife_set_origin(eife_grid g, const double* a);
 /* Load reading, EIFE_LOAD_LUMPED or EIFE_LOAD_NODAL. */
 int eife_set_load(eife_grid g, int kind);
 
+/* How the sine transforms are computed (Section 4 uses the FFT). */
+enum eife_transform {
+  EIFE_TX_FFT = 0,            /* default: FFT passes, the specialised kernels where N allows */
+  EIFE_TX_FFT_GENERIC = 1,    /* FFT passes, always the generic mixed-radix kernels */
+  EIFE_TX_GEMM_SPLITBF16 = 2  /* dense sine-matrix products on the matrix cores */
+};
+
+/* Select the transform implementation of later eife_step calls. */
+int eife_set_transform(eife_grid g, int kind);
+
 /* Parameters c0, c1 of EIFE_F_CONST / EIFE_F_AFFINE_T. */
 int eife_set_forcing(eife_grid g, double c0, double c1);
 

@@ -14,6 +14,7 @@ BC_DIRICHLET, BC_PERIODIC = 0, 1
 F32, F64 = 0, 1
 F_ZERO, F_ALLEN_CAHN, F_MMS_U2, F_EX51, F_CONST, F_AFFINE_T = range(6)
 LOAD_LUMPED, LOAD_NODAL = 0, 1
+TX_FFT, TX_FFT_GENERIC, TX_GEMM_SPLITBF16 = 0, 1, 2
 PASS_NAMES = ["row_phys", "row_fwd", "row_inv", "mid", "last_plain", "last_a", "last_b", "last_etd1"]
 
 _DTYPES = {"f32": (F32, torch.float32), "f64": (F64, torch.float64),
@@ -48,6 +49,7 @@ def load_library():
     lib.eife_set_origin.argtypes = [c_void_p, ctypes.POINTER(c_double)]
     lib.eife_set_load.argtypes = [c_void_p, c_int]
     lib.eife_set_forcing.argtypes = [c_void_p, c_double, c_double]
+    lib.eife_set_transform.argtypes = [c_void_p, c_int]
     lib.eife_step.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_int, c_double, c_void_p]
     lib.eife_norms.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]
     lib.eife_grid_size.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_int64)]
@@ -58,7 +60,7 @@ def load_library():
     lib.eife_version.argtypes = []
     for name in ("eife_create_grid", "eife_destroy_grid", "eife_set_phi", "eife_set_c2", "eife_set_origin",
                  "eife_set_load", "eife_set_forcing", "eife_step", "eife_norms", "eife_grid_size",
-                 "eife_version", "eife_profile", "eife_profile_read"):
+                 "eife_version", "eife_profile", "eife_profile_read", "eife_set_transform"):
         getattr(lib, name).restype = c_int
     _LIB = lib
     return lib
@@ -125,6 +127,9 @@ class Grid:
 
     def set_load(self, kind):
         _check(self._lib, self._lib.eife_set_load(self._g, int(kind)))
+
+    def set_transform(self, kind):
+        _check(self._lib, self._lib.eife_set_transform(self._g, int(kind)))
 
     def set_forcing(self, c0, c1=0.0):
         _check(self._lib, self._lib.eife_set_forcing(self._g, float(c0), float(c1)))

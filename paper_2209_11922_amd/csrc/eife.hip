@@ -25,6 +25,7 @@
 
 #include "../../include/eife.h"
 #include "eife_kernels.hpp"
+#include "eife_fast.hpp"
 
 using namespace eife;
 
@@ -51,6 +52,7 @@ int fail(int code, const char* fmt, ...) {
 constexpr int kThreads = 256;
 constexpr size_t kLdsBudget = 80 * 1024;  // per block, two blocks per CU fit in 160 KB
 constexpr int kNormBlocksMax = 1024;
+constexpr int kTabArrays = 5;  // lam, w, M, Q, Mc per axis
 
 bool factor_plan(int L, FftPlan* pl) {
   pl->L = L;
@@ -96,13 +98,14 @@ struct eife_grid_s {
   void* W = nullptr;
   void* H = nullptr;
   void* tw[3] = {nullptr, nullptr, nullptr};
-  double* tab[3] = {nullptr, nullptr, nullptr};  // 4 arrays per axis: lam, w, E, Ec
+  double* tab[3] = {nullptr, nullptr, nullptr};  // kTabArrays arrays per axis
   int tablen[3] = {0, 0, 0};
   double* partials = nullptr;
   double* out5 = nullptr;
   double* host5 = nullptr;  // pinned
   // launch shapes
   FftPlan plan[3];
+  int transform = EIFE_TX_FFT;
   int prow = 1;     // pairs per block, row pass
   int pcol[3] = {1, 1, 1};  // pairs per block, column pass along axis 1, 2
   int nlines_total() const { return n[1] * n[2]; }
@@ -151,29 +154,47 @@ double lamA1d(int N, double h, int k) {
   return (h / 6.0) * (4.0 + 2.0 * std::cos(t));
 }
 
+// expm1(z) and expm1(z) - z for z <= 0 without cancellation: power series
+// below |z| = 1/2, library expm1 above.
+double expm1_minus_z(double z) {
+  if (std::fabs(z) < 0.5) {
+    double term = z * z / 2.0, sum = 0.0;
+    for (int m = 2; m < 40 && term != 0.0; ++m) {
+      sum += term;
+      term *= z / double(m + 1);
+    }
+    return sum;
+  }
+  return std::expm1(z) - z;
+}
+
 int upload_tables(eife_grid_s* g) {
   for (int ax = 0; ax < 3; ++ax) {
     const int len = g->tablen[ax];
-    std::vector<double> buf(4 * size_t(len), 0.0);
+    std::vector<double> buf(kTabArrays * size_t(len), 0.0);
     double* lam = buf.data();
     double* w = lam + len;
-    double* E = w + len;
-    double* Ec = E + len;
+    double* M = w + len;
+    double* Q = M + len;
+    double* Mc = Q + len;
     const bool real_axis = ax < g->d;
     for (int k = 0; k < len; ++k) {
-      if (!real_axis) {
+      if (!real_axis) {  // virtual axis of a 1D/2D grid: the identity
         lam[k] = 0.0;
         w[k] = 1.0;
-        E[k] = 1.0;
-        Ec[k] = 1.0;
         continue;
       }
-      if (k >= g->n[ax]) continue;  // padding columns stay zero
+      if (k >= g->n[ax]) {  // padding column: stays exactly zero
+        lam[k] = 1.0;
+        continue;
+      }
       lam[k] = lam1d(g->N[ax], g->h[ax], k + 1);
       w[k] = (g->load == EIFE_LOAD_LUMPED) ? g->h[ax] / lamA1d(g->N[ax], g->h[ax], k + 1) : 1.0;
       if (g->phi_ready) {
-        E[k] = std::exp(-g->tau * g->D * lam[k]);
-        Ec[k] = std::exp(-g->c2 * g->tau * g->D * lam[k]);
+        const double z = -g->tau * g->D * lam[k];
+        M[k] = std::expm1(z);
+        Q[k] = expm1_minus_z(z);
+        Mc[k] = std::expm1(g->c2 * z);
       }
     }
     HIP_TRY(hipMemcpy(g->tab[ax], buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -187,8 +208,9 @@ Diag make_diag(const eife_grid_s* g) {
     const int len = g->tablen[ax];
     dg.ax[ax].lam = g->tab[ax];
     dg.ax[ax].w = g->tab[ax] + len;
-    dg.ax[ax].E = g->tab[ax] + 2 * len;
-    dg.ax[ax].Ec = g->tab[ax] + 3 * len;
+    dg.ax[ax].M = g->tab[ax] + 2 * len;
+    dg.ax[ax].Q = g->tab[ax] + 3 * len;
+    dg.ax[ax].Mc = g->tab[ax] + 4 * len;
   }
   dg.D = g->D;
   dg.tau = g->tau;
@@ -272,6 +294,70 @@ int prof_collect(eife_grid_s* g) {
   return EIFE_OK;
 }
 
+// Line pairs per block of the fast passes (LDS <= 64 KB, 64-byte column segments).
+template <typename T, int L>
+constexpr int fast_pb() {
+  return sizeof(T) == 4 ? (L == 128 ? 16 : (L == 1024 ? 4 : 8)) : (L == 128 ? 8 : (L == 1024 ? 2 : 4));
+}
+
+bool fast_len(int N) { return N == 64 || N == 128 || N == 256 || N == 512; }
+
+template <typename T, int L>
+void row_fast_launch(int mode, int nrows, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
+                     const Cx<T>* tw, const Forcing& F) {
+  constexpr int PB = fast_pb<T, L>();
+  constexpr int NT = PB * fast::FftShape<L>::LP;
+  dim3 grid((nrows + 2 * PB - 1) / (2 * PB));
+  if (mode == ROW_PHYS)
+    hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_PHYS>), grid, dim3(NT), 0, s, src, dst, dst2, rg, tw, F);
+  else if (mode == ROW_FWD_USER)
+    hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_FWD_USER>), grid, dim3(NT), 0, s, src, dst, dst2, rg, tw, F);
+  else
+    hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_INV_USER>), grid, dim3(NT), 0, s, src, dst, dst2, rg, tw, F);
+}
+
+template <typename T, int L>
+void col_fast_launch(int mode, int pitch, int outer, hipStream_t s, T* W, T* H, const ColGeom& cg,
+                     const Cx<T>* tw, const Diag& dg) {
+  constexpr int PB = fast_pb<T, L>();
+  constexpr int NT = PB * fast::FftShape<L>::LP;
+  dim3 grid(pitch / (2 * PB), outer);
+  if (mode == COL_PLAIN)
+    hipLaunchKernelGGL((fast::col_fast<T, L, PB, COL_PLAIN>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+  else if (mode == COL_STAGE_A)
+    hipLaunchKernelGGL((fast::col_fast<T, L, PB, COL_STAGE_A>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+  else if (mode == COL_STAGE_B)
+    hipLaunchKernelGGL((fast::col_fast<T, L, PB, COL_STAGE_B>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+  else
+    hipLaunchKernelGGL((fast::col_fast<T, L, PB, COL_ETD1>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+}
+
+template <typename T>
+bool try_row_fast(const eife_grid_s* g, int mode, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
+                  const Cx<T>* tw, const Forcing& F) {
+  if (g->transform != EIFE_TX_FFT || !fast_len(g->N[0])) return false;
+  switch (g->N[0]) {
+    case 64: row_fast_launch<T, 128>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F); return true;
+    case 128: row_fast_launch<T, 256>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F); return true;
+    case 256: row_fast_launch<T, 512>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F); return true;
+    case 512: row_fast_launch<T, 1024>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F); return true;
+  }
+  return false;
+}
+
+template <typename T>
+bool try_col_fast(const eife_grid_s* g, int axis, int mode, int outer, hipStream_t s, T* W, T* H,
+                  const ColGeom& cg, const Cx<T>* tw, const Diag& dg) {
+  if (g->transform != EIFE_TX_FFT || !fast_len(g->N[axis])) return false;
+  switch (g->N[axis]) {
+    case 64: col_fast_launch<T, 128>(mode, g->pitch, outer, s, W, H, cg, tw, dg); return true;
+    case 128: col_fast_launch<T, 256>(mode, g->pitch, outer, s, W, H, cg, tw, dg); return true;
+    case 256: col_fast_launch<T, 512>(mode, g->pitch, outer, s, W, H, cg, tw, dg); return true;
+    case 512: col_fast_launch<T, 1024>(mode, g->pitch, outer, s, W, H, cg, tw, dg); return true;
+  }
+  return false;
+}
+
 template <typename T>
 int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, int64_t ld_dst, T* dst2,
                const Forcing& F, hipStream_t s) {
@@ -289,6 +375,11 @@ int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, i
   const Cx<T>* tw = reinterpret_cast<const Cx<T>*>(g->tw[0]);
   const int pidx = prof_begin(g, mode == ROW_PHYS ? EIFE_PASS_ROW_PHYS
                                  : mode == ROW_FWD_USER ? EIFE_PASS_ROW_FWD : EIFE_PASS_ROW_INV, s);
+  if (try_row_fast<T>(g, mode, s, src, dst, dst2, rg, tw, F)) {
+    HIP_TRY(hipGetLastError());
+    prof_end(g, pidx, s);
+    return EIFE_OK;
+  }
   switch (mode) {
     case ROW_PHYS:
       hipLaunchKernelGGL((row_pass<T, ROW_PHYS>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F);
@@ -337,6 +428,11 @@ int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, h
            : mode == COL_STAGE_B ? EIFE_PASS_LAST_B : EIFE_PASS_LAST_ETD1;
   }
   const int pidx = prof_begin(g, kind, s);
+  if (try_col_fast<T>(g, axis, mode, outer, s, W, H, cg, tw, dg)) {
+    HIP_TRY(hipGetLastError());
+    prof_end(g, pidx, s);
+    return EIFE_OK;
+  }
   switch (mode) {
     case COL_PLAIN:
       hipLaunchKernelGGL((col_pass<T, COL_PLAIN>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
@@ -561,7 +657,7 @@ int eife_create_grid(int d, const int32_t* N, const double* h, double D, int bc,
       }
     }
     g->tablen[a] = (a == 0) ? g->pitch : g->n[a];
-    if (hipMalloc(reinterpret_cast<void**>(&g->tab[a]), 4 * size_t(g->tablen[a]) * sizeof(double)) != hipSuccess) {
+    if (hipMalloc(reinterpret_cast<void**>(&g->tab[a]), kTabArrays * size_t(g->tablen[a]) * sizeof(double)) != hipSuccess) {
       free_grid(g);
       return fail(EIFE_ENOMEM, "table allocation failed");
     }
@@ -609,6 +705,14 @@ int eife_set_load(eife_grid g, int kind) {
   if (kind != EIFE_LOAD_LUMPED && kind != EIFE_LOAD_NODAL) return fail(EIFE_EINVAL, "unknown load kind %d", kind);
   g->load = kind;
   return upload_tables(g);
+}
+
+int eife_set_transform(eife_grid g, int kind) {
+  RET_IF(check_grid(g));
+  if (kind == EIFE_TX_GEMM_SPLITBF16) return fail(EIFE_EUNSUPPORTED, "the split-BF16 GEMM transform is not built");
+  if (kind != EIFE_TX_FFT && kind != EIFE_TX_FFT_GENERIC) return fail(EIFE_EINVAL, "unknown transform kind %d", kind);
+  g->transform = kind;
+  return EIFE_OK;
 }
 
 int eife_set_forcing(eife_grid g, double c0, double c1) {

@@ -141,57 +141,63 @@ __device__ void fft_lines(Cx<T>* lds, int ls, int P, FftPlan pl, const Cx<T>* __
 }
 
 // ---------------------------------------------------------------------------
-// phi functions (Section 2.2) of z <= 0 in double: series sum_m z^m/(m+k)!
-// for |z| < 1/2, else phi_1 = (e^z - 1)/z and phi_2 = (phi_1 - 1)/z, which
-// cancel at most a factor of 4 there.  E = e^z is supplied by the caller.
-__device__ __forceinline__ void phi12(double z, double E, double& p1, double& p2) {
-  if (fabs(z) < 0.5) {
-    // Horner on 1/(m+1)! and 1/(m+2)!, m = 0..15 (truncation < 1e-19 at |z| = 1/2)
-    const double c1[16] = {1.0,
-                           0.5,
-                           1.6666666666666666667e-1,
-                           4.1666666666666666667e-2,
-                           8.3333333333333333333e-3,
-                           1.3888888888888888889e-3,
-                           1.9841269841269841270e-4,
-                           2.4801587301587301587e-5,
-                           2.7557319223985890653e-6,
-                           2.7557319223985890653e-7,
-                           2.5052108385441718775e-8,
-                           2.0876756987868098979e-9,
-                           1.6059043836821614599e-10,
-                           1.1470745597729724714e-11,
-                           7.6471637318198164759e-13,
-                           4.7794773323873852974e-14};
-    // phi1 = sum_m z^m / (m+1)!  (coefficients c1[m])
-    double a = c1[15];
-#pragma unroll
-    for (int m = 14; m >= 0; --m) a = a * z + c1[m];
-    // phi2 = sum_m z^m / (m+2)!  (coefficients c1[m+1], last one 1/17!)
-    double b = c1[15] / 17.0;
-#pragma unroll
-    for (int m = 14; m >= 0; --m) b = b * z + c1[m + 1];
-    p1 = a;
-    p2 = b;
+// Diagonal phi stage (Section 2.2, eqs. (2.13)-(2.14); Section 4, eq. (4.4)).
+// For a spectral index with eigenvalue Lam = D (lam_x + lam_y + lam_z) and
+// z = -tau Lam, the stage needs e^z, tau phi_1(z), tau phi_2(z) and
+// c2 tau phi_1(c2 z).  They are built from per-axis double tables
+//   M_a = e^{z_a} - 1,  Q_a = e^{z_a} - 1 - z_a,  Mc_a = e^{c2 z_a} - 1
+// (z_a = -tau D lam_a) with the exact identities
+//   e^{a+b} - 1       = M_a + M_b + M_a M_b
+//   e^{a+b} - 1 - a - b = Q_a + Q_b + M_a M_b,
+// in which, for z <= 0, every Q term and every product M_a M_b is >= 0, so
+// no cancellation occurs anywhere in the spectrum.  Then
+//   tau phi_1 = -M / Lam,  tau phi_2 = Q / (tau Lam^2),  c2 tau phi_1(c2 z) = -Mc / Lam.
+struct AxisTab {
+  const double* lam;  // lambda_k = lamB_k / lamA_k of the 1D pair (B, A) (padding: 1)
+  const double* w;    // load weight h / lamA_k (lumped) or 1 (nodal); 0 on padding
+  const double* M;    // expm1(-tau D lambda_k)
+  const double* Q;    // expm1(-tau D lambda_k) + tau D lambda_k
+  const double* Mc;   // expm1(-c2 tau D lambda_k)
+};
+
+struct Sep {
+  double lam, w, M, Q, Mc;
+};
+
+__device__ __forceinline__ Sep sep_load(const AxisTab& t, int k) {
+  return Sep{t.lam[k], t.w[k], t.M[k], t.Q[k], t.Mc[k]};
+}
+
+__device__ __forceinline__ Sep sep_combine(const Sep& a, const Sep& b) {
+  const double mm = a.M * b.M;
+  return Sep{a.lam + b.lam, a.w * b.w, a.M + b.M + mm, a.Q + b.Q + mm, a.Mc + b.Mc + a.Mc * b.Mc};
+}
+
+enum DiagMode { DIAG_A = 1, DIAG_B = 2, DIAG_ETD1 = 3 };
+
+// g: transformed (unweighted) reaction; h: spectral state (DIAG_A, DIAG_ETD1: u^;
+// DIAG_B: E u^ + tau (phi_1 - phi_2/c2) G^_1).  Returns the value to inverse
+// transform in *out and the new state in *nh.
+template <int MODE>
+__device__ __forceinline__ void diag_apply(const Sep& s, double D, double tau, double c2, double g, double h,
+                                           double* out, double* nh) {
+  const double G = g * s.w;
+  const double rL = 1.0 / (D * s.lam);
+  if (MODE == DIAG_ETD1) {
+    const double un = h + s.M * h - s.M * rL * G;
+    *out = un;
+    *nh = un;
+  } else if (MODE == DIAG_A) {
+    *out = h + s.Mc * h - s.Mc * rL * G;
+    const double a2 = s.Q * rL * rL / (tau * c2);
+    *nh = h + s.M * h - (s.M * rL + a2) * G;
   } else {
-    p1 = (E - 1.0) / z;
-    p2 = (p1 - 1.0) / z;
+    const double a2 = s.Q * rL * rL / (tau * c2);
+    const double un = h + a2 * G;
+    *out = un;
+    *nh = un;
   }
 }
-
-__device__ __forceinline__ double phi1_only(double z, double E) {
-  double p1, p2;
-  phi12(z, E, p1, p2);
-  return p1;
-}
-
-// ---------------------------------------------------------------------------
-struct AxisTab {
-  const double* lam;  // D-free eigenvalue lambda_k = lamB/lamA of the 1D pair (B, A)
-  const double* w;    // load weight h/lamA (lumped) or 1 (nodal); 0 on padding
-  const double* E;    // exp(-tau D lambda_k)
-  const double* Ec;   // exp(-c2 tau D lambda_k)
-};
 
 struct Diag {
   AxisTab ax[3];
@@ -416,10 +422,7 @@ __global__ void __launch_bounds__(256) col_pass(T* __restrict__ W, T* __restrict
     const T ga = -Z.im * scale, gb = Z.re * scale;
     const int ky = g.last_is_z ? outer : m;
     const int kz = g.last_is_z ? m : 0;
-    const double lyz = dg.ax[1].lam[ky] + dg.ax[2].lam[kz];
-    const double wyz = dg.ax[1].w[ky] * dg.ax[2].w[kz];
-    const double Eyz = dg.ax[1].E[ky] * dg.ax[2].E[kz];
-    const double Ecyz = dg.ax[1].Ec[ky] * dg.ax[2].Ec[kz];
+    const Sep syz = sep_combine(sep_load(dg.ax[1], ky), sep_load(dg.ax[2], kz));
     T* hp = H + base + m * g.ld_line + 2 * p;
     Cx<T> hv = *reinterpret_cast<Cx<T>*>(hp);
     T outv[2];
@@ -428,31 +431,16 @@ __global__ void __launch_bounds__(256) col_pass(T* __restrict__ W, T* __restrict
     const T hin[2] = {hv.re, hv.im};
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const int kx = c0 + 2 * p + q;
-      const double lam = D * (dg.ax[0].lam[kx] + lyz);
-      const double z = -tau * lam;
-      const double E = dg.ax[0].E[kx] * Eyz;
-      const double G = double(gin[q]) * (dg.ax[0].w[kx] * wyz);
-      const double h = double(hin[q]);
-      if (MODE == COL_ETD1) {
-        const double p1 = phi1_only(z, E);
-        const double un = E * h + tau * p1 * G;
-        newh[q] = T(un);
-        outv[q] = T(un);
-      } else if (MODE == COL_STAGE_A) {
-        double p1, p2;
-        phi12(z, E, p1, p2);
-        const double Ec = dg.ax[0].Ec[kx] * Ecyz;
-        const double p1c = phi1_only(c2 * z, Ec);
-        outv[q] = T(Ec * h + c2 * tau * p1c * G);
-        newh[q] = T(E * h + tau * (p1 - p2 / c2) * G);
-      } else {  // COL_STAGE_B: h holds E u + tau (phi1 - phi2/c2) G1
-        double p1, p2;
-        phi12(z, E, p1, p2);
-        const double un = h + tau * (p2 / c2) * G;
-        newh[q] = T(un);
-        outv[q] = T(un);
-      }
+      const Sep s = sep_combine(sep_load(dg.ax[0], c0 + 2 * p + q), syz);
+      double o, nh;
+      if (MODE == COL_ETD1)
+        diag_apply<DIAG_ETD1>(s, D, tau, c2, double(gin[q]), double(hin[q]), &o, &nh);
+      else if (MODE == COL_STAGE_A)
+        diag_apply<DIAG_A>(s, D, tau, c2, double(gin[q]), double(hin[q]), &o, &nh);
+      else
+        diag_apply<DIAG_B>(s, D, tau, c2, double(gin[q]), double(hin[q]), &o, &nh);
+      outv[q] = T(o);
+      newh[q] = T(nh);
     }
     *reinterpret_cast<Cx<T>*>(hp) = Cx<T>{newh[0], newh[1]};
     put_odd(line, L, m + 1, outv[0], outv[1]);

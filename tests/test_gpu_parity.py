@@ -252,3 +252,38 @@ def test_abi_errors():
     with pytest.raises(eife.EIFEError) as e:
         eife.Grid([8192, 8], [0.1, 0.1], 1.0)
     assert e.value.code == -3
+
+
+FAST_GRIDS = [
+    _case("2d-64x128", [64, 128]),
+    _case("2d-256x64", [256, 64]),
+    _case("2d-512x128", [512, 128]),
+    _case("3d-128x64x256", [128, 64, 256]),
+    _case("3d-256x96x48-mixed", [256, 96, 48]),
+    _case("1d-512", [512]),
+]
+
+
+@pytest.mark.parametrize("N", FAST_GRIDS)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("stages", [1, 2])
+def test_specialised_passes_match_generic_and_oracle(N, dtype, stages):
+    """The specialised power-of-two passes agree with the generic passes and the oracle."""
+    eife = _lib()
+    h = [1.0 / n for n in N]
+    D = 1e-3
+    u0 = seeded_inputs.uniform_field(31, N)
+    outs = []
+    for tx in (eife.binding.TX_FFT, eife.binding.TX_FFT_GENERIC):
+        g = eife.Grid(N, h, D, dtype)
+        g.set_transform(tx)
+        g.set_phi(0.01, stages)
+        u = torch.tensor(u0, dtype=g.torch_dtype, device="cuda")
+        g.step(u, 6, eife.F_ALLEN_CAHN)
+        torch.cuda.synchronize()
+        outs.append(u.double().cpu().numpy())
+        g.close()
+    ref = _oracle("C", N, h, D, u0, problems.allen_cahn(), 0.01, 6, stages)
+    assert _rel(outs[0], ref) <= TOL[dtype]
+    assert _rel(outs[1], ref) <= TOL[dtype]
+    assert _rel(outs[0], outs[1]) <= TOL[dtype]
