@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run a plain device copy of one work array's size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the EIFE path here is built and timed on a single MI355X "
@@ -88,6 +90,14 @@ def main():
     u0 = seeded_inputs.uniform_field(SEED, N)
     log(f"bench: 3D Allen-Cahn {N_INT - 1}^3 FP32 EIFE2 tau={TAU} warmup={args.warmup} steps={args.steps}")
 
+    if args.copy_calib:
+        a = torch.ones(ndof, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"bench: calibration copy of {ndof * 4} bytes x3")
+        del a, b
     g = eife.Grid(N, h, D, "f32")
     g.set_phi(TAU, 2)
     u = torch.tensor(u0, dtype=torch.float32, device="cuda")

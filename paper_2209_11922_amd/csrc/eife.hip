@@ -308,28 +308,48 @@ void row_fast_launch(int mode, int nrows, hipStream_t s, const T* src, T* dst, T
   constexpr int PB = fast_pb<T, L>();
   constexpr int NT = PB * fast::FftShape<L>::LP;
   dim3 grid((nrows + 2 * PB - 1) / (2 * PB));
-  if (mode == ROW_PHYS)
-    hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_PHYS>), grid, dim3(NT), 0, s, src, dst, dst2, rg, tw, F);
-  else if (mode == ROW_FWD_USER)
-    hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_FWD_USER>), grid, dim3(NT), 0, s, src, dst, dst2, rg, tw, F);
-  else
-    hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_INV_USER>), grid, dim3(NT), 0, s, src, dst, dst2, rg, tw, F);
+  if (mode == ROW_PHYS) {
+    if (F.kind == FK_AC)
+      hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_PHYS, fast::RK_AC>), grid, dim3(NT), 0, s, src, dst, dst2,
+                         rg, tw, F);
+    else
+      hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_PHYS, fast::RK_GENERIC>), grid, dim3(NT), 0, s, src, dst,
+                         dst2, rg, tw, F);
+  } else if (mode == ROW_FWD_USER) {
+    hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_FWD_USER, fast::RK_GENERIC>), grid, dim3(NT), 0, s, src, dst,
+                       dst2, rg, tw, F);
+  } else {
+    hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_INV_USER, fast::RK_GENERIC>), grid, dim3(NT), 0, s, src, dst,
+                       dst2, rg, tw, F);
+  }
+}
+
+// Column passes: 128-byte row segments (32 FP32 / 16 FP64 columns); pairs per
+// wavefront slice chosen so a block has at most 512 threads.
+template <typename T, int L>
+constexpr int col_pb() {
+  return (L >= 1024) ? (sizeof(T) == 4 ? 8 : 4) : (sizeof(T) == 4 ? 16 : 8);
+}
+template <typename T, int L>
+constexpr int col_ppw() {
+  return (col_pb<T, L>() * fast::FftShape<L>::LP > 512) ? col_pb<T, L>() * fast::FftShape<L>::LP / 512 : 1;
 }
 
 template <typename T, int L>
 void col_fast_launch(int mode, int pitch, int outer, hipStream_t s, T* W, T* H, const ColGeom& cg,
                      const Cx<T>* tw, const Diag& dg) {
-  constexpr int PB = fast_pb<T, L>();
-  constexpr int NT = PB * fast::FftShape<L>::LP;
+  constexpr int PB = col_pb<T, L>();
+  constexpr int PPW = col_ppw<T, L>();
+  constexpr int NT = PB / PPW * fast::FftShape<L>::LP;
   dim3 grid(pitch / (2 * PB), outer);
   if (mode == COL_PLAIN)
-    hipLaunchKernelGGL((fast::col_fast<T, L, PB, COL_PLAIN>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+    hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_PLAIN>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
   else if (mode == COL_STAGE_A)
-    hipLaunchKernelGGL((fast::col_fast<T, L, PB, COL_STAGE_A>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+    hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_STAGE_A>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
   else if (mode == COL_STAGE_B)
-    hipLaunchKernelGGL((fast::col_fast<T, L, PB, COL_STAGE_B>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+    hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_STAGE_B>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
   else
-    hipLaunchKernelGGL((fast::col_fast<T, L, PB, COL_ETD1>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+    hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_ETD1>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
 }
 
 template <typename T>

@@ -89,9 +89,32 @@ struct FftShape {
   static constexpr int E = (L <= 512) ? 8 : 16;  // complex values per lane
   static constexpr int LP = L / E;                // lanes per line pair
   static constexpr int R2 = L / (E * E);          // radix of the third stage
-  static constexpr int BUF = L + L / 8;           // padded exchange buffer (complex)
+  static constexpr int BUF = L + L / 8 + 4;       // pair region: padded exchange buffer + bank offset
+  static constexpr int NB2 = E / R2;              // third-stage butterflies per lane
   static_assert(LP <= 64, "a line pair must fit in one wavefront");
   static_assert(R2 >= 2 && R2 <= E, "unsupported FFT length");
+};
+
+// The twiddle factors one lane needs, loaded once per kernel.
+template <typename T, int L>
+struct LaneTw {
+  static constexpr int E = FftShape<L>::E;
+  static constexpr int R2 = FftShape<L>::R2;
+  static constexpr int NB2 = FftShape<L>::NB2;
+  static constexpr int LP = FftShape<L>::LP;
+  Cx<T> s1[E];        // stage 2 (Ns = E): W_L^{q k (L / E^2)}, k = lane mod E
+  Cx<T> s2[NB2][R2];  // stage 3 (Ns = E^2): W_L^{q j}, j = lane + LP b
+  __device__ __forceinline__ void load(const Cx<T>* __restrict__ tw, int lane) {
+    const int k = lane & (E - 1);
+#pragma unroll
+    for (int q = 1; q < E; ++q) s1[q] = tw[(q * k) * (L / (E * E))];
+#pragma unroll
+    for (int b = 0; b < NB2; ++b) {
+      const int j = lane + LP * b;
+#pragma unroll
+      for (int q = 1; q < R2; ++q) s2[b][q] = tw[q * j];
+    }
+  }
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -101,11 +124,11 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // One Stockham stage of radix R on the pair owned by this lane group.
-// `in(i)` yields input i of the stage; unless LAST, the outputs are written
-// to buf, else they stay in v (v[b*R+q] = output lane + LP*b + q*(L/R)).
-template <typename T, int L, int R, int Ns, bool LAST, typename In>
-__device__ __forceinline__ void wstage(Cx<T> (&v)[FftShape<L>::E], In in, Cx<T>* buf, int lane,
-                                       const Cx<T>* __restrict__ tw) {
+// `in(i, q)` yields input i of the stage; `tw(b, q)` the twiddle of input q of
+// butterfly b.  Unless LAST, the outputs are written to buf, else they stay
+// in v (v[b*R+q] = output lane + LP*b + q*(L/R)).
+template <typename T, int L, int R, int Ns, bool LAST, typename In, typename Tw>
+__device__ __forceinline__ void wstage(Cx<T> (&v)[FftShape<L>::E], In in, Tw twf, Cx<T>* buf, int lane) {
   constexpr int E = FftShape<L>::E;
   constexpr int LP = FftShape<L>::LP;
   constexpr int NB = E / R;
@@ -116,9 +139,8 @@ __device__ __forceinline__ void wstage(Cx<T> (&v)[FftShape<L>::E], In in, Cx<T>*
 #pragma unroll
     for (int q = 0; q < R; ++q) v[b * R + q] = in(j + STRIDE * q, q);
     if (Ns > 1) {
-      const int k = j & (Ns - 1);
 #pragma unroll
-      for (int q = 1; q < R; ++q) v[b * R + q] = cmul(v[b * R + q], tw[(q * k) * (L / (Ns * R))]);
+      for (int q = 1; q < R; ++q) v[b * R + q] = cmul(v[b * R + q], twf(b, q));
     }
     DftN<T, R>::run(&v[b * R]);
   }
@@ -139,7 +161,7 @@ __device__ __forceinline__ void wstage(Cx<T> (&v)[FftShape<L>::E], In in, Cx<T>*
 // outputs (see wstage with LAST).
 template <typename T, int L, typename Get>
 __device__ __forceinline__ void odd_fft(Cx<T> (&v)[FftShape<L>::E], Get get, Cx<T>* buf, int lane,
-                                        const Cx<T>* __restrict__ tw) {
+                                        const LaneTw<T, L>& tw) {
   constexpr int E = FftShape<L>::E;
   constexpr int R2 = FftShape<L>::R2;
   constexpr int N = L / 2;
@@ -154,11 +176,14 @@ __device__ __forceinline__ void odd_fft(Cx<T> (&v)[FftShape<L>::E], Get get, Cx<
     return Cx<T>{-c.re, -c.im};
   };
   auto inb = [&](int i, int) -> Cx<T> { return buf[xpad(i)]; };
-  wstage<T, L, E, 1, false>(v, in0, buf, lane, tw);
+  auto tw0 = [&](int, int) -> Cx<T> { return Cx<T>{T(1), T(0)}; };
+  auto tw1 = [&](int, int q) -> Cx<T> { return tw.s1[q]; };
+  auto tw2 = [&](int b, int q) -> Cx<T> { return tw.s2[b][q]; };
+  wstage<T, L, E, 1, false>(v, in0, tw0, buf, lane);
   wave_sync();
-  wstage<T, L, E, E, false>(v, inb, buf, lane, tw);
+  wstage<T, L, E, E, false>(v, inb, tw1, buf, lane);
   wave_sync();
-  wstage<T, L, R2, E * E, true>(v, inb, buf, lane, tw);
+  wstage<T, L, R2, E * E, true>(v, inb, tw2, buf, lane);
   wave_sync();  // buf may be rewritten by the next transform of this pair
 }
 
@@ -180,39 +205,70 @@ __device__ __forceinline__ void for_outputs(const Cx<T> (&v)[FftShape<L>::E], in
 }
 
 // ---------------------------------------------------------------------------
+// Each line pair owns one LDS region of FftShape<L>::BUF complex entries.  Its
+// first N - 1 entries hold the pair's node values (the "tile"); the whole
+// region doubles as the pair's FFT exchange buffer, which is safe because
+// stage 1 has read every node value before it writes the region and only
+// the pair's own wavefront slice touches it between block barriers.
+
+// Reaction kinds that get their own code path (everything else is generic).
+enum { RK_GENERIC = 0, RK_AC = 1 };
+
+template <typename T, int RK>
+__device__ __forceinline__ T reaction_k(const Forcing& F, T u, int ix, int iy, int iz) {
+  if (RK == RK_AC) return u - u * u * u;
+  return reaction<T>(F, u, ix, iy, iz);
+}
+
+// ---------------------------------------------------------------------------
 // Row passes (x lines, contiguous).  Block = PB line pairs = 2 PB rows.
-template <typename T, int L, int PB, int MODE>
-__global__ void __launch_bounds__(PB * FftShape<L>::LP) row_fast(const T* src, T* dst, T* __restrict__ dst2,
+template <typename T, int L, int PB, int MODE, int RK>
+__global__ void __launch_bounds__(PB * FftShape<L>::LP, 4) row_fast(const T* src, T* dst, T* __restrict__ dst2,
                                                                   RowGeom g, const Cx<T>* __restrict__ tw, Forcing F) {
   constexpr int N = L / 2;
   constexpr int n = N - 1;
   constexpr int LP = FftShape<L>::LP;
   constexpr int E = FftShape<L>::E;
-  constexpr int RS = N;  // tile row stride (complex)
-  __shared__ Cx<T> tile[PB * RS];
-  __shared__ Cx<T> xbuf[PB * FftShape<L>::BUF];
+  constexpr int BUF = FftShape<L>::BUF;
+  constexpr int NT = PB * LP;
+  __shared__ Cx<T> lds[PB * BUF];
   const int tid = threadIdx.x;
   const int r0 = blockIdx.x * 2 * PB;
   const T scale = T(1.0 / sqrt(double(L)));
+  const int p = tid / LP;
+  const int lane = tid - p * LP;
+  LaneTw<T, L> twl;
+  twl.load(tw, lane);
 
-  // coalesced load of 2 PB rows into the pair-major tile
-  for (int i = tid; i < 2 * PB * n; i += PB * LP) {
-    const int row = i / n;
-    const int m = i - row * n;
-    const int r = r0 + row;
-    const T val = (r < g.nrows) ? src[r * g.ld_src + m] : T(0);
-    T* slot = reinterpret_cast<T*>(&tile[(row >> 1) * RS + m]);
-    slot[row & 1] = val;
+  // coalesced load of 2 PB rows into the pair regions: all loads in flight first
+  constexpr int RIT = (2 * PB * n + NT - 1) / NT;
+  const T* srow = src + int64_t(r0) * g.ld_src;
+  const int nload = min(2 * PB, g.nrows - r0) * n;
+  {
+    T tmp[RIT];
+#pragma unroll
+    for (int it = 0; it < RIT; ++it) {
+      const int i = tid + it * NT;
+      const int row = i / n;
+      const int m = i - row * n;
+      tmp[it] = (i < nload) ? srow[row * g.ld_src + m] : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < RIT; ++it) {
+      const int i = tid + it * NT;
+      if (i < 2 * PB * n) {
+        const int row = i / n;
+        const int m = i - row * n;
+        reinterpret_cast<T*>(&lds[(row >> 1) * BUF + m])[row & 1] = tmp[it];
+      }
+    }
   }
   __syncthreads();
 
-  const int p = tid / LP;
-  const int lane = tid - p * LP;
-  Cx<T>* my = tile + p * RS;
-  Cx<T>* buf = xbuf + p * FftShape<L>::BUF;
+  Cx<T>* my = lds + p * BUF;
   auto get = [&](int i) -> Cx<T> { return my[i]; };
   Cx<T> v[E];
-  odd_fft<T, L>(v, get, buf, lane, tw);
+  odd_fft<T, L>(v, get, my, lane, twl);
 
   if (MODE == ROW_PHYS) {
     const int ra = r0 + 2 * p, rb = ra + 1;
@@ -220,65 +276,121 @@ __global__ void __launch_bounds__(PB * FftShape<L>::LP) row_fast(const T* src, T
     const int iyb = rb % g.ny, izb = rb / g.ny;
     for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) {
       const T ua = -Z.im * scale, ub = Z.re * scale;
-      const T fa = reaction<T>(F, ua, k - 1, iya, iza);
-      const T fb = (rb < g.nrows) ? reaction<T>(F, ub, k - 1, iyb, izb) : T(0);
+      const T fa = reaction_k<T, RK>(F, ua, k - 1, iya, iza);
+      const T fb = reaction_k<T, RK>(F, ub, k - 1, iyb, izb);
       my[k - 1] = Cx<T>{fa, fb};
     });
     wave_sync();
-    odd_fft<T, L>(v, get, buf, lane, tw);
+    odd_fft<T, L>(v, get, my, lane, twl);
   }
   for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
   __syncthreads();
-  for (int i = tid; i < 2 * PB * n; i += PB * LP) {
-    const int row = i / n;
-    const int m = i - row * n;
-    const int r = r0 + row;
-    if (r < g.nrows) {
-      const T val = reinterpret_cast<const T*>(&tile[(row >> 1) * RS + m])[row & 1];
-      dst[r * g.ld_dst + m] = val;
-      if (MODE == ROW_FWD_USER) dst2[r * g.ld_dst + m] = val;
+  T* drow = dst + int64_t(r0) * g.ld_dst;
+  T* drow2 = dst2 + int64_t(r0) * g.ld_dst;
+#pragma unroll
+  for (int it = 0; it < RIT; ++it) {
+    const int i = tid + it * NT;
+    if (i < nload) {
+      const int row = i / n;
+      const int m = i - row * n;
+      const T val = reinterpret_cast<const T*>(&lds[(row >> 1) * BUF + m])[row & 1];
+      drow[row * g.ld_dst + m] = val;
+      if (MODE == ROW_FWD_USER) drow2[row * g.ld_dst + m] = val;
     }
   }
 }
 
+// 1 / x in double from the hardware estimate and two Newton steps (x > 0 normal).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+template <int MODE>
+__device__ __forceinline__ void diag_fast(const Sep& s, double D, double tau, double rtc2, double g, double h,
+                                          double* out, double* nh) {
+  const double G = g * s.w;
+  const double rL = rcp64(D * s.lam);
+  if (MODE == COL_ETD1) {
+    const double un = fma(s.M, h - rL * G, h);  // h + M h - M rL G
+    *out = un;
+    *nh = un;
+  } else if (MODE == COL_STAGE_A) {
+    *out = fma(s.Mc, h - rL * G, h);
+    const double a2 = s.Q * rL * rL * rtc2;  // tau phi_2 / c2
+    *nh = fma(s.M, h, h) - fma(s.M, rL, a2) * G;
+  } else {
+    const double un = fma(s.Q * rL * rL * rtc2, G, h);
+    *out = un;
+    *nh = un;
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Column passes (strided axis).  Block = PB pairs = C = 2 PB adjacent x-columns.
-template <typename T, int L, int PB, int MODE>
-__global__ void __launch_bounds__(PB * FftShape<L>::LP) col_fast(T* __restrict__ W, T* __restrict__ H, ColGeom g,
-                                                                  const Cx<T>* __restrict__ tw, Diag dg) {
+// Column passes (strided axis).  Block = PB pairs = C = 2 PB adjacent x-columns
+// (C * sizeof(T) >= 128 bytes per row segment); each wavefront slice of LP
+// lanes transforms PPW of the pairs one after the other.
+template <typename T, int L, int PB, int PPW, int MODE>
+__global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* __restrict__ W, T* __restrict__ H,
+                                                                        ColGeom g, const Cx<T>* tw, Diag dg) {
   constexpr int N = L / 2;
   constexpr int n = N - 1;
   constexpr int LP = FftShape<L>::LP;
   constexpr int E = FftShape<L>::E;
-  constexpr int NT = PB * LP;
-  constexpr int TS = PB + 1;  // tile row stride (complex), padded against bank conflicts
-  __shared__ Cx<T> tile[n * TS];
-  __shared__ Cx<T> xbuf[PB * FftShape<L>::BUF];
+  constexpr int BUF = FftShape<L>::BUF;
+  constexpr int SLOTS = PB / PPW;
+  constexpr int NT = SLOTS * LP;
+  __shared__ Cx<T> lds[PB * BUF];
   const int tid = threadIdx.x;
   const int c0 = blockIdx.x * 2 * PB;
   const int outer = blockIdx.y;
   const int64_t base = int64_t(outer) * g.ld_outer + c0;
   const T scale = T(1.0 / sqrt(double(L)));
+  const int slot = tid / LP;
+  const int lane = tid - slot * LP;
 
-  for (int i = tid; i < n * PB; i += NT) {
-    const int m = i / PB;
-    const int q = i - m * PB;
-    tile[m * TS + q] = *reinterpret_cast<const Cx<T>*>(W + base + m * g.ld_line + 2 * q);
+  constexpr int CIT = (n * PB + NT - 1) / NT;
+  const T* Wb = W + base;
+  {
+    Cx<T> tmp[CIT];
+#pragma unroll
+    for (int it = 0; it < CIT; ++it) {
+      const int i = tid + it * NT;
+      const int m = i / PB;
+      const int q = i - m * PB;
+      if (i < n * PB) tmp[it] = *reinterpret_cast<const Cx<T>*>(Wb + m * g.ld_line + 2 * q);
+    }
+#pragma unroll
+    for (int it = 0; it < CIT; ++it) {
+      const int i = tid + it * NT;
+      const int m = i / PB;
+      const int q = i - m * PB;
+      if (i < n * PB) lds[q * BUF + m] = tmp[it];
+    }
   }
   __syncthreads();
 
-  const int p = tid / LP;
-  const int lane = tid - p * LP;
-  Cx<T>* buf = xbuf + p * FftShape<L>::BUF;
-  auto get = [&](int i) -> Cx<T> { return tile[i * TS + p]; };
   Cx<T> v[E];
-  odd_fft<T, L>(v, get, buf, lane, tw);
-  for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { tile[(k - 1) * TS + p] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+  {
+    LaneTw<T, L> twl;
+    twl.load(tw, lane);
+#pragma unroll 1
+    for (int r = 0; r < PPW; ++r) {
+      Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
+      auto get = [&](int i) -> Cx<T> { return my[i]; };
+      odd_fft<T, L>(v, get, my, lane, twl);
+      for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+    }
+  }
 
   if (MODE != COL_PLAIN) {
     __syncthreads();
     // diagonal stage over the tile: thread -> (row m, pair q), pair fixed per thread
-    const double tau = dg.tau, c2 = dg.c2, D = dg.D;
+    const double tau = dg.tau, D = dg.D;
+    const double rtc2 = 1.0 / (tau * dg.c2);
     const int q = tid % PB;
     const int kx0 = c0 + 2 * q;
     Sep sxy[2];
@@ -292,37 +404,54 @@ __global__ void __launch_bounds__(PB * FftShape<L>::LP) col_fast(T* __restrict__
       sxy[1] = sep_combine(sep_load(dg.ax[0], kx0 + 1), sz);
     }
     const AxisTab& line_tab = g.last_is_z ? dg.ax[2] : dg.ax[1];
-    for (int m = tid / PB; m < n; m += NT / PB) {
-      const Sep sl = sep_load(line_tab, m);
-      const Cx<T> gv = tile[m * TS + q];
-      Cx<T>* hp = reinterpret_cast<Cx<T>*>(H + base + m * g.ld_line + 2 * q);
-      const Cx<T> hv = *hp;
-      double o0, o1, n0, n1;
-      const Sep s0 = sep_combine(sxy[0], sl);
-      const Sep s1 = sep_combine(sxy[1], sl);
-      if (MODE == COL_ETD1) {
-        diag_apply<DIAG_ETD1>(s0, D, tau, c2, double(gv.re), double(hv.re), &o0, &n0);
-        diag_apply<DIAG_ETD1>(s1, D, tau, c2, double(gv.im), double(hv.im), &o1, &n1);
-      } else if (MODE == COL_STAGE_A) {
-        diag_apply<DIAG_A>(s0, D, tau, c2, double(gv.re), double(hv.re), &o0, &n0);
-        diag_apply<DIAG_A>(s1, D, tau, c2, double(gv.im), double(hv.im), &o1, &n1);
-      } else {
-        diag_apply<DIAG_B>(s0, D, tau, c2, double(gv.re), double(hv.re), &o0, &n0);
-        diag_apply<DIAG_B>(s1, D, tau, c2, double(gv.im), double(hv.im), &o1, &n1);
+    T* Hb = H + base + 2 * q;
+    Cx<T>* tq = lds + q * BUF;
+    constexpr int MS = NT / PB;  // rows advanced per iteration
+    constexpr int DIT = (n + MS - 1) / MS;
+    constexpr int BATCH = 4;
+    const int m0 = tid / PB;
+#pragma unroll
+    for (int b0 = 0; b0 < DIT; b0 += BATCH) {
+      Cx<T> hv[BATCH];
+#pragma unroll
+      for (int it = 0; it < BATCH; ++it) {
+        const int m = m0 + (b0 + it) * MS;
+        if (b0 + it < DIT && m < n) hv[it] = *reinterpret_cast<const Cx<T>*>(Hb + m * g.ld_line);
       }
-      *hp = Cx<T>{T(n0), T(n1)};
-      tile[m * TS + q] = Cx<T>{T(o0), T(o1)};
+#pragma unroll
+      for (int it = 0; it < BATCH; ++it) {
+        const int m = m0 + (b0 + it) * MS;
+        if (b0 + it < DIT && m < n) {
+          const Sep sl = sep_load(line_tab, m);
+          const Cx<T> gv = tq[m];
+          double o0, o1, n0, n1;
+          diag_fast<MODE>(sep_combine(sxy[0], sl), D, tau, rtc2, double(gv.re), double(hv[it].re), &o0, &n0);
+          diag_fast<MODE>(sep_combine(sxy[1], sl), D, tau, rtc2, double(gv.im), double(hv[it].im), &o1, &n1);
+          *reinterpret_cast<Cx<T>*>(Hb + m * g.ld_line) = Cx<T>{T(n0), T(n1)};
+          tq[m] = Cx<T>{T(o0), T(o1)};
+        }
+      }
     }
     __syncthreads();
-    odd_fft<T, L>(v, get, buf, lane, tw);
-    for_outputs<T, L>(v, lane,
-                      [&](int k, Cx<T> Z) { tile[(k - 1) * TS + p] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+    __asm__ volatile("" ::: "memory");
+    LaneTw<T, L> twl;
+    twl.load(tw, lane);
+#pragma unroll 1
+    for (int r = 0; r < PPW; ++r) {
+      Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
+      auto get = [&](int i) -> Cx<T> { return my[i]; };
+      odd_fft<T, L>(v, get, my, lane, twl);
+      for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+    }
   }
   __syncthreads();
-  for (int i = tid; i < n * PB; i += NT) {
+  T* Wo = W + base;
+#pragma unroll
+  for (int it = 0; it < CIT; ++it) {
+    const int i = tid + it * NT;
     const int m = i / PB;
     const int q = i - m * PB;
-    *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * q) = tile[m * TS + q];
+    if (i < n * PB) *reinterpret_cast<Cx<T>*>(Wo + m * g.ld_line + 2 * q) = lds[q * BUF + m];
   }
 }
 
