@@ -124,70 +124,93 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // One Stockham stage of radix R on the pair owned by this lane group.
-// `in(i, q)` yields input i of the stage; `tw(b, q)` the twiddle of input q of
-// butterfly b.  Unless LAST, the outputs are written to buf, else they stay
-// in v (v[b*R+q] = output lane + LP*b + q*(L/R)).
+// `in(b, q)` yields input q of butterfly b (stage input index
+// j + (L/R) q, j = lane + LP b); `tw(b, q)` its twiddle.  Unless LAST, the
+// outputs are written to buf, else they stay in v
+// (v[b*R+q] = output lane + LP*b + q*(L/R)).
+// Padded indices: xpad(B + 8t) = xpad(B) + 9t, so every buffer access is a
+// per-lane base plus a compile-time offset.
 template <typename T, int L, int R, int Ns, bool LAST, typename In, typename Tw>
 __device__ __forceinline__ void wstage(Cx<T> (&v)[FftShape<L>::E], In in, Tw twf, Cx<T>* buf, int lane) {
   constexpr int E = FftShape<L>::E;
   constexpr int LP = FftShape<L>::LP;
   constexpr int NB = E / R;
-  constexpr int STRIDE = L / R;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int j = lane + LP * b;
 #pragma unroll
-    for (int q = 0; q < R; ++q) v[b * R + q] = in(j + STRIDE * q, q);
-    if (Ns > 1) {
+    for (int q = 0; q < R; ++q) v[b * R + q] = in(b, q);
+    if constexpr (Ns > 1) {
 #pragma unroll
       for (int q = 1; q < R; ++q) v[b * R + q] = cmul(v[b * R + q], twf(b, q));
     }
     DftN<T, R>::run(&v[b * R]);
   }
-  if (!LAST) {
+  if constexpr (!LAST) {
+    if constexpr (Ns == 1) {
+      // base = R j: xpad(R j + q) = R j + (R j >> 3) + q + (q >> 3) (R multiple of 8)
+      static_assert(R % 8 == 0, "first stage radix must be a multiple of 8");
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int j = lane + LP * b;
-      const int k = j & (Ns - 1);
-      const int base = (j - k) * R + k;
+      for (int b = 0; b < NB; ++b) {
+        const int j = lane + LP * b;
+        Cx<T>* o = buf + R * j + ((R * j) >> 3);
 #pragma unroll
-      for (int q = 0; q < R; ++q) buf[xpad(base + q * Ns)] = v[b * R + q];
+        for (int q = 0; q < R; ++q) o[q + (q >> 3)] = v[b * R + q];
+      }
+    } else {
+      static_assert(Ns % 8 == 0, "stride of later stages must be a multiple of 8");
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = lane + LP * b;
+        const int k = j & (Ns - 1);
+        const int base = (j - k) * R + k;
+        Cx<T>* o = buf + xpad(base);
+#pragma unroll
+        for (int q = 0; q < R; ++q) o[q * Ns + (q * Ns) / 8] = v[b * R + q];
+      }
     }
   }
 }
 
 // Forward FFT of length L of the odd extension of the pair whose node values
-// are given by get(i) (i = node index 0 .. N-2).  On return v holds the
-// outputs (see wstage with LAST).
-template <typename T, int L, typename Get>
-__device__ __forceinline__ void odd_fft(Cx<T> (&v)[FftShape<L>::E], Get get, Cx<T>* buf, int lane,
+// sit at node[0 .. N-2].  On return v holds the outputs (see wstage with LAST).
+template <typename T, int L>
+__device__ __forceinline__ void odd_fft(Cx<T> (&v)[FftShape<L>::E], const Cx<T>* node, Cx<T>* buf, int lane,
                                         const LaneTw<T, L>& tw) {
   constexpr int E = FftShape<L>::E;
+  constexpr int LP = FftShape<L>::LP;
   constexpr int R2 = FftShape<L>::R2;
   constexpr int N = L / 2;
-  auto in0 = [&](int m, int q) -> Cx<T> {
-    // q < E/2  <=>  m < N  (m = j + (L/E) q with j < L/E)
+  // stage 0: input m = lane + LP q; q < E/2 <=> m < N
+  const Cx<T>* lo = node + (lane - 1);          // node[m - 1]
+  const Cx<T>* hi = node + (2 * N - 1 - lane);  // node[2N - m - 1] = hi[-LP q]
+  auto in0 = [&](int, int q) -> Cx<T> {
     if (q < E / 2) {
-      if (q == 0 && m == 0) return Cx<T>{T(0), T(0)};
-      return get(m - 1);
+      if (q == 0) return lane == 0 ? Cx<T>{T(0), T(0)} : lo[0];
+      return lo[LP * q];
     }
-    if (q == E / 2 && m == N) return Cx<T>{T(0), T(0)};
-    const Cx<T> c = get(2 * N - m - 1);
+    if (q == E / 2 && lane == 0) return Cx<T>{T(0), T(0)};
+    const Cx<T> c = hi[-LP * q];
     return Cx<T>{-c.re, -c.im};
   };
-  auto inb = [&](int i, int) -> Cx<T> { return buf[xpad(i)]; };
+  // later stages read input j + (L/R) q at xpad(j) + (L/R) q * 9/8
+  const Cx<T>* rb = buf + xpad(lane);
+  auto in1 = [&](int, int q) -> Cx<T> { return rb[(L / E) * q + (L / E) * q / 8]; };
+  auto in2 = [&](int b, int q) -> Cx<T> {
+    return rb[LP * b + (LP * b) / 8 + (L / R2) * q + (L / R2) * q / 8];
+  };
   auto tw0 = [&](int, int) -> Cx<T> { return Cx<T>{T(1), T(0)}; };
   auto tw1 = [&](int, int q) -> Cx<T> { return tw.s1[q]; };
   auto tw2 = [&](int b, int q) -> Cx<T> { return tw.s2[b][q]; };
   wstage<T, L, E, 1, false>(v, in0, tw0, buf, lane);
   wave_sync();
-  wstage<T, L, E, E, false>(v, inb, tw1, buf, lane);
+  wstage<T, L, E, E, false>(v, in1, tw1, buf, lane);
   wave_sync();
-  wstage<T, L, R2, E * E, true>(v, inb, tw2, buf, lane);
+  wstage<T, L, R2, E * E, true>(v, in2, tw2, buf, lane);
   wave_sync();  // buf may be rewritten by the next transform of this pair
 }
 
-// Visit the outputs k in [1, N-1] held by this lane: f(k, Z_k).
+// Visit the outputs k in [1, N-1] held by this lane: f(k, Z_k); k = lane + c
+// with c a compile-time offset for every entry.
 template <typename T, int L, typename F>
 __device__ __forceinline__ void for_outputs(const Cx<T> (&v)[FftShape<L>::E], int lane, F f) {
   constexpr int E = FftShape<L>::E;
@@ -221,57 +244,50 @@ __device__ __forceinline__ T reaction_k(const Forcing& F, T u, int ix, int iy, i
 }
 
 // ---------------------------------------------------------------------------
-// Row passes (x lines, contiguous).  Block = PB line pairs = 2 PB rows.
+// Row passes (x lines, contiguous).  Block = PB line pairs = 2 PB rows; each
+// wavefront slice loads, transforms and stores its own pair, so the pass
+// needs no block barrier.
 template <typename T, int L, int PB, int MODE, int RK>
 __global__ void __launch_bounds__(PB * FftShape<L>::LP, 4) row_fast(const T* src, T* dst, T* __restrict__ dst2,
-                                                                  RowGeom g, const Cx<T>* __restrict__ tw, Forcing F) {
+                                                                     RowGeom g, const Cx<T>* __restrict__ tw,
+                                                                     Forcing F) {
   constexpr int N = L / 2;
   constexpr int n = N - 1;
   constexpr int LP = FftShape<L>::LP;
   constexpr int E = FftShape<L>::E;
   constexpr int BUF = FftShape<L>::BUF;
-  constexpr int NT = PB * LP;
+  constexpr int RIT = (n + LP - 1) / LP;
   __shared__ Cx<T> lds[PB * BUF];
   const int tid = threadIdx.x;
-  const int r0 = blockIdx.x * 2 * PB;
-  const T scale = T(1.0 / sqrt(double(L)));
   const int p = tid / LP;
   const int lane = tid - p * LP;
+  const int ra = blockIdx.x * 2 * PB + 2 * p, rb = ra + 1;
+  const bool hasa = ra < g.nrows, hasb = rb < g.nrows;
+  const T scale = T(1.0 / sqrt(double(L)));
   LaneTw<T, L> twl;
   twl.load(tw, lane);
-
-  // coalesced load of 2 PB rows into the pair regions: all loads in flight first
-  constexpr int RIT = (2 * PB * n + NT - 1) / NT;
-  const T* srow = src + int64_t(r0) * g.ld_src;
-  const int nload = min(2 * PB, g.nrows - r0) * n;
-  {
-    T tmp[RIT];
-#pragma unroll
-    for (int it = 0; it < RIT; ++it) {
-      const int i = tid + it * NT;
-      const int row = i / n;
-      const int m = i - row * n;
-      tmp[it] = (i < nload) ? srow[row * g.ld_src + m] : T(0);
-    }
-#pragma unroll
-    for (int it = 0; it < RIT; ++it) {
-      const int i = tid + it * NT;
-      if (i < 2 * PB * n) {
-        const int row = i / n;
-        const int m = i - row * n;
-        reinterpret_cast<T*>(&lds[(row >> 1) * BUF + m])[row & 1] = tmp[it];
-      }
-    }
-  }
-  __syncthreads();
-
   Cx<T>* my = lds + p * BUF;
-  auto get = [&](int i) -> Cx<T> { return my[i]; };
+
+  {
+    const T* sa = src + int64_t(ra) * g.ld_src + lane;
+    const T* sb = src + int64_t(rb) * g.ld_src + lane;
+    T va[RIT], vb[RIT];
+#pragma unroll
+    for (int t = 0; t < RIT; ++t) {
+      const bool in = lane + LP * t < n;
+      va[t] = (in && hasa) ? sa[LP * t] : T(0);
+      vb[t] = (in && hasb) ? sb[LP * t] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < RIT; ++t)
+      if (lane + LP * t < n) my[lane + LP * t] = Cx<T>{va[t], vb[t]};
+  }
+  wave_sync();
+
   Cx<T> v[E];
-  odd_fft<T, L>(v, get, my, lane, twl);
+  odd_fft<T, L>(v, my, my, lane, twl);
 
   if (MODE == ROW_PHYS) {
-    const int ra = r0 + 2 * p, rb = ra + 1;
     const int iya = ra % g.ny, iza = ra / g.ny;
     const int iyb = rb % g.ny, izb = rb / g.ny;
     for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) {
@@ -281,21 +297,24 @@ __global__ void __launch_bounds__(PB * FftShape<L>::LP, 4) row_fast(const T* src
       my[k - 1] = Cx<T>{fa, fb};
     });
     wave_sync();
-    odd_fft<T, L>(v, get, my, lane, twl);
+    odd_fft<T, L>(v, my, my, lane, twl);
   }
   for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
-  __syncthreads();
-  T* drow = dst + int64_t(r0) * g.ld_dst;
-  T* drow2 = dst2 + int64_t(r0) * g.ld_dst;
+  wave_sync();
+  T* da = dst + int64_t(ra) * g.ld_dst + lane;
+  T* db = dst + int64_t(rb) * g.ld_dst + lane;
+  T* da2 = dst2 + int64_t(ra) * g.ld_dst + lane;
+  T* db2 = dst2 + int64_t(rb) * g.ld_dst + lane;
 #pragma unroll
-  for (int it = 0; it < RIT; ++it) {
-    const int i = tid + it * NT;
-    if (i < nload) {
-      const int row = i / n;
-      const int m = i - row * n;
-      const T val = reinterpret_cast<const T*>(&lds[(row >> 1) * BUF + m])[row & 1];
-      drow[row * g.ld_dst + m] = val;
-      if (MODE == ROW_FWD_USER) drow2[row * g.ld_dst + m] = val;
+  for (int t = 0; t < RIT; ++t) {
+    if (lane + LP * t < n) {
+      const Cx<T> c = my[lane + LP * t];
+      if (hasa) da[LP * t] = c.re;
+      if (hasb) db[LP * t] = c.im;
+      if (MODE == ROW_FWD_USER) {
+        if (hasa) da2[LP * t] = c.re;
+        if (hasb) db2[LP * t] = c.im;
+      }
     }
   }
 }
@@ -352,24 +371,22 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* __r
   const int slot = tid / LP;
   const int lane = tid - slot * LP;
 
-  constexpr int CIT = (n * PB + NT - 1) / NT;
-  const T* Wb = W + base;
+  // tile load: thread -> column pair q = tid % PB, rows m0 + MS it
+  constexpr int MS = NT / PB;
+  constexpr int CIT = (n + MS - 1) / MS;
+  const int tq = tid % PB;
+  const int m0 = tid / PB;
+  const int ldl = int(g.ld_line);  // tile offsets stay below 2^31 elements
+  const Cx<T>* gsrc = reinterpret_cast<const Cx<T>*>(W + base + m0 * ldl + 2 * tq);
+  Cx<T>* ltile = lds + tq * BUF + m0;
   {
     Cx<T> tmp[CIT];
 #pragma unroll
-    for (int it = 0; it < CIT; ++it) {
-      const int i = tid + it * NT;
-      const int m = i / PB;
-      const int q = i - m * PB;
-      if (i < n * PB) tmp[it] = *reinterpret_cast<const Cx<T>*>(Wb + m * g.ld_line + 2 * q);
-    }
+    for (int it = 0; it < CIT; ++it)
+      if (m0 + MS * it < n) tmp[it] = gsrc[(MS * it * ldl) / 2];
 #pragma unroll
-    for (int it = 0; it < CIT; ++it) {
-      const int i = tid + it * NT;
-      const int m = i / PB;
-      const int q = i - m * PB;
-      if (i < n * PB) lds[q * BUF + m] = tmp[it];
-    }
+    for (int it = 0; it < CIT; ++it)
+      if (m0 + MS * it < n) ltile[MS * it] = tmp[it];
   }
   __syncthreads();
 
@@ -380,8 +397,7 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* __r
 #pragma unroll 1
     for (int r = 0; r < PPW; ++r) {
       Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
-      auto get = [&](int i) -> Cx<T> { return my[i]; };
-      odd_fft<T, L>(v, get, my, lane, twl);
+      odd_fft<T, L>(v, my, my, lane, twl);
       for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
     }
   }
@@ -391,7 +407,7 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* __r
     // diagonal stage over the tile: thread -> (row m, pair q), pair fixed per thread
     const double tau = dg.tau, D = dg.D;
     const double rtc2 = 1.0 / (tau * dg.c2);
-    const int q = tid % PB;
+    const int q = tq;
     const int kx0 = c0 + 2 * q;
     Sep sxy[2];
     if (g.last_is_z) {
@@ -404,31 +420,28 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* __r
       sxy[1] = sep_combine(sep_load(dg.ax[0], kx0 + 1), sz);
     }
     const AxisTab& line_tab = g.last_is_z ? dg.ax[2] : dg.ax[1];
-    T* Hb = H + base + 2 * q;
-    Cx<T>* tq = lds + q * BUF;
-    constexpr int MS = NT / PB;  // rows advanced per iteration
-    constexpr int DIT = (n + MS - 1) / MS;
+    Cx<T>* hrow = reinterpret_cast<Cx<T>*>(H + base + m0 * ldl + 2 * q);
+    constexpr int DIT = CIT;
     constexpr int BATCH = 4;
-    const int m0 = tid / PB;
 #pragma unroll
     for (int b0 = 0; b0 < DIT; b0 += BATCH) {
       Cx<T> hv[BATCH];
 #pragma unroll
       for (int it = 0; it < BATCH; ++it) {
         const int m = m0 + (b0 + it) * MS;
-        if (b0 + it < DIT && m < n) hv[it] = *reinterpret_cast<const Cx<T>*>(Hb + m * g.ld_line);
+        if (b0 + it < DIT && m < n) hv[it] = hrow[(MS * (b0 + it) * ldl) / 2];
       }
 #pragma unroll
       for (int it = 0; it < BATCH; ++it) {
         const int m = m0 + (b0 + it) * MS;
         if (b0 + it < DIT && m < n) {
           const Sep sl = sep_load(line_tab, m);
-          const Cx<T> gv = tq[m];
+          const Cx<T> gv = ltile[MS * (b0 + it)];
           double o0, o1, n0, n1;
           diag_fast<MODE>(sep_combine(sxy[0], sl), D, tau, rtc2, double(gv.re), double(hv[it].re), &o0, &n0);
           diag_fast<MODE>(sep_combine(sxy[1], sl), D, tau, rtc2, double(gv.im), double(hv[it].im), &o1, &n1);
-          *reinterpret_cast<Cx<T>*>(Hb + m * g.ld_line) = Cx<T>{T(n0), T(n1)};
-          tq[m] = Cx<T>{T(o0), T(o1)};
+          hrow[(MS * (b0 + it) * ldl) / 2] = Cx<T>{T(n0), T(n1)};
+          ltile[MS * (b0 + it)] = Cx<T>{T(o0), T(o1)};
         }
       }
     }
@@ -439,20 +452,15 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* __r
 #pragma unroll 1
     for (int r = 0; r < PPW; ++r) {
       Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
-      auto get = [&](int i) -> Cx<T> { return my[i]; };
-      odd_fft<T, L>(v, get, my, lane, twl);
+      odd_fft<T, L>(v, my, my, lane, twl);
       for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
     }
   }
   __syncthreads();
-  T* Wo = W + base;
+  Cx<T>* gdst = reinterpret_cast<Cx<T>*>(W + base + m0 * ldl + 2 * tq);
 #pragma unroll
-  for (int it = 0; it < CIT; ++it) {
-    const int i = tid + it * NT;
-    const int m = i / PB;
-    const int q = i - m * PB;
-    if (i < n * PB) *reinterpret_cast<Cx<T>*>(Wo + m * g.ld_line + 2 * q) = lds[q * BUF + m];
-  }
+  for (int it = 0; it < CIT; ++it)
+    if (m0 + MS * it < n) gdst[(MS * it * ldl) / 2] = ltile[MS * it];
 }
 
 }  // namespace fast
