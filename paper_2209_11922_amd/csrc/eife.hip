@@ -53,6 +53,8 @@ constexpr int kThreads = 256;
 constexpr size_t kLdsBudget = 80 * 1024;  // per block, two blocks per CU fit in 160 KB
 constexpr int kNormBlocksMax = 1024;
 constexpr int kTabArrays = 5;  // lam, w, M, Q, Mc per axis
+constexpr int kPipeBlocksPerCu = 4;  // resident blocks of the pipelined column pass (LDS permitting)
+int g_cus = 256;                     // compute units of the device (set at grid creation)
 
 bool factor_plan(int L, FftPlan* pl) {
   pl->L = L;
@@ -342,9 +344,14 @@ void col_fast_launch(int mode, int pitch, int outer, hipStream_t s, T* W, T* H, 
   constexpr int PPW = col_ppw<T, L>();
   constexpr int NT = PB / PPW * fast::FftShape<L>::LP;
   dim3 grid(pitch / (2 * PB), outer);
-  if (mode == COL_PLAIN)
-    hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_PLAIN>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
-  else if (mode == COL_STAGE_A)
+  if (mode == COL_PLAIN) {
+    const int ntx = pitch / (2 * PB);
+    const int ntiles = ntx * outer;
+    constexpr int lds = PB * fast::FftShape<L>::BUF * int(sizeof(Cx<T>));
+    constexpr int per_cu = std::max(1, std::min(kPipeBlocksPerCu, 160 * 1024 / lds));
+    const int nblk = std::min(ntiles, g_cus * per_cu);
+    hipLaunchKernelGGL((fast::col_pipe<T, L, PB, PPW>), dim3(nblk), dim3(NT), 0, s, W, cg, tw, ntx, ntiles);
+  } else if (mode == COL_STAGE_A)
     hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_STAGE_A>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
   else if (mode == COL_STAGE_B)
     hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_STAGE_B>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
@@ -626,6 +633,8 @@ int eife_create_grid(int d, const int32_t* N, const double* h, double D, int bc,
   int maxlds = 65536;
   if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
   g->max_lds = size_t(maxlds);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) g_cus = cus;
   // launch shapes
   g->prow = pick_pairs(g, g->plan[0].L, std::min(16, (g->nlines_total() + 1) / 2));
   for (int a = 1; a < 3; ++a) {

@@ -89,7 +89,9 @@ struct FftShape {
   static constexpr int E = (L <= 512) ? 8 : 16;  // complex values per lane
   static constexpr int LP = L / E;                // lanes per line pair
   static constexpr int R2 = L / (E * E);          // radix of the third stage
-  static constexpr int BUF = L + L / 8 + 4;       // pair region: padded exchange buffer + bank offset
+  // pair region: padded exchange buffer, stride = 2 (mod 64) complex so that
+  // the column-tile accesses (16 pairs x rows) are free of LDS bank conflicts
+  static constexpr int BUF = ((L + L / 8 + 63) / 64) * 64 + 2;
   static constexpr int NB2 = E / R2;              // third-stage butterflies per lane
   static_assert(LP <= 64, "a line pair must fit in one wavefront");
   static_assert(R2 >= 2 && R2 <= E, "unsupported FFT length");
@@ -305,15 +307,17 @@ __global__ void __launch_bounds__(PB * FftShape<L>::LP, 4) row_fast(const T* src
   T* db = dst + int64_t(rb) * g.ld_dst + lane;
   T* da2 = dst2 + int64_t(ra) * g.ld_dst + lane;
   T* db2 = dst2 + int64_t(rb) * g.ld_dst + lane;
+  Cx<T> outv[RIT];
+#pragma unroll
+  for (int t = 0; t < RIT; ++t) outv[t] = my[lane + LP * t];  // full b64 reads (slot n..N-1 is scratch)
 #pragma unroll
   for (int t = 0; t < RIT; ++t) {
     if (lane + LP * t < n) {
-      const Cx<T> c = my[lane + LP * t];
-      if (hasa) da[LP * t] = c.re;
-      if (hasb) db[LP * t] = c.im;
+      if (hasa) da[LP * t] = outv[t].re;
+      if (hasb) db[LP * t] = outv[t].im;
       if (MODE == ROW_FWD_USER) {
-        if (hasa) da2[LP * t] = c.re;
-        if (hasb) db2[LP * t] = c.im;
+        if (hasa) da2[LP * t] = outv[t].re;
+        if (hasb) db2[LP * t] = outv[t].im;
       }
     }
   }
@@ -461,6 +465,76 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* __r
 #pragma unroll
   for (int it = 0; it < CIT; ++it)
     if (m0 + MS * it < n) gdst[(MS * it * ldl) / 2] = ltile[MS * it];
+}
+
+// ---------------------------------------------------------------------------
+// Persistent, software-pipelined plain column pass: each block walks tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's loads are issued
+// into registers before the current tile is transformed, so the memory
+// latency hides behind the FFTs.  Tile t covers columns (t % ntx) * C ... and
+// outer index t / ntx.
+template <typename T, int L, int PB, int PPW>
+__global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_pipe(T* __restrict__ W, ColGeom g,
+                                                                        const Cx<T>* tw, int ntx, int ntiles) {
+  constexpr int N = L / 2;
+  constexpr int n = N - 1;
+  constexpr int LP = FftShape<L>::LP;
+  constexpr int E = FftShape<L>::E;
+  constexpr int BUF = FftShape<L>::BUF;
+  constexpr int SLOTS = PB / PPW;
+  constexpr int NT = SLOTS * LP;
+  constexpr int MS = NT / PB;
+  constexpr int CIT = (n + MS - 1) / MS;
+  __shared__ Cx<T> lds[PB * BUF];
+  const int tid = threadIdx.x;
+  const int slot = tid / LP;
+  const int lane = tid - slot * LP;
+  const int tq = tid % PB;
+  const int m0 = tid / PB;
+  const int ldl = int(g.ld_line);
+  const T scale = T(1.0 / sqrt(double(L)));
+  LaneTw<T, L> twl;
+  twl.load(tw, lane);
+  Cx<T>* ltile = lds + tq * BUF + m0;
+  auto tile_ptr = [&](int t) -> Cx<T>* {
+    const int tx = t % ntx;
+    const int outer = t / ntx;
+    return reinterpret_cast<Cx<T>*>(W + int64_t(outer) * g.ld_outer + tx * 2 * PB + m0 * ldl + 2 * tq);
+  };
+  Cx<T> pre[CIT];
+  int t = blockIdx.x;
+  if (t < ntiles) {
+    const Cx<T>* gp = tile_ptr(t);
+#pragma unroll
+    for (int it = 0; it < CIT; ++it)
+      if (m0 + MS * it < n) pre[it] = gp[(MS * it * ldl) / 2];
+  }
+  for (; t < ntiles; t += gridDim.x) {
+#pragma unroll
+    for (int it = 0; it < CIT; ++it)
+      if (m0 + MS * it < n) ltile[MS * it] = pre[it];
+    __syncthreads();
+    const int tn = t + gridDim.x;
+    if (tn < ntiles) {
+      const Cx<T>* gp = tile_ptr(tn);
+#pragma unroll
+      for (int it = 0; it < CIT; ++it)
+        if (m0 + MS * it < n) pre[it] = gp[(MS * it * ldl) / 2];
+    }
+    Cx<T> v[E];
+#pragma unroll 1
+    for (int r = 0; r < PPW; ++r) {
+      Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
+      odd_fft<T, L>(v, my, my, lane, twl);
+      for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+    }
+    __syncthreads();
+    Cx<T>* gd = tile_ptr(t);
+#pragma unroll
+    for (int it = 0; it < CIT; ++it)
+      if (m0 + MS * it < n) gd[(MS * it * ldl) / 2] = ltile[MS * it];
+    __syncthreads();
+  }
 }
 
 }  // namespace fast
