@@ -41,6 +41,26 @@ BYTES_PER_DOF = {"row_phys": 8, "mid": 8, "last_a": 16, "last_b": 16, "row_fwd":
                  "last_plain": 8}
 
 
+def measured_traffic(pass_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None.
+
+    The record is only used while the kernel sources are byte-identical to the
+    ones the counters were taken on (sha256 over the two kernel headers).
+    """
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "traffic_255cubed_f32.json")
+    csrc = os.path.join(ROOT, "paper_2209_11922_amd", "csrc")
+    try:
+        rec = json.load(open(rec_path))
+        src = open(os.path.join(csrc, "eife_fast.hpp"), "rb").read() + \
+            open(os.path.join(csrc, "eife_kernels.hpp"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec.get("bytes_per_launch", {}).get(pass_name)
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -91,12 +111,13 @@ def main():
     log(f"bench: 3D Allen-Cahn {N_INT - 1}^3 FP32 EIFE2 tau={TAU} warmup={args.warmup} steps={args.steps}")
 
     if args.copy_calib:
+        # one elementwise kernel that reads and writes ndof floats once each
         a = torch.ones(ndof, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
-        log(f"bench: calibration copy of {ndof * 4} bytes x3")
+        log(f"bench: calibration copy (torch.mul) reading and writing {ndof * 4} bytes, x3")
         del a, b
     g = eife.Grid(N, h, D, "f32")
     g.set_phi(TAU, 2)
@@ -135,7 +156,7 @@ def main():
     log(f"  profiled step {prof_step_ms:.3f} ms; whole-step algorithmic bandwidth "
         f"{step_bytes / (dt / args.steps) / 1e9:.1f} GB/s")
     roof = {"bound": "hbm", "achieved": round(dom[4], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dom[4] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom[1],
+            "frac": round(dom[4] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom[1]), "kernel": dom[1],
             "kernel_avg_us": round(dom[3] * 1e3, 2),
             "bytes_per_launch": BYTES_PER_DOF[dom[1]] * ndof,
             "step_achieved_GBs": round(step_bytes / (dt / args.steps) / 1e9, 1)}
