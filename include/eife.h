@@ -165,6 +165,50 @@ int eife_profile(eife_grid g, int on);
  * (launches[EIFE_PASS_COUNT]) since eife_profile.  Blocks the host. */
 int eife_profile_read(eife_grid g, double* ms, int64_t* launches);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent 2D problems advanced together.  Instance i is a
+ * grid of N[2i] x N[2i+1] intervals with mesh widths h[2i], h[2i+1] and
+ * diffusion D[i] (same conventions as eife_create_grid with d = 2).  The
+ * nodal arrays of all instances lie back to back, in instance order, in one
+ * device buffer of the batch dtype; eife_batch_offsets gives where each
+ * starts.  Instances with equal (N, h) form a size class: each pass of a
+ * step is one launch per class covering all of its instances.
+ * ---------------------------------------------------------------------- */
+typedef struct eife_batch_s* eife_batch;
+
+/* Create a batch of B >= 1 instances.  Errors as eife_create_grid. */
+int eife_create_batch(int B, const int32_t* N, const double* h, const double* D, int dtype, eife_batch* out);
+
+/* Release the batch (see eife_destroy_grid for the stream caveat). */
+int eife_destroy_batch(eife_batch b);
+
+/* Element offsets of the instances in the batched nodal array:
+ * offsets[0..B], offsets[B] = total element count. */
+int eife_batch_offsets(eife_batch b, int64_t* offsets);
+
+/* eife_set_phi for every instance (same tau and stages for all). */
+int eife_batch_set_phi(eife_batch b, double tau, int stages);
+
+/* Advance every instance by n_steps steps (as eife_step, same f_kind and t0).
+ * With a non-null stream the whole sequence of launches is captured once
+ * into a HIP graph and replayed: a later call with the same u, n_steps,
+ * f_kind and t0 replays the cached graph.  Asynchronous on `stream`. */
+int eife_batch_step(eife_batch b, void* u, int64_t n_steps, int f_kind, double t0, void* stream);
+
+/* Choose, per size class, the launch shapes of the passes by timing the
+ * candidates on the device (eife_batch_set_phi must come first).  With a
+ * non-null cache_path, choices recorded there for this device, dtype and
+ * class are reused, and new ones are added to the file (JSON).  Blocks the
+ * host.  The timing runs leave the batch's internal state undefined; the
+ * next eife_batch_step starts from u as always. */
+int eife_batch_autotune(eife_batch b, const char* cache_path, void* stream);
+
+/* Launch shape chosen for size class k (order of first appearance):
+ * out[0] = class N_x, out[1] = N_y, out[2] = instances, out[3] = row-pass
+ * variant, out[4] = column-pass variant.  Returns EIFE_EINVAL past the last
+ * class. */
+int eife_batch_class_info(eife_batch b, int k, int32_t* out);
+
 /* Number of interior nodes of the grid (elements of a nodal array). */
 int eife_grid_size(eife_grid g, int64_t* count);
 

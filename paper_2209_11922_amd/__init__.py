@@ -6,6 +6,7 @@ PyTorch only for device memory and streams.  There is no fallback: without
 the built library every entry point raises.
 """
 from .binding import (  # noqa: F401
+    Batch,
     EIFEError,
     Grid,
     LOAD_LUMPED,

@@ -55,12 +55,22 @@ def load_library():
     lib.eife_grid_size.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_int64)]
     lib.eife_profile.argtypes = [c_void_p, c_int]
     lib.eife_profile_read.argtypes = [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.eife_create_batch.argtypes = [c_int, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(c_double),
+                                      ctypes.POINTER(c_double), c_int, ctypes.POINTER(c_void_p)]
+    lib.eife_destroy_batch.argtypes = [c_void_p]
+    lib.eife_batch_offsets.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_int64)]
+    lib.eife_batch_set_phi.argtypes = [c_void_p, c_double, c_int]
+    lib.eife_batch_step.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_int, c_double, c_void_p]
+    lib.eife_batch_autotune.argtypes = [c_void_p, ctypes.c_char_p, c_void_p]
+    lib.eife_batch_class_info.argtypes = [c_void_p, c_int, ctypes.POINTER(ctypes.c_int32)]
     lib.eife_last_error.restype = ctypes.c_char_p
     lib.eife_last_error.argtypes = []
     lib.eife_version.argtypes = []
     for name in ("eife_create_grid", "eife_destroy_grid", "eife_set_phi", "eife_set_c2", "eife_set_origin",
                  "eife_set_load", "eife_set_forcing", "eife_step", "eife_norms", "eife_grid_size",
-                 "eife_version", "eife_profile", "eife_profile_read", "eife_set_transform"):
+                 "eife_version", "eife_profile", "eife_profile_read", "eife_set_transform", "eife_create_batch",
+                 "eife_destroy_batch", "eife_batch_offsets", "eife_batch_set_phi", "eife_batch_step",
+                 "eife_batch_autotune", "eife_batch_class_info"):
         getattr(lib, name).restype = c_int
     _LIB = lib
     return lib
@@ -171,3 +181,70 @@ class Grid:
         code = self._lib.eife_norms(self._g, ctypes.c_void_p(u.data_ptr()), ref, out, _stream_ptr(stream))
         _check(self._lib, code)
         return tuple(out)
+
+
+class Batch:
+    """Independent 2D instances advanced together (eife_create_batch ... eife_batch_step).
+
+    grids: list of (Nx, Ny, hx, hy, D).  The batched nodal array is one
+    contiguous 1-D tensor; `offsets` says where instance i starts.
+    """
+
+    def __init__(self, grids, dtype="f32"):
+        self._lib = load_library()
+        self.B = len(grids)
+        self.dtype_code, self.torch_dtype = _DTYPES[dtype]
+        N = (ctypes.c_int32 * (2 * self.B))(*[int(v) for g in grids for v in g[:2]])
+        h = (ctypes.c_double * (2 * self.B))(*[float(v) for g in grids for v in g[2:4]])
+        D = (ctypes.c_double * self.B)(*[float(g[4]) for g in grids])
+        handle = ctypes.c_void_p()
+        _check(self._lib, self._lib.eife_create_batch(self.B, N, h, D, self.dtype_code, ctypes.byref(handle)))
+        self._b = handle
+        off = (ctypes.c_int64 * (self.B + 1))()
+        _check(self._lib, self._lib.eife_batch_offsets(self._b, off))
+        self.offsets = list(off)
+        self.shapes = [(int(g[1]) - 1, int(g[0]) - 1) for g in grids]
+
+    def close(self):
+        if getattr(self, "_b", None):
+            self._lib.eife_destroy_batch(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def size(self):
+        return self.offsets[-1]
+
+    def set_phi(self, tau, stages):
+        _check(self._lib, self._lib.eife_batch_set_phi(self._b, float(tau), int(stages)))
+
+    def autotune(self, cache_path=None, stream=None):
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(self._lib, self._lib.eife_batch_autotune(self._b, path, _stream_ptr(stream)))
+
+    def class_info(self):
+        out, k = [], 0
+        buf = (ctypes.c_int32 * 5)()
+        while self._lib.eife_batch_class_info(self._b, k, buf) == OK:
+            out.append(tuple(buf))
+            k += 1
+        return out
+
+    def step(self, u, n_steps, f_kind, t0=0.0, stream=None, graph=True):
+        """Advance every instance in place; graph=False enqueues on the null stream (no capture)."""
+        if not isinstance(u, torch.Tensor) or not u.is_cuda or u.dtype != self.torch_dtype:
+            raise TypeError("u must be a CUDA tensor of the batch dtype")
+        if not u.is_contiguous() or u.numel() != self.size():
+            raise ValueError(f"u must be contiguous with {self.size()} elements")
+        sp = _stream_ptr(stream) if graph else ctypes.c_void_p(0)
+        _check(self._lib, self._lib.eife_batch_step(self._b, ctypes.c_void_p(u.data_ptr()), int(n_steps),
+                                                    int(f_kind), float(t0), sp))
+        return u
+
+    def views(self, u):
+        """Per-instance 2D views of a batched nodal array."""
+        return [u[self.offsets[i]:self.offsets[i + 1]].view(self.shapes[i]) for i in range(self.B)]

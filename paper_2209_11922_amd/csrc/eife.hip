@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -235,25 +236,25 @@ Forcing make_forcing(const eife_grid_s* g, int kind, double t) {
   return F;
 }
 
+template <typename T, bool BAT>
+int set_lds_attrs_v(int b) {
+  const void* fns[] = {reinterpret_cast<const void*>(&row_pass<T, ROW_PHYS, BAT>),
+                       reinterpret_cast<const void*>(&row_pass<T, ROW_FWD_USER, BAT>),
+                       reinterpret_cast<const void*>(&row_pass<T, ROW_INV_USER, BAT>),
+                       reinterpret_cast<const void*>(&col_pass<T, COL_PLAIN, BAT>),
+                       reinterpret_cast<const void*>(&col_pass<T, COL_STAGE_A, BAT>),
+                       reinterpret_cast<const void*>(&col_pass<T, COL_STAGE_B, BAT>),
+                       reinterpret_cast<const void*>(&col_pass<T, COL_ETD1, BAT>)};
+  for (const void* f : fns) HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b));
+  return EIFE_OK;
+}
+
 template <typename T>
 int set_lds_attrs(size_t bytes) {
   if (bytes <= 65536) return EIFE_OK;
-  const int b = int(bytes);
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&row_pass<T, ROW_PHYS>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, b));
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&row_pass<T, ROW_FWD_USER>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, b));
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&row_pass<T, ROW_INV_USER>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, b));
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&col_pass<T, COL_PLAIN>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, b));
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&col_pass<T, COL_STAGE_A>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, b));
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&col_pass<T, COL_STAGE_B>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, b));
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&col_pass<T, COL_ETD1>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, b));
-  return EIFE_OK;
+  const int r = set_lds_attrs_v<T, false>(int(bytes));
+  if (r != EIFE_OK) return r;
+  return set_lds_attrs_v<T, true>(int(bytes));
 }
 
 hipEvent_t take_event(eife_grid_s* g) {
@@ -296,98 +297,168 @@ int prof_collect(eife_grid_s* g) {
   return EIFE_OK;
 }
 
-// Line pairs per block of the fast passes (LDS <= 64 KB, 64-byte column segments).
+// ---------------------------------------------------------------------------
+// Launch layer.  Every pass launch may cover several instances of one size
+// class (a batch): `count` instances, per-instance pointers and tables in
+// the device tables `rinst` / `cinst` (null for a single grid).  `var`
+// selects a launch shape (pairs per block) among the tuned variants.
+
+// Row passes, specialised kernels: pairs per block (variant 0 / 1).
 template <typename T, int L>
-constexpr int fast_pb() {
-  return sizeof(T) == 4 ? (L == 128 ? 16 : (L == 1024 ? 4 : 8)) : (L == 128 ? 8 : (L == 1024 ? 2 : 4));
+constexpr int row_pb(int var) {
+  return var == 0 ? (sizeof(T) == 4 ? (L == 128 ? 16 : (L == 1024 ? 4 : 8)) : (L == 128 ? 8 : (L == 1024 ? 2 : 4)))
+                  : (sizeof(T) == 4 ? (L == 128 ? 8 : (L == 1024 ? 2 : 4)) : (L == 128 ? 4 : (L == 1024 ? 1 : 2)));
+}
+
+// Column passes, specialised kernels: variant 0 uses 128-byte row segments
+// (32 FP32 / 16 FP64 columns), variant 1 64-byte segments.
+template <typename T, int L>
+constexpr int col_pb(int var) {
+  return var == 0 ? ((L >= 1024) ? (sizeof(T) == 4 ? 8 : 4) : (sizeof(T) == 4 ? 16 : 8))
+                  : ((L >= 1024) ? (sizeof(T) == 4 ? 4 : 2) : (sizeof(T) == 4 ? 8 : 4));
+}
+template <typename T, int L, int PB>
+constexpr int col_ppw() {
+  return (PB * fast::FftShape<L>::LP > 512) ? PB * fast::FftShape<L>::LP / 512 : 1;
 }
 
 bool fast_len(int N) { return N == 64 || N == 128 || N == 256 || N == 512; }
 
-template <typename T, int L>
-void row_fast_launch(int mode, int nrows, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
-                     const Cx<T>* tw, const Forcing& F) {
-  constexpr int PB = fast_pb<T, L>();
+template <typename T, int L, int PB, bool BAT>
+void row_fast_go(int mode, int nrows, int count, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
+                 const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
   constexpr int NT = PB * fast::FftShape<L>::LP;
-  dim3 grid((nrows + 2 * PB - 1) / (2 * PB));
+  dim3 grid((nrows + 2 * PB - 1) / (2 * PB), count);
   if (mode == ROW_PHYS) {
     if (F.kind == FK_AC)
-      hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_PHYS, fast::RK_AC>), grid, dim3(NT), 0, s, src, dst, dst2,
-                         rg, tw, F);
+      hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_PHYS, fast::RK_AC, BAT>), grid, dim3(NT), 0, s, src, dst,
+                         dst2, rg, tw, F, ri);
     else
-      hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_PHYS, fast::RK_GENERIC>), grid, dim3(NT), 0, s, src, dst,
-                         dst2, rg, tw, F);
+      hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_PHYS, fast::RK_GENERIC, BAT>), grid, dim3(NT), 0, s, src,
+                         dst, dst2, rg, tw, F, ri);
   } else if (mode == ROW_FWD_USER) {
-    hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_FWD_USER, fast::RK_GENERIC>), grid, dim3(NT), 0, s, src, dst,
-                       dst2, rg, tw, F);
+    hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_FWD_USER, fast::RK_GENERIC, BAT>), grid, dim3(NT), 0, s, src,
+                       dst, dst2, rg, tw, F, ri);
   } else {
-    hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_INV_USER, fast::RK_GENERIC>), grid, dim3(NT), 0, s, src, dst,
-                       dst2, rg, tw, F);
+    hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_INV_USER, fast::RK_GENERIC, BAT>), grid, dim3(NT), 0, s, src,
+                       dst, dst2, rg, tw, F, ri);
   }
 }
 
-// Column passes: 128-byte row segments (32 FP32 / 16 FP64 columns); pairs per
-// wavefront slice chosen so a block has at most 512 threads.
 template <typename T, int L>
-constexpr int col_pb() {
-  return (L >= 1024) ? (sizeof(T) == 4 ? 8 : 4) : (sizeof(T) == 4 ? 16 : 8);
+void row_fast_launch(int var, int mode, int nrows, int count, hipStream_t s, const T* src, T* dst, T* dst2,
+                     const RowGeom& rg, const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
+  if (ri) {
+    if (var == 0)
+      row_fast_go<T, L, row_pb<T, L>(0), true>(mode, nrows, count, s, src, dst, dst2, rg, tw, F, ri);
+    else
+      row_fast_go<T, L, row_pb<T, L>(1), true>(mode, nrows, count, s, src, dst, dst2, rg, tw, F, ri);
+  } else {
+    row_fast_go<T, L, row_pb<T, L>(0), false>(mode, nrows, count, s, src, dst, dst2, rg, tw, F, ri);
+  }
 }
-template <typename T, int L>
-constexpr int col_ppw() {
-  return (col_pb<T, L>() * fast::FftShape<L>::LP > 512) ? col_pb<T, L>() * fast::FftShape<L>::LP / 512 : 1;
+
+template <typename T, int L, int PB, bool BAT>
+void col_fast_go(int mode, int pitch, int outer, int count, bool pipe, hipStream_t s, T* W, T* H, const ColGeom& cg,
+                 const Cx<T>* tw, const Diag& dg, const ColInst<T>* ci) {
+  constexpr int PPW = col_ppw<T, L, PB>();
+  constexpr int NT = PB / PPW * fast::FftShape<L>::LP;
+  dim3 grid(pitch / (2 * PB), outer, count);
+  if (mode == COL_PLAIN) {
+    if (pipe && !ci) {
+      const int ntx = pitch / (2 * PB);
+      const int ntiles = ntx * outer;
+      constexpr int lds = PB * fast::FftShape<L>::BUF * int(sizeof(Cx<T>));
+      constexpr int per_cu = std::max(1, std::min(kPipeBlocksPerCu, 160 * 1024 / lds));
+      const int nblk = std::min(ntiles, g_cus * per_cu);
+      hipLaunchKernelGGL((fast::col_pipe<T, L, PB, PPW>), dim3(nblk), dim3(NT), 0, s, W, cg, tw, ntx, ntiles);
+    } else {
+      hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_PLAIN, BAT>), grid, dim3(NT), 0, s, W, H, cg, tw, dg, ci);
+    }
+  } else if (mode == COL_STAGE_A) {
+    hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_STAGE_A, BAT>), grid, dim3(NT), 0, s, W, H, cg, tw, dg, ci);
+  } else if (mode == COL_STAGE_B) {
+    hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_STAGE_B, BAT>), grid, dim3(NT), 0, s, W, H, cg, tw, dg, ci);
+  } else {
+    hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_ETD1, BAT>), grid, dim3(NT), 0, s, W, H, cg, tw, dg, ci);
+  }
 }
 
 template <typename T, int L>
-void col_fast_launch(int mode, int pitch, int outer, hipStream_t s, T* W, T* H, const ColGeom& cg,
-                     const Cx<T>* tw, const Diag& dg) {
-  constexpr int PB = col_pb<T, L>();
-  constexpr int PPW = col_ppw<T, L>();
-  constexpr int NT = PB / PPW * fast::FftShape<L>::LP;
-  dim3 grid(pitch / (2 * PB), outer);
-  if (mode == COL_PLAIN) {
-    const int ntx = pitch / (2 * PB);
-    const int ntiles = ntx * outer;
-    constexpr int lds = PB * fast::FftShape<L>::BUF * int(sizeof(Cx<T>));
-    constexpr int per_cu = std::max(1, std::min(kPipeBlocksPerCu, 160 * 1024 / lds));
-    const int nblk = std::min(ntiles, g_cus * per_cu);
-    hipLaunchKernelGGL((fast::col_pipe<T, L, PB, PPW>), dim3(nblk), dim3(NT), 0, s, W, cg, tw, ntx, ntiles);
-  } else if (mode == COL_STAGE_A)
-    hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_STAGE_A>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
-  else if (mode == COL_STAGE_B)
-    hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_STAGE_B>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
-  else
-    hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_ETD1>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+void col_fast_launch(int var, int mode, int pitch, int outer, int count, hipStream_t s, T* W, T* H,
+                     const ColGeom& cg, const Cx<T>* tw, const Diag& dg, const ColInst<T>* ci) {
+  if (ci) {
+    if (var == 0)
+      col_fast_go<T, L, col_pb<T, L>(0), true>(mode, pitch, outer, count, false, s, W, H, cg, tw, dg, ci);
+    else
+      col_fast_go<T, L, col_pb<T, L>(1), true>(mode, pitch, outer, count, false, s, W, H, cg, tw, dg, ci);
+  } else {
+    col_fast_go<T, L, col_pb<T, L>(0), false>(mode, pitch, outer, count, true, s, W, H, cg, tw, dg, ci);
+  }
 }
 
 template <typename T>
-bool try_row_fast(const eife_grid_s* g, int mode, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
-                  const Cx<T>* tw, const Forcing& F) {
+bool try_row_fast(const eife_grid_s* g, int var, int mode, int count, hipStream_t s, const T* src, T* dst, T* dst2,
+                  const RowGeom& rg, const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
   if (g->transform != EIFE_TX_FFT || !fast_len(g->N[0])) return false;
   switch (g->N[0]) {
-    case 64: row_fast_launch<T, 128>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F); return true;
-    case 128: row_fast_launch<T, 256>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F); return true;
-    case 256: row_fast_launch<T, 512>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F); return true;
-    case 512: row_fast_launch<T, 1024>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F); return true;
+    case 64: row_fast_launch<T, 128>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
+    case 128: row_fast_launch<T, 256>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
+    case 256: row_fast_launch<T, 512>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
+    case 512: row_fast_launch<T, 1024>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
   }
   return false;
 }
 
 template <typename T>
-bool try_col_fast(const eife_grid_s* g, int axis, int mode, int outer, hipStream_t s, T* W, T* H,
-                  const ColGeom& cg, const Cx<T>* tw, const Diag& dg) {
+bool try_col_fast(const eife_grid_s* g, int var, int axis, int mode, int outer, int count, hipStream_t s, T* W, T* H,
+                  const ColGeom& cg, const Cx<T>* tw, const Diag& dg, const ColInst<T>* ci) {
   if (g->transform != EIFE_TX_FFT || !fast_len(g->N[axis])) return false;
   switch (g->N[axis]) {
-    case 64: col_fast_launch<T, 128>(mode, g->pitch, outer, s, W, H, cg, tw, dg); return true;
-    case 128: col_fast_launch<T, 256>(mode, g->pitch, outer, s, W, H, cg, tw, dg); return true;
-    case 256: col_fast_launch<T, 512>(mode, g->pitch, outer, s, W, H, cg, tw, dg); return true;
-    case 512: col_fast_launch<T, 1024>(mode, g->pitch, outer, s, W, H, cg, tw, dg); return true;
+    case 64: col_fast_launch<T, 128>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
+    case 128: col_fast_launch<T, 256>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
+    case 256: col_fast_launch<T, 512>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
+    case 512: col_fast_launch<T, 1024>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
   }
   return false;
 }
+
+template <typename T, bool BATR>
+void row_generic_go(int mode, dim3 grid, size_t shm, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
+                    const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
+  if (mode == ROW_PHYS)
+    hipLaunchKernelGGL((row_pass<T, ROW_PHYS, BATR>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F, ri);
+  else if (mode == ROW_FWD_USER)
+    hipLaunchKernelGGL((row_pass<T, ROW_FWD_USER, BATR>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F, ri);
+  else
+    hipLaunchKernelGGL((row_pass<T, ROW_INV_USER, BATR>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F, ri);
+}
+
+template <typename T, bool BATC>
+void col_generic_go(int mode, dim3 grid, size_t shm, hipStream_t s, T* W, T* H, const ColGeom& cg, const Cx<T>* tw,
+                    const Diag& dg, const ColInst<T>* ci) {
+  if (mode == COL_PLAIN)
+    hipLaunchKernelGGL((col_pass<T, COL_PLAIN, BATC>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+  else if (mode == COL_STAGE_A)
+    hipLaunchKernelGGL((col_pass<T, COL_STAGE_A, BATC>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+  else if (mode == COL_STAGE_B)
+    hipLaunchKernelGGL((col_pass<T, COL_STAGE_B, BATC>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+  else
+    hipLaunchKernelGGL((col_pass<T, COL_ETD1, BATC>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+}
+
+// A launch of one pass over `count` instances shaped like grid `g`.
+struct Batchlet {
+  int count = 1;
+  const void* rinst = nullptr;  // RowInst<T>[count] (device) or null
+  const void* cinst = nullptr;  // ColInst<T>[count] (device) or null
+  int var_row = 0, var_col = 0;  // tuned launch variants
+  int prow = 0, pcol = 0;        // generic-kernel pairs per block (0 = the grid's default)
+};
 
 template <typename T>
 int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, int64_t ld_dst, T* dst2,
-               const Forcing& F, hipStream_t s) {
+               const Forcing& F, hipStream_t s, const Batchlet& B = Batchlet()) {
   RowGeom rg;
   rg.n = g->n[0];
   rg.nrows = g->nlines_total();
@@ -395,37 +466,29 @@ int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, i
   rg.ld_src = ld_src;
   rg.ld_dst = ld_dst;
   rg.pl = g->plan[0];
-  rg.P = g->prow;
+  rg.P = B.prow > 0 ? B.prow : g->prow;
   rg.ls = rg.pl.L + 1;
-  const size_t shm = lds_bytes(g, rg.P, rg.pl.L);
-  dim3 grid((rg.nrows + 2 * rg.P - 1) / (2 * rg.P));
+  const RowInst<T>* ri = static_cast<const RowInst<T>*>(B.rinst);
   const Cx<T>* tw = reinterpret_cast<const Cx<T>*>(g->tw[0]);
   const int pidx = prof_begin(g, mode == ROW_PHYS ? EIFE_PASS_ROW_PHYS
                                  : mode == ROW_FWD_USER ? EIFE_PASS_ROW_FWD : EIFE_PASS_ROW_INV, s);
-  if (try_row_fast<T>(g, mode, s, src, dst, dst2, rg, tw, F)) {
-    HIP_TRY(hipGetLastError());
-    prof_end(g, pidx, s);
-    return EIFE_OK;
-  }
-  switch (mode) {
-    case ROW_PHYS:
-      hipLaunchKernelGGL((row_pass<T, ROW_PHYS>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F);
-      break;
-    case ROW_FWD_USER:
-      hipLaunchKernelGGL((row_pass<T, ROW_FWD_USER>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F);
-      break;
-    default:
-      hipLaunchKernelGGL((row_pass<T, ROW_INV_USER>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F);
-      break;
+  if (!try_row_fast<T>(g, B.var_row, mode, B.count, s, src, dst, dst2, rg, tw, F, ri)) {
+    const size_t shm = lds_bytes(g, rg.P, rg.pl.L);
+    dim3 grid((rg.nrows + 2 * rg.P - 1) / (2 * rg.P), B.count);
+    if (ri)
+      row_generic_go<T, true>(mode, grid, shm, s, src, dst, dst2, rg, tw, F, ri);
+    else
+      row_generic_go<T, false>(mode, grid, shm, s, src, dst, dst2, rg, tw, F, ri);
   }
   HIP_TRY(hipGetLastError());
   prof_end(g, pidx, s);
   return EIFE_OK;
 }
 
-// axis = 1 (y) or 2 (z); `last` selects the diagonal mode
+// axis = 1 (y) or 2 (z)
 template <typename T>
-int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, hipStream_t s) {
+int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, hipStream_t s,
+               const Batchlet& B = Batchlet()) {
   ColGeom cg;
   const int64_t pitch = g->pitch;
   int outer;
@@ -442,11 +505,12 @@ int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, h
     outer = g->n[1];
     cg.last_is_z = 1;
   }
+  cg.ncols = g->n[0];
   cg.pl = g->plan[axis];
-  cg.P = g->pcol[axis];
+  cg.P = B.pcol > 0 ? B.pcol : g->pcol[axis];
+  while (g->pitch % (2 * cg.P) != 0) cg.P--;
   cg.ls = cg.pl.L + 1;
-  const size_t shm = lds_bytes(g, cg.P, cg.pl.L);
-  dim3 grid(g->pitch / (2 * cg.P), outer);
+  const ColInst<T>* ci = static_cast<const ColInst<T>*>(B.cinst);
   const Cx<T>* tw = reinterpret_cast<const Cx<T>*>(g->tw[axis]);
   int kind = EIFE_PASS_MID;
   if (!(axis == 1 && g->d == 3)) {
@@ -455,24 +519,13 @@ int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, h
            : mode == COL_STAGE_B ? EIFE_PASS_LAST_B : EIFE_PASS_LAST_ETD1;
   }
   const int pidx = prof_begin(g, kind, s);
-  if (try_col_fast<T>(g, axis, mode, outer, s, W, H, cg, tw, dg)) {
-    HIP_TRY(hipGetLastError());
-    prof_end(g, pidx, s);
-    return EIFE_OK;
-  }
-  switch (mode) {
-    case COL_PLAIN:
-      hipLaunchKernelGGL((col_pass<T, COL_PLAIN>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
-      break;
-    case COL_STAGE_A:
-      hipLaunchKernelGGL((col_pass<T, COL_STAGE_A>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
-      break;
-    case COL_STAGE_B:
-      hipLaunchKernelGGL((col_pass<T, COL_STAGE_B>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
-      break;
-    default:
-      hipLaunchKernelGGL((col_pass<T, COL_ETD1>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
-      break;
+  if (!try_col_fast<T>(g, B.var_col, axis, mode, outer, B.count, s, W, H, cg, tw, dg, ci)) {
+    const size_t shm = lds_bytes(g, cg.P, cg.pl.L);
+    dim3 grid(g->pitch / (2 * cg.P), outer, B.count);
+    if (ci)
+      col_generic_go<T, true>(mode, grid, shm, s, W, H, cg, tw, dg, ci);
+    else
+      col_generic_go<T, false>(mode, grid, shm, s, W, H, cg, tw, dg, ci);
   }
   HIP_TRY(hipGetLastError());
   prof_end(g, pidx, s);
@@ -823,6 +876,382 @@ int eife_norms(eife_grid g, const void* u, const void* uref, double* out, void* 
   out[3] = 0.5 * g->D * r[3] + cellvol * r[4];
   for (int k = 0; k < 4; ++k)
     if (!std::isfinite(out[k])) return fail(EIFE_ENONFINITE, "norm %d is not finite", k);
+  return EIFE_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batches of independent 2D instances.
+// ===========================================================================
+struct eife_batch_s {
+  int B = 0;
+  int dtype = EIFE_F32;
+  std::vector<eife_grid_s*> inst;
+  std::vector<int64_t> uoff;  // B + 1 element offsets in the caller's array
+  struct Class {
+    std::vector<int> members;
+    void* rinst = nullptr;    // RowInst<T>[members]
+    void* cinst = nullptr;    // ColInst<T>[members], W -> H (stage passes)
+    void* cinst_h = nullptr;  // ColInst<T>[members] acting on H only (prologue)
+    int var_row = 0, var_col = 0;
+    int prow = 0, pcol = 0;
+  };
+  std::vector<Class> classes;
+  bool phi_ready = false;
+  int stages = 0;
+  // cached graph of the last captured step sequence
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  void* g_u = nullptr;
+  int64_t g_steps = -1;
+  int g_fkind = -1;
+  double g_t0 = 0.0;
+};
+
+namespace {
+
+template <typename T>
+int build_batch_tables(eife_batch_s* b) {
+  for (auto& c : b->classes) {
+    const size_t n = c.members.size();
+    std::vector<RowInst<T>> ri(n);
+    std::vector<ColInst<T>> ci(n), ch(n);
+    for (size_t k = 0; k < n; ++k) {
+      eife_grid_s* g = b->inst[c.members[k]];
+      ri[k].W = static_cast<T*>(g->W);
+      ri[k].H = static_cast<T*>(g->H);
+      ri[k].uoff = b->uoff[c.members[k]];
+      ri[k].D = g->D;
+      const Diag dg = make_diag(g);
+      for (int a = 0; a < 3; ++a) ci[k].ax[a] = dg.ax[a];
+      ci[k].W = static_cast<T*>(g->W);
+      ci[k].H = static_cast<T*>(g->H);
+      ci[k].D = g->D;
+      ch[k] = ci[k];
+      ch[k].W = static_cast<T*>(g->H);
+    }
+    if (hipMalloc(&c.rinst, n * sizeof(RowInst<T>)) != hipSuccess ||
+        hipMalloc(&c.cinst, n * sizeof(ColInst<T>)) != hipSuccess ||
+        hipMalloc(&c.cinst_h, n * sizeof(ColInst<T>)) != hipSuccess)
+      return fail(EIFE_ENOMEM, "batch descriptor allocation failed");
+    HIP_TRY(hipMemcpy(c.rinst, ri.data(), n * sizeof(RowInst<T>), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c.cinst, ci.data(), n * sizeof(ColInst<T>), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c.cinst_h, ch.data(), n * sizeof(ColInst<T>), hipMemcpyHostToDevice));
+  }
+  return EIFE_OK;
+}
+
+Batchlet class_batchlet(const eife_batch_s::Class& c, bool on_h) {
+  Batchlet B;
+  B.count = int(c.members.size());
+  B.rinst = c.rinst;
+  B.cinst = on_h ? c.cinst_h : c.cinst;
+  B.var_row = c.var_row;
+  B.var_col = c.var_col;
+  B.prow = c.prow;
+  B.pcol = c.pcol;
+  return B;
+}
+
+// One EIFE step (both stages) of class c at time tn.
+template <typename T>
+int class_step(eife_batch_s* b, const eife_batch_s::Class& c, int f_kind, double tn, hipStream_t s) {
+  eife_grid_s* g = b->inst[c.members[0]];
+  const Batchlet B = class_batchlet(c, false);
+  const Diag dg = make_diag(g);
+  RET_IF(launch_row<T>(g, ROW_PHYS, nullptr, g->pitch, nullptr, g->pitch, nullptr, make_forcing(g, f_kind, tn), s, B));
+  RET_IF(launch_col<T>(g, 1, g->stages == 1 ? COL_ETD1 : COL_STAGE_A, nullptr, nullptr, dg, s, B));
+  if (g->stages == 2) {
+    RET_IF(launch_row<T>(g, ROW_PHYS, nullptr, g->pitch, nullptr, g->pitch, nullptr,
+                         make_forcing(g, f_kind, tn + g->c2 * g->tau), s, B));
+    RET_IF(launch_col<T>(g, 1, COL_STAGE_B, nullptr, nullptr, dg, s, B));
+  }
+  return EIFE_OK;
+}
+
+template <typename T>
+int batch_enqueue(eife_batch_s* b, T* u, int64_t n_steps, int f_kind, double t0, hipStream_t s) {
+  for (auto& c : b->classes) {
+    eife_grid_s* g = b->inst[c.members[0]];
+    const Batchlet B = class_batchlet(c, false);
+    RET_IF(launch_row<T>(g, ROW_FWD_USER, u, g->n[0], nullptr, g->pitch, nullptr, make_forcing(g, f_kind, t0), s, B));
+    RET_IF(launch_col<T>(g, 1, COL_PLAIN, nullptr, nullptr, make_diag(g), s, class_batchlet(c, true)));
+  }
+  for (int64_t st = 0; st < n_steps; ++st) {
+    const double tn = t0 + double(st) * b->inst[0]->tau;
+    for (auto& c : b->classes) RET_IF(class_step<T>(b, c, f_kind, tn, s));
+  }
+  for (auto& c : b->classes) {
+    eife_grid_s* g = b->inst[c.members[0]];
+    const Batchlet B = class_batchlet(c, false);
+    RET_IF(launch_row<T>(g, ROW_INV_USER, nullptr, g->pitch, u, g->n[0], nullptr, make_forcing(g, f_kind, t0), s, B));
+  }
+  return EIFE_OK;
+}
+
+void drop_graph(eife_batch_s* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->g_steps = -1;
+}
+
+void free_batch(eife_batch_s* b) {
+  if (!b) return;
+  drop_graph(b);
+  for (auto& c : b->classes) {
+    (void)hipFree(c.rinst);
+    (void)hipFree(c.cinst);
+    (void)hipFree(c.cinst_h);
+  }
+  for (auto* g : b->inst) free_grid(g);
+  delete b;
+}
+
+// --- autotuning -------------------------------------------------------------
+std::string tune_key(const eife_batch_s* b, const eife_batch_s::Class& c) {
+  const eife_grid_s* g = b->inst[c.members[0]];
+  hipDeviceProp_t prop;
+  char arch[64] = "gfx";
+  if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+  for (char* p = arch; *p; ++p)
+    if (*p == ':') *p = '_';
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s/%s/N%dx%d/n%zu", arch, b->dtype == EIFE_F32 ? "f32" : "f64", g->N[0], g->N[1],
+           c.members.size());
+  return buf;
+}
+
+// Cache file: a JSON object with one "key": [var_row, var_col, prow, pcol, us] entry per line.
+bool tune_lookup(const char* path, const std::string& key, int v[4]) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    char k[256];
+    int a, b2, c, d;
+    double us;
+    if (sscanf(line, " \"%255[^\"]\" : [ %d , %d , %d , %d , %lf ]", k, &a, &b2, &c, &d, &us) == 6 && key == k) {
+      v[0] = a;
+      v[1] = b2;
+      v[2] = c;
+      v[3] = d;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void tune_store(const char* path, const std::string& key, const int v[4], double us) {
+  if (!path) return;
+  std::vector<std::string> entries;
+  FILE* f = fopen(path, "r");
+  if (f) {
+    char line[512];
+    while (fgets(line, sizeof(line), f)) {
+      char k[256];
+      if (sscanf(line, " \"%255[^\"]\"", k) == 1 && key != k) {
+        std::string l(line);
+        while (!l.empty() && (l.back() == '\n' || l.back() == ',' || l.back() == ' ')) l.pop_back();
+        entries.push_back(l);
+      }
+    }
+    fclose(f);
+  }
+  char buf[512];
+  snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %d, %.3f]", key.c_str(), v[0], v[1], v[2], v[3], us);
+  entries.push_back(buf);
+  f = fopen(path, "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  for (size_t i = 0; i < entries.size(); ++i) fprintf(f, "%s%s\n", entries[i].c_str(), i + 1 < entries.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+}
+
+template <typename T>
+int tune_class(eife_batch_s* b, eife_batch_s::Class& c, const char* path, hipStream_t s) {
+  const std::string key = tune_key(b, c);
+  int v[4];
+  if (tune_lookup(path, key, v)) {
+    c.var_row = v[0];
+    c.var_col = v[1];
+    c.prow = v[2];
+    c.pcol = v[3];
+    return EIFE_OK;
+  }
+  eife_grid_s* g = b->inst[c.members[0]];
+  const bool fast = g->transform == EIFE_TX_FFT && fast_len(g->N[0]) && fast_len(g->N[1]);
+  std::vector<std::array<int, 4>> cands;
+  if (fast) {
+    for (int r = 0; r < 2; ++r)
+      for (int cc = 0; cc < 2; ++cc) cands.push_back({r, cc, 0, 0});
+  } else {
+    for (int pr : {4, 8, 16})
+      for (int pc : {4, 8, 16}) cands.push_back({0, 0, pr, pc});
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double best = 1e30;
+  std::array<int, 4> bestc = cands[0];
+  for (const auto& cd : cands) {
+    c.var_row = cd[0];
+    c.var_col = cd[1];
+    c.prow = cd[2];
+    c.pcol = cd[3];
+    if (!fast && (pick_pairs(g, g->plan[0].L, c.prow) != c.prow || pick_pairs(g, g->plan[1].L, c.pcol) != c.pcol ||
+                  lds_bytes(g, c.prow, g->plan[0].L) > 65536 || lds_bytes(g, c.pcol, g->plan[1].L) > 65536 ||
+                  g->pitch % (2 * c.pcol) != 0))
+      continue;  // shape does not fit this line length
+    RET_IF(class_step<T>(b, c, EIFE_F_ALLEN_CAHN, 0.0, s));  // warm
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < 3; ++r) RET_IF(class_step<T>(b, c, EIFE_F_ALLEN_CAHN, 0.0, s));
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      bestc = cd;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c.var_row = bestc[0];
+  c.var_col = bestc[1];
+  c.prow = bestc[2];
+  c.pcol = bestc[3];
+  const int vv[4] = {bestc[0], bestc[1], bestc[2], bestc[3]};
+  tune_store(path, key, vv, best * 1e3 / 3.0);
+  return EIFE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int eife_create_batch(int B, const int32_t* N, const double* h, const double* D, int dtype, eife_batch* out) {
+  if (!out) return fail(EIFE_EINVAL, "out is null");
+  *out = nullptr;
+  if (B < 1 || !N || !h || !D) return fail(EIFE_EINVAL, "B must be >= 1 and N, h, D non-null");
+  eife_batch_s* b = new eife_batch_s();
+  b->B = B;
+  b->dtype = dtype;
+  b->uoff.assign(B + 1, 0);
+  for (int i = 0; i < B; ++i) {
+    eife_grid g = nullptr;
+    const int r = eife_create_grid(2, N + 2 * i, h + 2 * i, D[i], EIFE_BC_DIRICHLET, dtype, &g);
+    if (r != EIFE_OK) {
+      const std::string msg = g_last_error;
+      free_batch(b);
+      return fail(r, "instance %d: %s", i, msg.c_str());
+    }
+    b->inst.push_back(g);
+    b->uoff[i + 1] = b->uoff[i] + int64_t(g->n[0]) * g->n[1];
+    // size class: equal N and h
+    int found = -1;
+    for (size_t k = 0; k < b->classes.size(); ++k) {
+      const eife_grid_s* r0 = b->inst[b->classes[k].members[0]];
+      if (r0->N[0] == g->N[0] && r0->N[1] == g->N[1] && r0->h[0] == g->h[0] && r0->h[1] == g->h[1]) found = int(k);
+    }
+    if (found < 0) {
+      b->classes.emplace_back();
+      found = int(b->classes.size()) - 1;
+    }
+    b->classes[found].members.push_back(i);
+  }
+  const int r = dtype == EIFE_F32 ? build_batch_tables<float>(b) : build_batch_tables<double>(b);
+  if (r != EIFE_OK) {
+    free_batch(b);
+    return r;
+  }
+  *out = b;
+  return EIFE_OK;
+}
+
+int eife_destroy_batch(eife_batch b) {
+  free_batch(b);
+  return EIFE_OK;
+}
+
+int eife_batch_offsets(eife_batch b, int64_t* offsets) {
+  if (!b || !offsets) return fail(EIFE_EINVAL, "null batch or offsets");
+  for (int i = 0; i <= b->B; ++i) offsets[i] = b->uoff[i];
+  return EIFE_OK;
+}
+
+int eife_batch_set_phi(eife_batch b, double tau, int stages) {
+  if (!b) return fail(EIFE_EINVAL, "null batch");
+  for (auto* g : b->inst) RET_IF(eife_set_phi(g, tau, stages));
+  b->phi_ready = true;
+  b->stages = stages;
+  drop_graph(b);
+  return EIFE_OK;
+}
+
+int eife_batch_step(eife_batch b, void* u, int64_t n_steps, int f_kind, double t0, void* stream) {
+  if (!b) return fail(EIFE_EINVAL, "null batch");
+  if (!u) return fail(EIFE_EINVAL, "u is null");
+  if (n_steps < 0) return fail(EIFE_EINVAL, "n_steps must be >= 0");
+  if (f_kind < EIFE_F_ZERO || f_kind > EIFE_F_AFFINE_T) return fail(EIFE_EINVAL, "unknown f_kind %d", f_kind);
+  if (!std::isfinite(t0)) return fail(EIFE_EINVAL, "t0 must be finite");
+  if (!b->phi_ready) return fail(EIFE_ESTATE, "eife_batch_set_phi must be called before eife_batch_step");
+  if (n_steps == 0) return EIFE_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto enqueue = [&]() -> int {
+    return b->dtype == EIFE_F32 ? batch_enqueue<float>(b, static_cast<float*>(u), n_steps, f_kind, t0, s)
+                                : batch_enqueue<double>(b, static_cast<double*>(u), n_steps, f_kind, t0, s);
+  };
+  if (!s) return enqueue();  // the legacy default stream cannot be captured
+  if (!(b->gexec && b->g_u == u && b->g_steps == n_steps && b->g_fkind == f_kind && b->g_t0 == t0)) {
+    drop_graph(b);
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    const int r = enqueue();
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    if (r != EIFE_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return r;
+    }
+    if (e != hipSuccess) return fail(EIFE_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    b->graph = graph;
+    HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+    b->g_u = u;
+    b->g_steps = n_steps;
+    b->g_fkind = f_kind;
+    b->g_t0 = t0;
+  }
+  HIP_TRY(hipGraphLaunch(b->gexec, s));
+  return EIFE_OK;
+}
+
+int eife_batch_autotune(eife_batch b, const char* cache_path, void* stream) {
+  if (!b) return fail(EIFE_EINVAL, "null batch");
+  if (!b->phi_ready) return fail(EIFE_ESTATE, "eife_batch_set_phi must be called before eife_batch_autotune");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (auto& c : b->classes)
+    RET_IF(b->dtype == EIFE_F32 ? tune_class<float>(b, c, cache_path, s) : tune_class<double>(b, c, cache_path, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  drop_graph(b);
+  return EIFE_OK;
+}
+
+int eife_batch_class_info(eife_batch b, int k, int32_t* out) {
+  if (!b || !out) return fail(EIFE_EINVAL, "null batch or out");
+  if (k < 0 || k >= int(b->classes.size())) return fail(EIFE_EINVAL, "class %d out of range", k);
+  const auto& c = b->classes[k];
+  const eife_grid_s* g = b->inst[c.members[0]];
+  out[0] = g->N[0];
+  out[1] = g->N[1];
+  out[2] = int32_t(c.members.size());
+  out[3] = c.prow > 0 ? c.prow : c.var_row;
+  out[4] = c.pcol > 0 ? c.pcol : c.var_col;
   return EIFE_OK;
 }
 

@@ -249,10 +249,11 @@ __device__ __forceinline__ T reaction_k(const Forcing& F, T u, int ix, int iy, i
 // Row passes (x lines, contiguous).  Block = PB line pairs = 2 PB rows; each
 // wavefront slice loads, transforms and stores its own pair, so the pass
 // needs no block barrier.
-template <typename T, int L, int PB, int MODE, int RK>
-__global__ void __launch_bounds__(PB * FftShape<L>::LP, 4) row_fast(const T* src, T* dst, T* __restrict__ dst2,
-                                                                     RowGeom g, const Cx<T>* __restrict__ tw,
-                                                                     Forcing F) {
+template <typename T, int L, int PB, int MODE, int RK, bool BAT>
+__global__ void __launch_bounds__(PB * FftShape<L>::LP, 4) row_fast(const T* src, T* dst, T* dst2, RowGeom g,
+                                                                     const Cx<T>* __restrict__ tw, Forcing F,
+                                                                     const RowInst<T>* __restrict__ insts) {
+  if constexpr (BAT) row_inst_ptrs<T, MODE>(insts, src, dst, dst2, F);
   constexpr int N = L / 2;
   constexpr int n = N - 1;
   constexpr int LP = FftShape<L>::LP;
@@ -356,9 +357,10 @@ __device__ __forceinline__ void diag_fast(const Sep& s, double D, double tau, do
 // Column passes (strided axis).  Block = PB pairs = C = 2 PB adjacent x-columns
 // (C * sizeof(T) >= 128 bytes per row segment); each wavefront slice of LP
 // lanes transforms PPW of the pairs one after the other.
-template <typename T, int L, int PB, int PPW, int MODE>
-__global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* __restrict__ W, T* __restrict__ H,
-                                                                        ColGeom g, const Cx<T>* tw, Diag dg) {
+template <typename T, int L, int PB, int PPW, int MODE, bool BAT>
+__global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* W, T* H, ColGeom g, const Cx<T>* tw,
+                                                                        Diag dg, const ColInst<T>* __restrict__ insts) {
+  if constexpr (BAT) col_inst_ptrs<T>(insts, W, H, dg);
   constexpr int N = L / 2;
   constexpr int n = N - 1;
   constexpr int LP = FftShape<L>::LP;
@@ -390,7 +392,7 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* __r
       if (m0 + MS * it < n) tmp[it] = gsrc[(MS * it * ldl) / 2];
 #pragma unroll
     for (int it = 0; it < CIT; ++it)
-      if (m0 + MS * it < n) ltile[MS * it] = tmp[it];
+      if (m0 + MS * it < n) ltile[MS * it] = mask_pad(tmp[it], c0 + 2 * tq, g.ncols);
   }
   __syncthreads();
 
@@ -444,7 +446,7 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* __r
           double o0, o1, n0, n1;
           diag_fast<MODE>(sep_combine(sxy[0], sl), D, tau, rtc2, double(gv.re), double(hv[it].re), &o0, &n0);
           diag_fast<MODE>(sep_combine(sxy[1], sl), D, tau, rtc2, double(gv.im), double(hv[it].im), &o1, &n1);
-          hrow[(MS * (b0 + it) * ldl) / 2] = Cx<T>{T(n0), T(n1)};
+          hrow[(MS * (b0 + it) * ldl) / 2] = mask_pad(Cx<T>{T(n0), T(n1)}, kx0, g.ncols);
           ltile[MS * (b0 + it)] = Cx<T>{T(o0), T(o1)};
         }
       }
@@ -464,7 +466,7 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* __r
   Cx<T>* gdst = reinterpret_cast<Cx<T>*>(W + base + m0 * ldl + 2 * tq);
 #pragma unroll
   for (int it = 0; it < CIT; ++it)
-    if (m0 + MS * it < n) gdst[(MS * it * ldl) / 2] = ltile[MS * it];
+    if (m0 + MS * it < n) gdst[(MS * it * ldl) / 2] = mask_pad(ltile[MS * it], c0 + 2 * tq, g.ncols);
 }
 
 // ---------------------------------------------------------------------------
@@ -510,9 +512,10 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_pipe(T* __r
       if (m0 + MS * it < n) pre[it] = gp[(MS * it * ldl) / 2];
   }
   for (; t < ntiles; t += gridDim.x) {
+    const int cpair = (t % ntx) * 2 * PB + 2 * tq;  // first column of this thread's pair
 #pragma unroll
     for (int it = 0; it < CIT; ++it)
-      if (m0 + MS * it < n) ltile[MS * it] = pre[it];
+      if (m0 + MS * it < n) ltile[MS * it] = mask_pad(pre[it], cpair, g.ncols);
     __syncthreads();
     const int tn = t + gridDim.x;
     if (tn < ntiles) {
@@ -532,7 +535,7 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_pipe(T* __r
     Cx<T>* gd = tile_ptr(t);
 #pragma unroll
     for (int it = 0; it < CIT; ++it)
-      if (m0 + MS * it < n) gd[(MS * it * ldl) / 2] = ltile[MS * it];
+      if (m0 + MS * it < n) gd[(MS * it * ldl) / 2] = mask_pad(ltile[MS * it], cpair, g.ncols);
     __syncthreads();
   }
 }

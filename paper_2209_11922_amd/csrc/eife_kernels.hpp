@@ -217,6 +217,25 @@ struct Forcing {
 
 enum FKind { FK_ZERO = 0, FK_AC = 1, FK_MMS = 2, FK_EX51 = 3, FK_CONST = 4, FK_AFFINE = 5 };
 
+// Per-instance data of a batched launch (instances of one size class share
+// geometry and launch shape; blockIdx.y (row passes) or blockIdx.z (column
+// passes) selects the instance).  A single grid launches with a null table.
+template <typename T>
+struct RowInst {
+  T* W;          // work array
+  T* H;          // spectral state
+  int64_t uoff;  // offset of the instance in the caller's batched nodal array
+  double D;      // diffusion coefficient (used by the manufactured forcing)
+};
+
+template <typename T>
+struct ColInst {
+  T* W;
+  T* H;
+  AxisTab ax[3];  // per-instance tables (phi tables depend on D)
+  double D;
+};
+
 template <typename T>
 __device__ __forceinline__ T reaction(const Forcing& F, T u, int ix, int iy, int iz) {
   switch (F.kind) {
@@ -275,9 +294,31 @@ __device__ __forceinline__ void put_odd(Cx<T>* line, int L, int k, T a, T b) {
   line[L - k] = Cx<T>{-a, -b};
 }
 
+// Pointers of a row pass for one instance (batched launches) or the launch's own.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) row_pass(const T* src, T* dst, T* __restrict__ dst2, RowGeom g,
-                                                const Cx<T>* __restrict__ tw, Forcing F) {
+__device__ __forceinline__ void row_inst_ptrs(const RowInst<T>* insts, const T*& src, T*& dst, T*& dst2,
+                                              Forcing& F) {
+  if (!insts) return;
+  const RowInst<T>& I = insts[blockIdx.y];
+  F.D = I.D;
+  if (MODE == ROW_FWD_USER) {
+    src = src + I.uoff;
+    dst = I.W;
+    dst2 = I.H;
+  } else if (MODE == ROW_INV_USER) {
+    src = I.W;
+    dst = dst + I.uoff;
+  } else {
+    src = I.W;
+    dst = I.W;
+  }
+}
+
+template <typename T, int MODE, bool BAT>
+__global__ void __launch_bounds__(256) row_pass(const T* src, T* dst, T* dst2, RowGeom g,
+                                                const Cx<T>* __restrict__ tw, Forcing F,
+                                                const RowInst<T>* __restrict__ insts) {
+  if constexpr (BAT) row_inst_ptrs<T, MODE>(insts, src, dst, dst2, F);
   extern __shared__ unsigned char smem_raw[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem_raw);
   const int n = g.n;
@@ -375,11 +416,33 @@ struct ColGeom {
   int P;
   int ls;
   int last_is_z;    // 1: spectral index (kx, ky, kz) = (c, outer, m); 0: (c, m, 0)
+  int ncols;        // real x-columns; columns ncols .. pitch-1 are padding, kept exactly zero
 };
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(256) col_pass(T* __restrict__ W, T* __restrict__ H, ColGeom g,
-                                                const Cx<T>* __restrict__ tw, Diag dg) {
+// Zero the padding half of a column pair (c = first column of the pair).
+template <typename T>
+__device__ __forceinline__ Cx<T> mask_pad(Cx<T> v, int c, int ncols) {
+  if (c >= ncols) return Cx<T>{T(0), T(0)};
+  if (c + 1 >= ncols) return Cx<T>{v.re, T(0)};
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void col_inst_ptrs(const ColInst<T>* insts, T*& W, T*& H, Diag& dg) {
+  if (!insts) return;
+  const ColInst<T>& I = insts[blockIdx.z];
+  W = I.W;
+  H = I.H;
+  dg.ax[0] = I.ax[0];
+  dg.ax[1] = I.ax[1];
+  dg.ax[2] = I.ax[2];
+  dg.D = I.D;
+}
+
+template <typename T, int MODE, bool BAT>
+__global__ void __launch_bounds__(256) col_pass(T* W, T* H, ColGeom g, const Cx<T>* __restrict__ tw, Diag dg,
+                                                const ColInst<T>* __restrict__ insts) {
+  if constexpr (BAT) col_inst_ptrs<T>(insts, W, H, dg);
   extern __shared__ unsigned char smem_raw[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem_raw);
   const int n = g.n;
@@ -396,7 +459,7 @@ __global__ void __launch_bounds__(256) col_pass(T* __restrict__ W, T* __restrict
   for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
     const int m = i / P;
     const int p = i - m * P;
-    const Cx<T> v = *reinterpret_cast<const Cx<T>*>(W + base + m * g.ld_line + 2 * p);
+    const Cx<T> v = mask_pad(*reinterpret_cast<const Cx<T>*>(W + base + m * g.ld_line + 2 * p), c0 + 2 * p, g.ncols);
     put_odd(lds + p * g.ls, L, m + 1, v.re, v.im);
   }
   __syncthreads();
@@ -407,7 +470,8 @@ __global__ void __launch_bounds__(256) col_pass(T* __restrict__ W, T* __restrict
       const int m = i / P;
       const int p = i - m * P;
       const Cx<T> Z = lds[p * g.ls + m + 1];
-      *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) = Cx<T>{-Z.im * scale, Z.re * scale};
+      *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) =
+          mask_pad(Cx<T>{-Z.im * scale, Z.re * scale}, c0 + 2 * p, g.ncols);
     }
     return;
   }
@@ -442,7 +506,7 @@ __global__ void __launch_bounds__(256) col_pass(T* __restrict__ W, T* __restrict
       outv[q] = T(o);
       newh[q] = T(nh);
     }
-    *reinterpret_cast<Cx<T>*>(hp) = Cx<T>{newh[0], newh[1]};
+    *reinterpret_cast<Cx<T>*>(hp) = mask_pad(Cx<T>{newh[0], newh[1]}, c0 + 2 * p, g.ncols);
     put_odd(line, L, m + 1, outv[0], outv[1]);
     if (m == 0) {
       line[0] = Cx<T>{T(0), T(0)};
@@ -455,7 +519,8 @@ __global__ void __launch_bounds__(256) col_pass(T* __restrict__ W, T* __restrict
     const int m = i / P;
     const int p = i - m * P;
     const Cx<T> Z = lds[p * g.ls + m + 1];
-    *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) = Cx<T>{-Z.im * scale, Z.re * scale};
+    *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) =
+        mask_pad(Cx<T>{-Z.im * scale, Z.re * scale}, c0 + 2 * p, g.ncols);
   }
 }
 

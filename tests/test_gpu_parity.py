@@ -287,3 +287,22 @@ def test_specialised_passes_match_generic_and_oracle(N, dtype, stages):
     assert _rel(outs[0], ref) <= TOL[dtype]
     assert _rel(outs[1], ref) <= TOL[dtype]
     assert _rel(outs[0], outs[1]) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_repeated_runs_are_bitwise_identical(dtype):
+    """A grid's result depends only on its inputs, not on what it computed before."""
+    eife = _lib()
+    for N in ([64, 48], [96, 128], [24, 16, 64]):
+        h = [1.0 / n for n in N]
+        g = eife.Grid(N, h, 1e-3, dtype)
+        g.set_phi(0.01, 2)
+        u0 = torch.tensor(seeded_inputs.uniform_field(77, N), dtype=g.torch_dtype, device="cuda")
+        outs = []
+        for _ in range(3):
+            u = u0.clone()
+            g.step(u, 6, eife.F_ALLEN_CAHN)
+            torch.cuda.synchronize()
+            outs.append(u)
+        assert torch.equal(outs[0], outs[1]) and torch.equal(outs[1], outs[2]), N
+        g.close()
