@@ -303,31 +303,44 @@ int prof_collect(eife_grid_s* g) {
 // the device tables `rinst` / `cinst` (null for a single grid).  `var`
 // selects a launch shape (pairs per block) among the tuned variants.
 
-// Row passes, specialised kernels: pairs per block (variant 0 / 1).
+// Pairs per block of the specialised kernels: the largest power of two whose
+// LDS regions fit the budget (64 KB rows, 80 KB columns = two blocks per CU),
+// capped so row blocks stay within 512 threads and column tiles at 128-byte
+// row segments.  Variant 1 halves it.
+template <typename T, int L>
+constexpr int pb_fit(int budget, int cap) {
+  int pb = 1;
+  while (pb < cap && size_t(2 * pb) * fast::Line<T, L>::BUF * sizeof(Cx<T>) <= size_t(budget)) pb *= 2;
+  return pb;
+}
 template <typename T, int L>
 constexpr int row_pb(int var) {
-  return var == 0 ? (sizeof(T) == 4 ? (L == 128 ? 16 : (L == 1024 ? 4 : 8)) : (L == 128 ? 8 : (L == 1024 ? 2 : 4)))
-                  : (sizeof(T) == 4 ? (L == 128 ? 8 : (L == 1024 ? 2 : 4)) : (L == 128 ? 4 : (L == 1024 ? 1 : 2)));
+  constexpr int cap = std::min(16, 512 / fast::Line<T, L>::LP);
+  constexpr int pb = pb_fit<T, L>(65536, cap);
+  return var == 0 ? pb : std::max(1, pb / 2);
 }
-
-// Column passes, specialised kernels: variant 0 uses 128-byte row segments
-// (32 FP32 / 16 FP64 columns), variant 1 64-byte segments.
 template <typename T, int L>
 constexpr int col_pb(int var) {
-  return var == 0 ? ((L >= 1024) ? (sizeof(T) == 4 ? 8 : 4) : (sizeof(T) == 4 ? 16 : 8))
-                  : ((L >= 1024) ? (sizeof(T) == 4 ? 4 : 2) : (sizeof(T) == 4 ? 8 : 4));
-}
-template <typename T, int L, int PB>
-constexpr int col_ppw() {
-  return (PB * fast::FftShape<L>::LP > 512) ? PB * fast::FftShape<L>::LP / 512 : 1;
+  constexpr int pb = pb_fit<T, L>(81920, int(128 / (2 * sizeof(T))));
+  return var == 0 ? pb : std::max(1, pb / 2);
 }
 
-bool fast_len(int N) { return N == 64 || N == 128 || N == 256 || N == 512; }
+template <typename T, int L, int PB>
+constexpr int col_ppw() {
+  return (PB * fast::Line<T, L>::LP > 512) ? PB * fast::Line<T, L>::LP / 512 : 1;
+}
+
+// Line lengths with specialised kernels (the three-subsequence form of
+// N = 384 needs more registers than double data allows without spilling).
+template <typename T>
+bool fast_len(int N) {
+  return N == 64 || N == 128 || N == 256 || N == 512 || N == 192 || (N == 384 && sizeof(T) == 4);
+}
 
 template <typename T, int L, int PB, bool BAT>
 void row_fast_go(int mode, int nrows, int count, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
                  const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
-  constexpr int NT = PB * fast::FftShape<L>::LP;
+  constexpr int NT = PB * fast::Line<T, L>::LP;
   dim3 grid((nrows + 2 * PB - 1) / (2 * PB), count);
   if (mode == ROW_PHYS) {
     if (F.kind == FK_AC)
@@ -362,13 +375,13 @@ template <typename T, int L, int PB, bool BAT>
 void col_fast_go(int mode, int pitch, int outer, int count, bool pipe, hipStream_t s, T* W, T* H, const ColGeom& cg,
                  const Cx<T>* tw, const Diag& dg, const ColInst<T>* ci) {
   constexpr int PPW = col_ppw<T, L, PB>();
-  constexpr int NT = PB / PPW * fast::FftShape<L>::LP;
+  constexpr int NT = PB / PPW * fast::Line<T, L>::LP;
   dim3 grid(pitch / (2 * PB), outer, count);
   if (mode == COL_PLAIN) {
     if (pipe && !ci) {
       const int ntx = pitch / (2 * PB);
       const int ntiles = ntx * outer;
-      constexpr int lds = PB * fast::FftShape<L>::BUF * int(sizeof(Cx<T>));
+      constexpr int lds = PB * fast::Line<T, L>::BUF * int(sizeof(Cx<T>));
       constexpr int per_cu = std::max(1, std::min(kPipeBlocksPerCu, 160 * 1024 / lds));
       const int nblk = std::min(ntiles, g_cus * per_cu);
       hipLaunchKernelGGL((fast::col_pipe<T, L, PB, PPW>), dim3(nblk), dim3(NT), 0, s, W, cg, tw, ntx, ntiles);
@@ -400,12 +413,19 @@ void col_fast_launch(int var, int mode, int pitch, int outer, int count, hipStre
 template <typename T>
 bool try_row_fast(const eife_grid_s* g, int var, int mode, int count, hipStream_t s, const T* src, T* dst, T* dst2,
                   const RowGeom& rg, const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
-  if (g->transform != EIFE_TX_FFT || !fast_len(g->N[0])) return false;
+  if (g->transform != EIFE_TX_FFT || !fast_len<T>(g->N[0])) return false;
   switch (g->N[0]) {
     case 64: row_fast_launch<T, 128>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
     case 128: row_fast_launch<T, 256>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
     case 256: row_fast_launch<T, 512>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
     case 512: row_fast_launch<T, 1024>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
+    case 192: row_fast_launch<T, 384>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
+    case 384:
+      if constexpr (sizeof(T) == 4) {
+        row_fast_launch<T, 768>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri);
+        return true;
+      }
+      return false;
   }
   return false;
 }
@@ -413,12 +433,19 @@ bool try_row_fast(const eife_grid_s* g, int var, int mode, int count, hipStream_
 template <typename T>
 bool try_col_fast(const eife_grid_s* g, int var, int axis, int mode, int outer, int count, hipStream_t s, T* W, T* H,
                   const ColGeom& cg, const Cx<T>* tw, const Diag& dg, const ColInst<T>* ci) {
-  if (g->transform != EIFE_TX_FFT || !fast_len(g->N[axis])) return false;
+  if (g->transform != EIFE_TX_FFT || !fast_len<T>(g->N[axis])) return false;
   switch (g->N[axis]) {
     case 64: col_fast_launch<T, 128>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
     case 128: col_fast_launch<T, 256>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
     case 256: col_fast_launch<T, 512>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
     case 512: col_fast_launch<T, 1024>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
+    case 192: col_fast_launch<T, 384>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
+    case 384:
+      if constexpr (sizeof(T) == 4) {
+        col_fast_launch<T, 768>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci);
+        return true;
+      }
+      return false;
   }
   return false;
 }
@@ -1086,7 +1113,7 @@ int tune_class(eife_batch_s* b, eife_batch_s::Class& c, const char* path, hipStr
     return EIFE_OK;
   }
   eife_grid_s* g = b->inst[c.members[0]];
-  const bool fast = g->transform == EIFE_TX_FFT && fast_len(g->N[0]) && fast_len(g->N[1]);
+  const bool fast = g->transform == EIFE_TX_FFT && fast_len<T>(g->N[0]) && fast_len<T>(g->N[1]);
   std::vector<std::array<int, 4>> cands;
   if (fast) {
     for (int r = 0; r < 2; ++r)

@@ -97,6 +97,14 @@ struct FftShape {
   static_assert(R2 >= 2 && R2 <= E, "unsupported FFT length");
 };
 
+// Occupancy hint (waves per SIMD) of the pass kernels: 4 keeps two 8-wave
+// blocks per CU for FP32 lines up to 512 points; longer or double lines
+// need more registers than that leaves.
+template <typename T, int L>
+struct MinWaves {
+  static constexpr int value = (L >= 1024 || sizeof(T) == 8) ? 2 : 4;
+};
+
 // The twiddle factors one lane needs, loaded once per kernel.
 template <typename T, int L>
 struct LaneTw {
@@ -106,15 +114,16 @@ struct LaneTw {
   static constexpr int LP = FftShape<L>::LP;
   Cx<T> s1[E];        // stage 2 (Ns = E): W_L^{q k (L / E^2)}, k = lane mod E
   Cx<T> s2[NB2][R2];  // stage 3 (Ns = E^2): W_L^{q j}, j = lane + LP b
-  __device__ __forceinline__ void load(const Cx<T>* __restrict__ tw, int lane) {
+  // tw[i] = exp(-2 pi i i / (L * stride)): the table of a line stride times as long
+  __device__ __forceinline__ void load(const Cx<T>* __restrict__ tw, int lane, int stride = 1) {
     const int k = lane & (E - 1);
 #pragma unroll
-    for (int q = 1; q < E; ++q) s1[q] = tw[(q * k) * (L / (E * E))];
+    for (int q = 1; q < E; ++q) s1[q] = tw[stride * (q * k) * (L / (E * E))];
 #pragma unroll
     for (int b = 0; b < NB2; ++b) {
       const int j = lane + LP * b;
 #pragma unroll
-      for (int q = 1; q < R2; ++q) s2[b][q] = tw[q * j];
+      for (int q = 1; q < R2; ++q) s2[b][q] = tw[stride * q * j];
     }
   }
 };
@@ -173,6 +182,34 @@ __device__ __forceinline__ void wstage(Cx<T> (&v)[FftShape<L>::E], In in, Tw twf
   }
 }
 
+// Stages 2 and 3 of a length-L FFT whose first stage has been written to buf.
+template <typename T, int L>
+__device__ __forceinline__ void fft_tail(Cx<T> (&v)[FftShape<L>::E], Cx<T>* buf, int lane, const LaneTw<T, L>& tw) {
+  constexpr int E = FftShape<L>::E;
+  constexpr int LP = FftShape<L>::LP;
+  constexpr int R2 = FftShape<L>::R2;
+  // input j + (L/R) q sits at xpad(j) + (L/R) q * 9/8
+  const Cx<T>* rb = buf + xpad(lane);
+  auto in1 = [&](int, int q) -> Cx<T> { return rb[(L / E) * q + (L / E) * q / 8]; };
+  auto in2 = [&](int b, int q) -> Cx<T> {
+    return rb[LP * b + (LP * b) / 8 + (L / R2) * q + (L / R2) * q / 8];
+  };
+  auto tw1 = [&](int, int q) -> Cx<T> { return tw.s1[q]; };
+  auto tw2 = [&](int b, int q) -> Cx<T> { return tw.s2[b][q]; };
+  wstage<T, L, E, E, false>(v, in1, tw1, buf, lane);
+  wave_sync();
+  wstage<T, L, R2, E * E, true>(v, in2, tw2, buf, lane);
+}
+
+// First stage of a length-L FFT on the inputs already in v (v[q] = input lane + LP q).
+template <typename T, int L>
+__device__ __forceinline__ void fft_head(Cx<T> (&v)[FftShape<L>::E], Cx<T>* buf, int lane) {
+  constexpr int E = FftShape<L>::E;
+  auto inr = [&](int, int q) -> Cx<T> { return v[q]; };
+  auto tw0 = [&](int, int) -> Cx<T> { return Cx<T>{T(1), T(0)}; };
+  wstage<T, L, E, 1, false>(v, inr, tw0, buf, lane);
+}
+
 // Forward FFT of length L of the odd extension of the pair whose node values
 // sit at node[0 .. N-2].  On return v holds the outputs (see wstage with LAST).
 template <typename T, int L>
@@ -180,34 +217,24 @@ __device__ __forceinline__ void odd_fft(Cx<T> (&v)[FftShape<L>::E], const Cx<T>*
                                         const LaneTw<T, L>& tw) {
   constexpr int E = FftShape<L>::E;
   constexpr int LP = FftShape<L>::LP;
-  constexpr int R2 = FftShape<L>::R2;
   constexpr int N = L / 2;
   // stage 0: input m = lane + LP q; q < E/2 <=> m < N
   const Cx<T>* lo = node + (lane - 1);          // node[m - 1]
   const Cx<T>* hi = node + (2 * N - 1 - lane);  // node[2N - m - 1] = hi[-LP q]
-  auto in0 = [&](int, int q) -> Cx<T> {
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
     if (q < E / 2) {
-      if (q == 0) return lane == 0 ? Cx<T>{T(0), T(0)} : lo[0];
-      return lo[LP * q];
+      v[q] = (q == 0 && lane == 0) ? Cx<T>{T(0), T(0)} : lo[LP * q];
+    } else if (q == E / 2 && lane == 0) {
+      v[q] = Cx<T>{T(0), T(0)};
+    } else {
+      const Cx<T> c = hi[-LP * q];
+      v[q] = Cx<T>{-c.re, -c.im};
     }
-    if (q == E / 2 && lane == 0) return Cx<T>{T(0), T(0)};
-    const Cx<T> c = hi[-LP * q];
-    return Cx<T>{-c.re, -c.im};
-  };
-  // later stages read input j + (L/R) q at xpad(j) + (L/R) q * 9/8
-  const Cx<T>* rb = buf + xpad(lane);
-  auto in1 = [&](int, int q) -> Cx<T> { return rb[(L / E) * q + (L / E) * q / 8]; };
-  auto in2 = [&](int b, int q) -> Cx<T> {
-    return rb[LP * b + (LP * b) / 8 + (L / R2) * q + (L / R2) * q / 8];
-  };
-  auto tw0 = [&](int, int) -> Cx<T> { return Cx<T>{T(1), T(0)}; };
-  auto tw1 = [&](int, int q) -> Cx<T> { return tw.s1[q]; };
-  auto tw2 = [&](int b, int q) -> Cx<T> { return tw.s2[b][q]; };
-  wstage<T, L, E, 1, false>(v, in0, tw0, buf, lane);
+  }
+  fft_head<T, L>(v, buf, lane);
   wave_sync();
-  wstage<T, L, E, E, false>(v, in1, tw1, buf, lane);
-  wave_sync();
-  wstage<T, L, R2, E * E, true>(v, in2, tw2, buf, lane);
+  fft_tail<T, L>(v, buf, lane, tw);
   wave_sync();  // buf may be rewritten by the next transform of this pair
 }
 
@@ -230,6 +257,113 @@ __device__ __forceinline__ void for_outputs(const Cx<T> (&v)[FftShape<L>::E], in
 }
 
 // ---------------------------------------------------------------------------
+// Line<T, L>: the transform of one line pair of FFT length L = 2N, for L a
+// power of two (one wave-local FFT) or L = 3M with M a power of two (the
+// odd extension split into its three stride-3 subsequences, three M-point
+// wave FFTs, then a radix-3 combination:
+//   Z_{k'+jM} = F0_{k'} + w^j W_L^{k'} F1_{k'} + w^{2j} W_L^{2k'} F2_{k'},  w = exp(-2 pi i/3)).
+// Interface: LP (lanes per pair), BUF (LDS region per pair), Regs, Tw,
+// transform(regs, node, region, lane, tw, twL), outputs(regs, lane, twL, f).
+template <int L>
+struct IsPow2 {
+  static constexpr bool value = (L & (L - 1)) == 0;
+};
+
+template <typename T, int L, bool P2 = IsPow2<L>::value>
+struct Line;
+
+template <typename T, int L>
+struct Line<T, L, true> {
+  static constexpr int LP = FftShape<L>::LP;
+  static constexpr int BUF = FftShape<L>::BUF;
+  struct Regs {
+    Cx<T> v[FftShape<L>::E];
+  };
+  struct Tw {
+    LaneTw<T, L> t;
+    __device__ __forceinline__ void load(const Cx<T>* __restrict__ tw, int lane) { t.load(tw, lane, 1); }
+  };
+  static __device__ __forceinline__ void transform(Regs& r, const Cx<T>* node, Cx<T>* region, int lane, const Tw& tw,
+                                                   const Cx<T>* __restrict__) {
+    odd_fft<T, L>(r.v, node, region, lane, tw.t);
+  }
+  template <typename F>
+  static __device__ __forceinline__ void outputs(const Regs& r, int lane, const Cx<T>* __restrict__, F f) {
+    for_outputs<T, L>(r.v, lane, f);
+  }
+};
+
+template <typename T, int L>
+struct Line<T, L, false> {
+  static constexpr int M = L / 3;
+  static_assert(3 * M == L && IsPow2<M>::value, "line length must be 2^k or 3 * 2^k");
+  static constexpr int E = FftShape<M>::E;
+  static constexpr int LP = FftShape<M>::LP;
+  static constexpr int R2 = FftShape<M>::R2;
+  static constexpr int SUB = M + M / 8;  // exchange buffer of one sub-transform (multiple of 8)
+  static constexpr int BUF = ((3 * SUB + 63) / 64) * 64 + 2;
+  struct Regs {
+    Cx<T> v[3][E];
+  };
+  struct Tw {
+    LaneTw<T, M> t;
+    __device__ __forceinline__ void load(const Cx<T>* __restrict__ tw, int lane) { t.load(tw, lane, 3); }
+  };
+  static __device__ __forceinline__ void transform(Regs& r, const Cx<T>* node, Cx<T>* region, int lane, const Tw& tw,
+                                                   const Cx<T>* __restrict__) {
+    constexpr int N = L / 2;
+    // every node value is read before the exchange buffers (which overlay the
+    // nodes) are written
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int p = 3 * (lane + LP * q) + s;  // index in the odd extension
+        Cx<T> val = Cx<T>{T(0), T(0)};
+        if (p != 0 && p != N) {
+          if (p < N) {
+            val = node[p - 1];
+          } else {
+            const Cx<T> c = node[L - p - 1];
+            val = Cx<T>{-c.re, -c.im};
+          }
+        }
+        r.v[s][q] = val;
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < 3; ++s) fft_head<T, M>(r.v[s], region + s * SUB, lane);
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < 3; ++s) fft_tail<T, M>(r.v[s], region + s * SUB, lane, tw.t);
+    wave_sync();
+  }
+  template <typename F>
+  static __device__ __forceinline__ void outputs(const Regs& r, int lane, const Cx<T>* __restrict__ twL, F f) {
+    constexpr int NB = E / R2;
+    const T h = T(0.86602540378443864676);  // sqrt(3)/2
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+      for (int q = 0; q < R2; ++q) {
+        const int kp = lane + LP * b + q * (M / R2);  // output of the sub-transforms, 0 <= kp < M
+        const Cx<T> f0 = r.v[0][b * R2 + q];
+        const Cx<T> t1 = cmul(r.v[1][b * R2 + q], twL[kp]);
+        const Cx<T> t2 = cmul(r.v[2][b * R2 + q], twL[2 * kp]);
+        const Cx<T> sum = cadd(t1, t2);
+        if (kp >= 1) f(kp, cadd(f0, sum));
+        if (kp < M / 2) {
+          const Cx<T> d = csub(t1, t2);
+          // f0 + w t1 + w^2 t2 = f0 - sum/2 - i (sqrt(3)/2) d
+          f(M + kp, Cx<T>{f0.re - T(0.5) * sum.re + h * d.im, f0.im - T(0.5) * sum.im - h * d.re});
+        }
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Each line pair owns one LDS region of FftShape<L>::BUF complex entries.  Its
 // first N - 1 entries hold the pair's node values (the "tile"); the whole
 // region doubles as the pair's FFT exchange buffer, which is safe because
@@ -250,15 +384,15 @@ __device__ __forceinline__ T reaction_k(const Forcing& F, T u, int ix, int iy, i
 // wavefront slice loads, transforms and stores its own pair, so the pass
 // needs no block barrier.
 template <typename T, int L, int PB, int MODE, int RK, bool BAT>
-__global__ void __launch_bounds__(PB * FftShape<L>::LP, 4) row_fast(const T* src, T* dst, T* dst2, RowGeom g,
+__global__ void __launch_bounds__((PB * Line<T, L>::LP), (MinWaves<T, L>::value)) row_fast(const T* src, T* dst, T* dst2, RowGeom g,
                                                                      const Cx<T>* __restrict__ tw, Forcing F,
                                                                      const RowInst<T>* __restrict__ insts) {
   if constexpr (BAT) row_inst_ptrs<T, MODE>(insts, src, dst, dst2, F);
+  using Ln = Line<T, L>;
   constexpr int N = L / 2;
   constexpr int n = N - 1;
-  constexpr int LP = FftShape<L>::LP;
-  constexpr int E = FftShape<L>::E;
-  constexpr int BUF = FftShape<L>::BUF;
+  constexpr int LP = Ln::LP;
+  constexpr int BUF = Ln::BUF;
   constexpr int RIT = (n + LP - 1) / LP;
   __shared__ Cx<T> lds[PB * BUF];
   const int tid = threadIdx.x;
@@ -267,7 +401,7 @@ __global__ void __launch_bounds__(PB * FftShape<L>::LP, 4) row_fast(const T* src
   const int ra = blockIdx.x * 2 * PB + 2 * p, rb = ra + 1;
   const bool hasa = ra < g.nrows, hasb = rb < g.nrows;
   const T scale = T(1.0 / sqrt(double(L)));
-  LaneTw<T, L> twl;
+  typename Ln::Tw twl;
   twl.load(tw, lane);
   Cx<T>* my = lds + p * BUF;
 
@@ -287,22 +421,22 @@ __global__ void __launch_bounds__(PB * FftShape<L>::LP, 4) row_fast(const T* src
   }
   wave_sync();
 
-  Cx<T> v[E];
-  odd_fft<T, L>(v, my, my, lane, twl);
+  typename Ln::Regs v;
+  Ln::transform(v, my, my, lane, twl, tw);
 
   if (MODE == ROW_PHYS) {
     const int iya = ra % g.ny, iza = ra / g.ny;
     const int iyb = rb % g.ny, izb = rb / g.ny;
-    for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) {
+    Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) {
       const T ua = -Z.im * scale, ub = Z.re * scale;
       const T fa = reaction_k<T, RK>(F, ua, k - 1, iya, iza);
       const T fb = reaction_k<T, RK>(F, ub, k - 1, iyb, izb);
       my[k - 1] = Cx<T>{fa, fb};
     });
     wave_sync();
-    odd_fft<T, L>(v, my, my, lane, twl);
+    Ln::transform(v, my, my, lane, twl, tw);
   }
-  for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+  Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
   wave_sync();
   T* da = dst + int64_t(ra) * g.ld_dst + lane;
   T* db = dst + int64_t(rb) * g.ld_dst + lane;
@@ -358,14 +492,14 @@ __device__ __forceinline__ void diag_fast(const Sep& s, double D, double tau, do
 // (C * sizeof(T) >= 128 bytes per row segment); each wavefront slice of LP
 // lanes transforms PPW of the pairs one after the other.
 template <typename T, int L, int PB, int PPW, int MODE, bool BAT>
-__global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* W, T* H, ColGeom g, const Cx<T>* tw,
+__global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::value)) col_fast(T* W, T* H, ColGeom g, const Cx<T>* tw,
                                                                         Diag dg, const ColInst<T>* __restrict__ insts) {
   if constexpr (BAT) col_inst_ptrs<T>(insts, W, H, dg);
+  using Ln = Line<T, L>;
   constexpr int N = L / 2;
   constexpr int n = N - 1;
-  constexpr int LP = FftShape<L>::LP;
-  constexpr int E = FftShape<L>::E;
-  constexpr int BUF = FftShape<L>::BUF;
+  constexpr int LP = Ln::LP;
+  constexpr int BUF = Ln::BUF;
   constexpr int SLOTS = PB / PPW;
   constexpr int NT = SLOTS * LP;
   __shared__ Cx<T> lds[PB * BUF];
@@ -396,15 +530,15 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* W, 
   }
   __syncthreads();
 
-  Cx<T> v[E];
+  typename Ln::Regs v;
   {
-    LaneTw<T, L> twl;
+    typename Ln::Tw twl;
     twl.load(tw, lane);
 #pragma unroll 1
     for (int r = 0; r < PPW; ++r) {
       Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
-      odd_fft<T, L>(v, my, my, lane, twl);
-      for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+      Ln::transform(v, my, my, lane, twl, tw);
+      Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
     }
   }
 
@@ -453,13 +587,13 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* W, 
     }
     __syncthreads();
     __asm__ volatile("" ::: "memory");
-    LaneTw<T, L> twl;
+    typename Ln::Tw twl;
     twl.load(tw, lane);
 #pragma unroll 1
     for (int r = 0; r < PPW; ++r) {
       Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
-      odd_fft<T, L>(v, my, my, lane, twl);
-      for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+      Ln::transform(v, my, my, lane, twl, tw);
+      Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
     }
   }
   __syncthreads();
@@ -476,13 +610,13 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_fast(T* W, 
 // latency hides behind the FFTs.  Tile t covers columns (t % ntx) * C ... and
 // outer index t / ntx.
 template <typename T, int L, int PB, int PPW>
-__global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_pipe(T* __restrict__ W, ColGeom g,
+__global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::value)) col_pipe(T* __restrict__ W, ColGeom g,
                                                                         const Cx<T>* tw, int ntx, int ntiles) {
+  using Ln = Line<T, L>;
   constexpr int N = L / 2;
   constexpr int n = N - 1;
-  constexpr int LP = FftShape<L>::LP;
-  constexpr int E = FftShape<L>::E;
-  constexpr int BUF = FftShape<L>::BUF;
+  constexpr int LP = Ln::LP;
+  constexpr int BUF = Ln::BUF;
   constexpr int SLOTS = PB / PPW;
   constexpr int NT = SLOTS * LP;
   constexpr int MS = NT / PB;
@@ -495,7 +629,7 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_pipe(T* __r
   const int m0 = tid / PB;
   const int ldl = int(g.ld_line);
   const T scale = T(1.0 / sqrt(double(L)));
-  LaneTw<T, L> twl;
+  typename Ln::Tw twl;
   twl.load(tw, lane);
   Cx<T>* ltile = lds + tq * BUF + m0;
   auto tile_ptr = [&](int t) -> Cx<T>* {
@@ -524,12 +658,12 @@ __global__ void __launch_bounds__(PB / PPW * FftShape<L>::LP, 4) col_pipe(T* __r
       for (int it = 0; it < CIT; ++it)
         if (m0 + MS * it < n) pre[it] = gp[(MS * it * ldl) / 2];
     }
-    Cx<T> v[E];
+    typename Ln::Regs v;
 #pragma unroll 1
     for (int r = 0; r < PPW; ++r) {
       Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
-      odd_fft<T, L>(v, my, my, lane, twl);
-      for_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+      Ln::transform(v, my, my, lane, twl, tw);
+      Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
     }
     __syncthreads();
     Cx<T>* gd = tile_ptr(t);

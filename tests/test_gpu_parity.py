@@ -261,6 +261,8 @@ FAST_GRIDS = [
     _case("3d-128x64x256", [128, 64, 256]),
     _case("3d-256x96x48-mixed", [256, 96, 48]),
     _case("1d-512", [512]),
+    _case("2d-192x384-radix3", [192, 384]),
+    _case("3d-192x64x48-radix3", [192, 64, 48]),
 ]
 
 
