@@ -41,6 +41,11 @@ BYTES_PER_DOF = {"row_phys": 8, "mid": 8, "last_a": 16, "last_b": 16, "row_fwd":
                  "last_plain": 8}
 
 
+# Sine-matrix products per launch of each pass kind on the matrix-core transform.
+GEMMS_PER_PASS = {"row_phys": 2, "mid": 1, "last_a": 2, "last_b": 2, "row_fwd": 1, "row_inv": 1, "last_plain": 1}
+BF16_PEAK_TFS = 2500.0
+
+
 def measured_traffic(pass_name):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None.
 
@@ -94,6 +99,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--workload", choices=["cube", "batched"], default="cube",
                     help="cube: 3D Allen-Cahn 255^3 (default line); batched: 512 independent 2D instances")
+    ap.add_argument("--transform", choices=["fft", "gemm"], default="fft",
+                    help="cube workload: FFT sine transforms (default) or split-BF16 matrix-core products")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain device copy of one work array's size (counter calibration)")
     args = ap.parse_args()
@@ -125,6 +132,9 @@ def main():
         log(f"bench: calibration copy (torch.mul) reading and writing {ndof * 4} bytes, x3")
         del a, b
     g = eife.Grid(N, h, D, "f32")
+    gemm = args.transform == "gemm"
+    if gemm:
+        g.set_transform(eife.binding.TX_GEMM_SPLITBF16)
     g.set_phi(TAU, 2)
     u = torch.tensor(u0, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
@@ -161,22 +171,31 @@ def main():
     log(f"  profiled step {prof_step_ms:.3f} ms; whole-step algorithmic bandwidth "
         f"{step_bytes / (dt / args.steps) / 1e9:.1f} GB/s")
     roof = {"bound": "hbm", "achieved": round(dom[4], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dom[4] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom[1]), "kernel": dom[1],
-            "kernel_avg_us": round(dom[3] * 1e3, 2),
+            "frac": round(dom[4] / HBM_PEAK_GBS, 4), "traffic": None if gemm else measured_traffic(dom[1]),
+            "kernel": dom[1], "kernel_avg_us": round(dom[3] * 1e3, 2),
             "bytes_per_launch": BYTES_PER_DOF[dom[1]] * ndof,
             "step_achieved_GBs": round(step_bytes / (dt / args.steps) / 1e9, 1)}
+    if gemm:
+        # matrix-core view: 3 BF16 products of 2 (N-1) flops per DoF per transform
+        gemms = GEMMS_PER_PASS[dom[1]]
+        flops = gemms * 3 * 2 * (N_INT - 1) * ndof
+        tfs = flops / (dom[3] * 1e-3) / 1e12
+        roof["mfma"] = {"achieved": round(tfs, 1), "peak": BF16_PEAK_TFS, "unit": "TFLOP/s",
+                        "frac": round(tfs / BF16_PEAK_TFS, 4), "flops_per_launch": flops}
+        log(f"  dominant pass {dom[1]}: {tfs:.1f} TFLOP/s BF16 ({tfs / BF16_PEAK_TFS * 100:.1f}% of dense peak)")
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and not gemm:
         cpu = cpu_baseline(u0, N, h, D)
         log(f"bench: cpu oracle {cpu['value']:.4e} DoF-steps/s on {cpu['cores']} cores")
 
     out = {"metric": METRIC, "value": value, "unit": "DoF-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3+f32acc" if gemm else "f32", "data": "synthetic",
            "config": {"workload": "3D Allen-Cahn eps=0.02, Q1 grid 256^3 intervals (255^3 DoFs), Dirichlet, "
-                                  "u0 uniform[-0.9,0.9] seed 0, EIFE2 c2=1/2 tau=0.005, FP32 sine-transform path",
-                      "dofs": ndof, "tau": TAU, "scheme": "EIFE2"},
+                                  "u0 uniform[-0.9,0.9] seed 0, EIFE2 c2=1/2 tau=0.005, "
+                                  + ("split-BF16 matrix-core sine transforms" if gemm else "FP32 sine-transform path"),
+                      "dofs": ndof, "tau": TAU, "scheme": "EIFE2", "transform": args.transform},
            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     g.close()

@@ -113,7 +113,15 @@ enum eife_transform {
   EIFE_TX_GEMM_SPLITBF16 = 2  /* dense sine-matrix products on the matrix cores */
 };
 
-/* Select the transform implementation of later eife_step calls. */
+/* Select the transform implementation of later eife_step calls.
+ * EIFE_TX_GEMM_SPLITBF16 applies the orthonormal sine matrix of Section 4
+ * along each axis as a dense product on the matrix cores, with FP32 data and
+ * matrix split into BF16 high and low parts (three products, FP32
+ * accumulation; relative error of order 1e-5 per step instead of FP32
+ * round-off).  It needs an FP32 grid with every N <= 1024, else
+ * EIFE_EUNSUPPORTED; the library builds the matrices (2 * kp^2 BF16 values
+ * per axis, kp = the next power of two >= max(64, N - 1)) on the first
+ * selection.  Unknown kind: EIFE_EINVAL.  Batches ignore this setting. */
 int eife_set_transform(eife_grid g, int kind);
 
 /* Parameters c0, c1 of EIFE_F_CONST / EIFE_F_AFFINE_T. */

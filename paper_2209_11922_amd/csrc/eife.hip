@@ -27,6 +27,7 @@
 #include "../../include/eife.h"
 #include "eife_kernels.hpp"
 #include "eife_fast.hpp"
+#include "eife_gemm.hpp"
 
 using namespace eife;
 
@@ -109,6 +110,8 @@ struct eife_grid_s {
   // launch shapes
   FftPlan plan[3];
   int transform = EIFE_TX_FFT;
+  void* smat[3] = {nullptr, nullptr, nullptr};  // split-BF16 sine matrices (hi then lo, kp x kp each)
+  int kp[3] = {0, 0, 0};
   int prow = 1;     // pairs per block, row pass
   int pcol[3] = {1, 1, 1};  // pairs per block, column pass along axis 1, 2
   int nlines_total() const { return n[1] * n[2]; }
@@ -474,6 +477,161 @@ void col_generic_go(int mode, dim3 grid, size_t shm, hipStream_t s, T* W, T* H, 
     hipLaunchKernelGGL((col_pass<T, COL_ETD1, BATC>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
 }
 
+// ---------------------------------------------------------------------------
+// Split-BF16 matrix-core transform (single grids, FP32).
+
+int gemm_kp(int n) {
+  int kp = 64;
+  while (kp < n) kp *= 2;
+  return kp;
+}
+
+uint16_t bf16_bits(float x) {  // round to nearest even
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+float bf16_value(uint16_t b) {
+  const uint32_t u = uint32_t(b) << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+
+// S_mk = sqrt(2/N) sin((m+1)(k+1) pi / N) for m, k < N-1, zero padded to kp x kp,
+// split into hi = bf16(s) and lo = bf16(s - hi).
+int build_smat(eife_grid_s* g, int a) {
+  const int n = g->n[a], N = g->N[a], kp = gemm_kp(n);
+  std::vector<uint16_t> v(size_t(2) * kp * kp, 0);
+  const double sc = std::sqrt(2.0 / N);
+  for (int m = 0; m < n; ++m)
+    for (int k = 0; k < n; ++k) {
+      const long long j = (long long)(m + 1) * (k + 1) % (2 * N);  // sin is 2N-periodic in j
+      const double sv = sc * std::sin(M_PI * double(j) / N);
+      const uint16_t hi = bf16_bits(float(sv));
+      v[size_t(m) * kp + k] = hi;
+      v[size_t(kp) * kp + size_t(m) * kp + k] = bf16_bits(float(sv - double(bf16_value(hi))));
+    }
+  hipFree(g->smat[a]);
+  g->smat[a] = nullptr;
+  if (hipMalloc(&g->smat[a], v.size() * 2) != hipSuccess) return fail(EIFE_ENOMEM, "sine matrix allocation failed");
+  HIP_TRY(hipMemcpy(g->smat[a], v.data(), v.size() * 2, hipMemcpyHostToDevice));
+  g->kp[a] = kp;
+  return EIFE_OK;
+}
+
+gemm::SMat smat_of(const eife_grid_s* g, int a) {
+  const __bf16* p = static_cast<const __bf16*>(g->smat[a]);
+  return gemm::SMat{p, p + size_t(g->kp[a]) * g->kp[a]};
+}
+
+template <int KP>
+int gemm_attrs() {
+  const int shm = int(gemm::Shape<KP>::LDS);
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm::gemm_row<KP, ROW_PHYS, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm::gemm_row<KP, ROW_PHYS, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm::gemm_row<KP, ROW_FWD_USER, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm::gemm_row<KP, ROW_INV_USER, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm::gemm_col<KP, COL_PLAIN>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm::gemm_col<KP, COL_STAGE_A>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm::gemm_col<KP, COL_STAGE_B>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm::gemm_col<KP, COL_ETD1>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  return EIFE_OK;
+}
+
+int gemm_attrs_all() {
+  static int done = 0;  // per process; the attribute holds for every device
+  if (done) return EIFE_OK;
+  int r = gemm_attrs<64>();
+  if (r == EIFE_OK) r = gemm_attrs<128>();
+  if (r == EIFE_OK) r = gemm_attrs<256>();
+  if (r == EIFE_OK) r = gemm_attrs<512>();
+  if (r == EIFE_OK) r = gemm_attrs<1024>();
+  if (r == EIFE_OK) done = 1;
+  return r;
+}
+
+template <int KP>
+void gemm_row_go(int mode, bool ac, hipStream_t s, const float* src, float* dst, float* dst2, const RowGeom& rg,
+                 gemm::SMat S, const Forcing& F) {
+  using Sh = gemm::Shape<KP>;
+  const dim3 grid((rg.nrows + Sh::TL - 1) / Sh::TL);
+  const dim3 blk(Sh::THREADS);
+  if (mode == ROW_PHYS && ac)
+    hipLaunchKernelGGL((gemm::gemm_row<KP, ROW_PHYS, true>), grid, blk, Sh::LDS, s, src, dst, dst2, rg, S, F);
+  else if (mode == ROW_PHYS)
+    hipLaunchKernelGGL((gemm::gemm_row<KP, ROW_PHYS, false>), grid, blk, Sh::LDS, s, src, dst, dst2, rg, S, F);
+  else if (mode == ROW_FWD_USER)
+    hipLaunchKernelGGL((gemm::gemm_row<KP, ROW_FWD_USER, false>), grid, blk, Sh::LDS, s, src, dst, dst2, rg, S, F);
+  else
+    hipLaunchKernelGGL((gemm::gemm_row<KP, ROW_INV_USER, false>), grid, blk, Sh::LDS, s, src, dst, dst2, rg, S, F);
+}
+
+template <int KP>
+void gemm_col_go(int mode, int pitch, int outer, hipStream_t s, float* W, float* H, const ColGeom& cg,
+                 gemm::SMat S, const Diag& dg) {
+  using Sh = gemm::Shape<KP>;
+  const dim3 grid((pitch + Sh::TL - 1) / Sh::TL, outer);
+  const dim3 blk(Sh::THREADS);
+  if (mode == COL_PLAIN)
+    hipLaunchKernelGGL((gemm::gemm_col<KP, COL_PLAIN>), grid, blk, Sh::LDS, s, W, H, cg, pitch, S, dg);
+  else if (mode == COL_STAGE_A)
+    hipLaunchKernelGGL((gemm::gemm_col<KP, COL_STAGE_A>), grid, blk, Sh::LDS, s, W, H, cg, pitch, S, dg);
+  else if (mode == COL_STAGE_B)
+    hipLaunchKernelGGL((gemm::gemm_col<KP, COL_STAGE_B>), grid, blk, Sh::LDS, s, W, H, cg, pitch, S, dg);
+  else
+    hipLaunchKernelGGL((gemm::gemm_col<KP, COL_ETD1>), grid, blk, Sh::LDS, s, W, H, cg, pitch, S, dg);
+}
+
+template <typename T>
+bool try_row_gemm(const eife_grid_s* g, int mode, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
+                  const Forcing& F) {
+  if constexpr (sizeof(T) != 4) {
+    return false;
+  } else {
+    if (g->transform != EIFE_TX_GEMM_SPLITBF16) return false;
+    const gemm::SMat S = smat_of(g, 0);
+    const bool ac = F.kind == FK_AC;
+    switch (g->kp[0]) {
+      case 64: gemm_row_go<64>(mode, ac, s, src, dst, dst2, rg, S, F); return true;
+      case 128: gemm_row_go<128>(mode, ac, s, src, dst, dst2, rg, S, F); return true;
+      case 256: gemm_row_go<256>(mode, ac, s, src, dst, dst2, rg, S, F); return true;
+      case 512: gemm_row_go<512>(mode, ac, s, src, dst, dst2, rg, S, F); return true;
+      case 1024: gemm_row_go<1024>(mode, ac, s, src, dst, dst2, rg, S, F); return true;
+    }
+    return false;
+  }
+}
+
+template <typename T>
+bool try_col_gemm(const eife_grid_s* g, int axis, int mode, int outer, hipStream_t s, T* W, T* H, const ColGeom& cg,
+                  const Diag& dg) {
+  if constexpr (sizeof(T) != 4) {
+    return false;
+  } else {
+    if (g->transform != EIFE_TX_GEMM_SPLITBF16) return false;
+    const gemm::SMat S = smat_of(g, axis);
+    switch (g->kp[axis]) {
+      case 64: gemm_col_go<64>(mode, g->pitch, outer, s, W, H, cg, S, dg); return true;
+      case 128: gemm_col_go<128>(mode, g->pitch, outer, s, W, H, cg, S, dg); return true;
+      case 256: gemm_col_go<256>(mode, g->pitch, outer, s, W, H, cg, S, dg); return true;
+      case 512: gemm_col_go<512>(mode, g->pitch, outer, s, W, H, cg, S, dg); return true;
+      case 1024: gemm_col_go<1024>(mode, g->pitch, outer, s, W, H, cg, S, dg); return true;
+    }
+    return false;
+  }
+}
+
 // A launch of one pass over `count` instances shaped like grid `g`.
 struct Batchlet {
   int count = 1;
@@ -499,7 +657,8 @@ int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, i
   const Cx<T>* tw = reinterpret_cast<const Cx<T>*>(g->tw[0]);
   const int pidx = prof_begin(g, mode == ROW_PHYS ? EIFE_PASS_ROW_PHYS
                                  : mode == ROW_FWD_USER ? EIFE_PASS_ROW_FWD : EIFE_PASS_ROW_INV, s);
-  if (!try_row_fast<T>(g, B.var_row, mode, B.count, s, src, dst, dst2, rg, tw, F, ri)) {
+  if (!(B.count == 1 && !ri && try_row_gemm<T>(g, mode, s, src, dst, dst2, rg, F)) &&
+      !try_row_fast<T>(g, B.var_row, mode, B.count, s, src, dst, dst2, rg, tw, F, ri)) {
     const size_t shm = lds_bytes(g, rg.P, rg.pl.L);
     dim3 grid((rg.nrows + 2 * rg.P - 1) / (2 * rg.P), B.count);
     if (ri)
@@ -546,7 +705,8 @@ int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, h
            : mode == COL_STAGE_B ? EIFE_PASS_LAST_B : EIFE_PASS_LAST_ETD1;
   }
   const int pidx = prof_begin(g, kind, s);
-  if (!try_col_fast<T>(g, B.var_col, axis, mode, outer, B.count, s, W, H, cg, tw, dg, ci)) {
+  if (!(B.count == 1 && !ci && try_col_gemm<T>(g, axis, mode, outer, s, W, H, cg, dg)) &&
+      !try_col_fast<T>(g, B.var_col, axis, mode, outer, B.count, s, W, H, cg, tw, dg, ci)) {
     const size_t shm = lds_bytes(g, cg.P, cg.pl.L);
     dim3 grid(g->pitch / (2 * cg.P), outer, B.count);
     if (ci)
@@ -645,6 +805,7 @@ void free_grid(eife_grid_s* g) {
   for (int a = 0; a < 3; ++a) {
     hipFree(g->tw[a]);
     hipFree(g->tab[a]);
+    hipFree(g->smat[a]);
   }
   for (auto& r : g->prof_pending) {
     g->ev_pool.push_back(r.a);
@@ -818,8 +979,16 @@ int eife_set_load(eife_grid g, int kind) {
 
 int eife_set_transform(eife_grid g, int kind) {
   RET_IF(check_grid(g));
-  if (kind == EIFE_TX_GEMM_SPLITBF16) return fail(EIFE_EUNSUPPORTED, "the split-BF16 GEMM transform is not built");
-  if (kind != EIFE_TX_FFT && kind != EIFE_TX_FFT_GENERIC) return fail(EIFE_EINVAL, "unknown transform kind %d", kind);
+  if (kind != EIFE_TX_FFT && kind != EIFE_TX_FFT_GENERIC && kind != EIFE_TX_GEMM_SPLITBF16)
+    return fail(EIFE_EINVAL, "unknown transform kind %d", kind);
+  if (kind == EIFE_TX_GEMM_SPLITBF16) {
+    if (g->dtype != EIFE_F32) return fail(EIFE_EUNSUPPORTED, "the split-BF16 transform takes FP32 grids only");
+    for (int a = 0; a < g->d; ++a)
+      if (g->N[a] > 1024) return fail(EIFE_EUNSUPPORTED, "the split-BF16 transform takes N <= 1024 (N = %d)", g->N[a]);
+    RET_IF(gemm_attrs_all());
+    for (int a = 0; a < 3; ++a)
+      if (!g->smat[a]) RET_IF(build_smat(g, a));
+  }
   g->transform = kind;
   return EIFE_OK;
 }
