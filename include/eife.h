@@ -226,6 +226,81 @@ const char* eife_last_error(void);
 /* ABI version of this library. */
 int eife_version(void);
 
+/* ------------------------------------------------------------------------
+ * Learned corrector (an addition on top of the EIFE2 step of eq. (2.14); not
+ * part of the paper).  One coarse step u_c = EIFE2(u_n, tau_c) is followed by
+ * a convolutional network that predicts the residual towards several fine
+ * steps from u_n: u_{n+1} = u_c + delta.  Per image, with the RMS coarse
+ * change c = sqrt(mean((u_c - u_n)^2)) + 1e-30, the network reads the
+ * channels (u_c, (u_c - u_n) / c) and delta = s_out * c * o.
+ *
+ * Network: six 3x3 convolutions over the interior nodes of a 2D grid (x
+ * fastest), channels 2 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, ReLU after the
+ * first five, zero padding (the homogeneous Dirichlet boundary).  Tap
+ * t = 3 (dy + 1) + (dx + 1) reads the input at (y + dy, x + dx).  The four
+ * 32 -> 32 layers run on the matrix cores with BF16 weights and activations
+ * and FP32 accumulation; the first and last layers in FP32.
+ *
+ * Parameters: EIFE_CORR_PARAMS floats, in order W1 [9][2][32] (tap, input
+ * (u_n, u_c), output), b1 [32]; four times W [9][32][32] (tap, output,
+ * input), b [32]; W6 [9][32] (tap, input), b6 [1].
+ *
+ * Device arrays (un, uc, uf, delta, u) are FP32, [batch][ny][nx] contiguous;
+ * the library keeps no pointer to them after a call.  Calls are asynchronous
+ * on `stream` (NULL = default stream) unless they return host values. */
+#define EIFE_CORR_PARAMS 37889
+typedef struct eife_corr_s* eife_corr;
+
+/* Workspace for images of nx * ny nodes and batches up to max_batch
+ * (activations: 7 arrays of max_batch * nx * ny * 64 bytes).  Parameters
+ * start at zero.  Errors: EIFE_EINVAL, EIFE_ENOMEM, EIFE_EHIP. */
+int eife_corr_create(int nx, int ny, int max_batch, eife_corr* out);
+int eife_corr_destroy(eife_corr c);
+
+/* Copy count = EIFE_CORR_PARAMS FP32 parameters from / to host memory.
+ * Setting them resets the Adam moments and step count.  Blocks the host.
+ * Errors: EIFE_EINVAL (count), EIFE_ENONFINITE (a parameter not finite). */
+int eife_corr_set_params(eife_corr c, const float* host, int64_t count);
+int eife_corr_get_params(eife_corr c, float* host, int64_t count);
+
+/* Output scale s_out > 0 (default 1e-3). */
+int eife_corr_set_scale(eife_corr c, double s_out);
+
+/* delta = s_out * o(un, uc) for `batch` images. */
+int eife_corr_forward(eife_corr c, const float* un, const float* uc, float* delta, int batch, void* stream);
+
+/* Loss = mean over the batch's nodes of (o - (uf - uc) / (s_out c))^2 and its
+ * gradient in the parameters, copied to grad_host (EIFE_CORR_PARAMS floats);
+ * *loss (if loss is not NULL) receives the loss.  Blocks the host. */
+int eife_corr_grad(eife_corr c, const float* un, const float* uc, const float* uf, int batch, float* grad_host,
+                   double* loss, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr >= 0) on
+ * the gradient of the loss above.  With loss != NULL, blocks the host and
+ * stores the batch loss (before the update). */
+int eife_corr_train_step(eife_corr c, const float* un, const float* uc, const float* uf, int batch, double lr,
+                         double* loss, void* stream);
+
+/* Fall back in eife_corr_infer_step whenever the RMS coarse change exceeds
+ * max_change_rms > 0 (fast transients; default: no limit). */
+int eife_corr_set_guard(eife_corr c, double max_change_rms);
+
+/* One corrected step of the single image u (in place): u_c = one step of
+ * `coarse` (f = Allen-Cahn, from t0), delta from the network, and u = u_c +
+ * delta if r = ||delta||_2 / (||u_c - u_n||_2 + 1e-12) <= theta,
+ * max|u| <= 1 + 1e-3 (the maximum bound principle) and the RMS coarse change
+ * is within the guard (eife_corr_set_guard); otherwise u = fine_steps
+ * steps of `fine` from the original u and *fell_back = 1.  out2 (if not
+ * NULL) receives (r, max|u_c + delta|).  Both grids must be FP32 2D grids of
+ * nx * ny nodes with eife_set_phi done (coarse: the coarse step; fine: the
+ * fine step, fine_steps * fine tau = coarse tau).  Blocks the host once to
+ * read the indicator.  Errors: EIFE_EINVAL, errors of eife_step. */
+int eife_corr_infer_step(eife_corr c, eife_grid coarse, eife_grid fine, float* u, double t0, int64_t fine_steps,
+                         double theta, int* fell_back, double* out2, void* stream);
+
+/* Message of the calling thread's most recent failed eife_corr_* call. */
+const char* eife_corr_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

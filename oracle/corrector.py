@@ -9,8 +9,10 @@ the HIP kernels are checked.
 
 Network: six 3x3 convolutions over the interior nodes of a 2D grid, channels
 2 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, ReLU after the first five, zero padding
-(the padded ring is the homogeneous Dirichlet boundary).  Input channels are
-(u_n, u_c); the output o is scaled, delta = s_out * o.
+(the padded ring is the homogeneous Dirichlet boundary).  Per image, with the
+RMS coarse change c = sqrt(mean((u_c - u_n)^2)) + 1e-30, the input channels
+are (u_c, (u_c - u_n) / c) and the output o is scaled, delta = s_out c o: the
+network sees the change at unit scale and answers relative to it.
 
 Arrays are [B][ny][nx][C] (x fastest, channels innermost).  Tap t = 3 (dy + 1)
 + (dx + 1) reads the input at (y + dy, x + dx).  Parameter vector (float):
@@ -64,10 +66,23 @@ def init_params(seed):
     return pack(layers)
 
 
+def change_scale(un, uc):
+    """Per image: c = sqrt(mean over nodes of (u_c - u_n)^2) + 1e-30, shape [B]."""
+    d = np.asarray(uc, np.float64) - np.asarray(un, np.float64)
+    return np.sqrt(np.mean(d * d, axis=(1, 2))) + 1e-30
+
+
+def features(un, uc):
+    """Input channels [B][ny][nx][2]: (u_c, (u_c - u_n) / c)."""
+    un, uc = np.asarray(un, np.float64), np.asarray(uc, np.float64)
+    c = change_scale(un, uc)
+    return np.stack([uc, (uc - un) / c[:, None, None]], axis=-1)
+
+
 def forward(p, un, uc):
     """Network output o [B][ny][nx] and the activations [X0, Y1, ..., Y5]."""
     L = unpack(p)
-    X0 = np.stack([np.asarray(un, np.float64), np.asarray(uc, np.float64)], axis=-1)
+    X0 = features(un, uc)
     acts = [X0]
     W1, b1 = L[0]
     Z = b1 + sum(shift(X0, dy, dx) @ W1[t] for t, (dy, dx) in enumerate(TAPS))
@@ -82,11 +97,18 @@ def forward(p, un, uc):
     return o, acts
 
 
+def delta(p, un, uc, s_out):
+    """The predicted residual delta = s_out c o."""
+    o, _ = forward(p, un, uc)
+    return s_out * change_scale(un, uc)[:, None, None] * o
+
+
 def loss_and_grad(p, un, uc, uf, s_out):
-    """MSE of o against the scaled residual (uf - uc) / s_out, and its gradient in p."""
+    """MSE of o against the scaled residual (uf - uc) / (s_out c), and its gradient in p."""
     o, acts = forward(p, un, uc)
     L = unpack(p)
-    target = (np.asarray(uf, np.float64) - np.asarray(uc, np.float64)) / s_out
+    c = change_scale(un, uc)[:, None, None]
+    target = (np.asarray(uf, np.float64) - np.asarray(uc, np.float64)) / (s_out * c)
     e = o - target
     loss = float(np.mean(e * e))
     g = 2.0 * e / e.size  # dloss/do
@@ -130,10 +152,12 @@ class Adam:
         return p - lr * mh / (np.sqrt(vh) + self.eps)
 
 
-def indicator(un, uc, delta, h):
-    """Acceptance data of one corrected step: (r, max|u_c + delta|) with
-    r = ||delta||_h / (||u_c - u_n||_h + 1e-12), ||v||_h^2 = prod(h) sum v^2."""
-    w = float(np.prod(h))
-    nd = np.sqrt(w * np.sum(np.asarray(delta, np.float64) ** 2))
-    ns = np.sqrt(w * np.sum((np.asarray(uc, np.float64) - np.asarray(un, np.float64)) ** 2))
-    return nd / (ns + 1e-12), float(np.max(np.abs(np.asarray(uc, np.float64) + delta)))
+def indicator(un, uc, delta):
+    """Acceptance data of one corrected step: (r, max|u_c + delta|, c_rms) with
+    r = ||delta||_2 / (||u_c - u_n||_2 + 1e-12) over the nodal values (a mesh
+    weight would cancel in the ratio) and c_rms the RMS coarse change."""
+    d = np.asarray(uc, np.float64) - np.asarray(un, np.float64)
+    nd = np.sqrt(np.sum(np.asarray(delta, np.float64) ** 2))
+    ns = np.sqrt(np.sum(d ** 2))
+    return nd / (ns + 1e-12), float(np.max(np.abs(np.asarray(uc, np.float64) + delta))), \
+        float(np.sqrt(np.mean(d ** 2)))

@@ -7,6 +7,7 @@ the built library every entry point raises.
 """
 from .binding import (  # noqa: F401
     Batch,
+    Corrector,
     EIFEError,
     Grid,
     LOAD_LUMPED,

@@ -63,6 +63,26 @@ def load_library():
     lib.eife_batch_step.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_int, c_double, c_void_p]
     lib.eife_batch_autotune.argtypes = [c_void_p, ctypes.c_char_p, c_void_p]
     lib.eife_batch_class_info.argtypes = [c_void_p, c_int, ctypes.POINTER(ctypes.c_int32)]
+    f32p = ctypes.POINTER(ctypes.c_float)
+    lib.eife_corr_create.argtypes = [c_int, c_int, c_int, ctypes.POINTER(c_void_p)]
+    lib.eife_corr_destroy.argtypes = [c_void_p]
+    lib.eife_corr_set_params.argtypes = [c_void_p, f32p, ctypes.c_int64]
+    lib.eife_corr_get_params.argtypes = [c_void_p, f32p, ctypes.c_int64]
+    lib.eife_corr_set_scale.argtypes = [c_void_p, c_double]
+    lib.eife_corr_set_guard.argtypes = [c_void_p, c_double]
+    lib.eife_corr_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]
+    lib.eife_corr_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, f32p, ctypes.POINTER(c_double),
+                                   c_void_p]
+    lib.eife_corr_train_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double,
+                                         ctypes.POINTER(c_double), c_void_p]
+    lib.eife_corr_infer_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, ctypes.c_int64, c_double,
+                                         ctypes.POINTER(c_int), ctypes.POINTER(c_double), c_void_p]
+    lib.eife_corr_last_error.restype = ctypes.c_char_p
+    lib.eife_corr_last_error.argtypes = []
+    for name in ("eife_corr_create", "eife_corr_destroy", "eife_corr_set_params", "eife_corr_get_params",
+                 "eife_corr_set_scale", "eife_corr_set_guard", "eife_corr_forward", "eife_corr_grad", "eife_corr_train_step",
+                 "eife_corr_infer_step"):
+        getattr(lib, name).restype = c_int
     lib.eife_last_error.restype = ctypes.c_char_p
     lib.eife_last_error.argtypes = []
     lib.eife_version.argtypes = []
@@ -248,3 +268,100 @@ class Batch:
     def views(self, u):
         """Per-instance 2D views of a batched nodal array."""
         return [u[self.offsets[i]:self.offsets[i + 1]].view(self.shapes[i]) for i in range(self.B)]
+
+
+CORR_PARAMS = 37889
+
+
+def _ccheck(lib, code):
+    if code != OK:
+        raise EIFEError(code, lib.eife_corr_last_error().decode(errors="replace"))
+
+
+def _f32_dev(x, shape_tail):
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+        raise TypeError("expected a contiguous float32 CUDA tensor")
+    if tuple(x.shape[-2:]) != shape_tail:
+        raise ValueError(f"expected trailing shape {shape_tail}, got {tuple(x.shape)}")
+    return ctypes.c_void_p(x.data_ptr())
+
+
+class Corrector:
+    """Learned corrector (eife_corr_*): a 6-layer 3x3 convolutional network on
+    (u_n, u_c) that predicts delta with u_{n+1} = u_c + delta.  Images are
+    float32 CUDA tensors of shape (batch, ny, nx) or (ny, nx)."""
+
+    def __init__(self, nx, ny, max_batch=1):
+        self._lib = load_library()
+        self.nx, self.ny, self.max_batch = int(nx), int(ny), int(max_batch)
+        handle = ctypes.c_void_p()
+        _ccheck(self._lib, self._lib.eife_corr_create(self.nx, self.ny, self.max_batch, ctypes.byref(handle)))
+        self._c = handle
+
+    def close(self):
+        if getattr(self, "_c", None):
+            self._lib.eife_corr_destroy(self._c)
+            self._c = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _batch(self, x):
+        return 1 if x.dim() == 2 else int(x.shape[0])
+
+    def set_params(self, p):
+        import numpy as np
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        _ccheck(self._lib, self._lib.eife_corr_set_params(
+            self._c, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(CORR_PARAMS, dtype=np.float32)
+        _ccheck(self._lib, self._lib.eife_corr_get_params(
+            self._c, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+        return a
+
+    def set_scale(self, s_out):
+        _ccheck(self._lib, self._lib.eife_corr_set_scale(self._c, float(s_out)))
+
+    def set_guard(self, max_change_rms):
+        _ccheck(self._lib, self._lib.eife_corr_set_guard(self._c, float(max_change_rms)))
+
+    def forward(self, un, uc, delta=None, stream=None):
+        if delta is None:
+            delta = torch.empty_like(uc)
+        sh = (self.ny, self.nx)
+        _ccheck(self._lib, self._lib.eife_corr_forward(self._c, _f32_dev(un, sh), _f32_dev(uc, sh),
+                                                       _f32_dev(delta, sh), self._batch(un), _stream_ptr(stream)))
+        return delta
+
+    def grad(self, un, uc, uf, stream=None):
+        import numpy as np
+        g = np.empty(CORR_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        sh = (self.ny, self.nx)
+        _ccheck(self._lib, self._lib.eife_corr_grad(self._c, _f32_dev(un, sh), _f32_dev(uc, sh), _f32_dev(uf, sh),
+                                                    self._batch(un), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                    ctypes.byref(loss), _stream_ptr(stream)))
+        return loss.value, g
+
+    def train_step(self, un, uc, uf, lr, want_loss=False, stream=None):
+        loss = ctypes.c_double()
+        sh = (self.ny, self.nx)
+        _ccheck(self._lib, self._lib.eife_corr_train_step(
+            self._c, _f32_dev(un, sh), _f32_dev(uc, sh), _f32_dev(uf, sh), self._batch(un), float(lr),
+            ctypes.byref(loss) if want_loss else None, _stream_ptr(stream)))
+        return loss.value if want_loss else None
+
+    def infer_step(self, coarse, fine, u, t0, fine_steps, theta, stream=None):
+        """One corrected step of u in place; returns (fell_back, r, max|u_c + delta|)."""
+        fb = ctypes.c_int()
+        out2 = (ctypes.c_double * 2)()
+        _ccheck(self._lib, self._lib.eife_corr_infer_step(
+            self._c, coarse._g, fine._g, _f32_dev(u, (self.ny, self.nx)), float(t0), int(fine_steps), float(theta),
+            ctypes.byref(fb), out2, _stream_ptr(stream)))
+        return bool(fb.value), out2[0], out2[1]

@@ -6,7 +6,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libeife.so")
-SOURCES = [os.path.join(PKG, "csrc", "eife.hip")]
+SOURCES = [os.path.join(PKG, "csrc", "eife.hip"), os.path.join(PKG, "csrc", "eife_corr.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -27,16 +27,34 @@ def hipcc():
 
 
 def build(verbose=False):
-    """Compile every HIP source of the package into libeife.so (always rebuilds)."""
+    """Compile every HIP source of the package into libeife.so (always rebuilds).
+
+    The sources are compiled to objects in parallel, then linked."""
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(PKG, os.path.basename(src) + ".o")
+        cmd = [hipcc()] + [f for f in HIPCC_FLAGS if f != "-shared"] + ["-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
+        objs.append(obj)
+    failed = False
+    for p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out)
+            failed = True
+    if failed:
+        raise RuntimeError("hipcc failed building libeife.so")
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-o", tmp] + SOURCES
-    if verbose:
-        print(" ".join(cmd), flush=True)
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         sys.stderr.write(proc.stdout + proc.stderr)
-        raise RuntimeError("hipcc failed building libeife.so")
+        raise RuntimeError("hipcc failed linking libeife.so")
     os.replace(tmp, LIB)
+    for obj in objs:
+        os.remove(obj)
     return LIB
 
 

@@ -352,6 +352,13 @@ void row_fast_go(int mode, int nrows, int count, hipStream_t s, const T* src, T*
     else
       hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_PHYS, fast::RK_GENERIC, BAT>), grid, dim3(NT), 0, s, src,
                          dst, dst2, rg, tw, F, ri);
+  } else if (mode == ROW_FWD_PHYS) {
+    if (F.kind == FK_AC)
+      hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_FWD_PHYS, fast::RK_AC, BAT>), grid, dim3(NT), 0, s, src, dst,
+                         dst2, rg, tw, F, ri);
+    else
+      hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_FWD_PHYS, fast::RK_GENERIC, BAT>), grid, dim3(NT), 0, s, src,
+                         dst, dst2, rg, tw, F, ri);
   } else if (mode == ROW_FWD_USER) {
     hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_FWD_USER, fast::RK_GENERIC, BAT>), grid, dim3(NT), 0, s, src,
                        dst, dst2, rg, tw, F, ri);
@@ -370,7 +377,14 @@ void row_fast_launch(int var, int mode, int nrows, int count, hipStream_t s, con
     else
       row_fast_go<T, L, row_pb<T, L>(1), true>(mode, nrows, count, s, src, dst, dst2, rg, tw, F, ri);
   } else {
-    row_fast_go<T, L, row_pb<T, L>(0), false>(mode, nrows, count, s, src, dst, dst2, rg, tw, F, ri);
+    // a single grid with few rows (2D grids up to N = 512): fewer pairs per
+    // block so that the launch spreads over the compute units
+    constexpr int pb0 = row_pb<T, L>(0);
+    constexpr int pbs = std::max(1, pb0 / 4);
+    if ((nrows + 2 * pb0 - 1) / (2 * pb0) < g_cus)
+      row_fast_go<T, L, pbs, false>(mode, nrows, count, s, src, dst, dst2, rg, tw, F, ri);
+    else
+      row_fast_go<T, L, pb0, false>(mode, nrows, count, s, src, dst, dst2, rg, tw, F, ri);
   }
 }
 
@@ -409,7 +423,13 @@ void col_fast_launch(int var, int mode, int pitch, int outer, int count, hipStre
     else
       col_fast_go<T, L, col_pb<T, L>(1), true>(mode, pitch, outer, count, false, s, W, H, cg, tw, dg, ci);
   } else {
-    col_fast_go<T, L, col_pb<T, L>(0), false>(mode, pitch, outer, count, true, s, W, H, cg, tw, dg, ci);
+    // a single grid with few column tiles (2D grids): narrower tiles
+    constexpr int pb0 = col_pb<T, L>(0);
+    constexpr int pbs = std::max(1, pb0 / 8);
+    if ((pitch / (2 * pb0)) * outer < g_cus)
+      col_fast_go<T, L, pbs, false>(mode, pitch, outer, count, true, s, W, H, cg, tw, dg, ci);
+    else
+      col_fast_go<T, L, pb0, false>(mode, pitch, outer, count, true, s, W, H, cg, tw, dg, ci);
   }
 }
 
@@ -632,6 +652,13 @@ bool try_col_gemm(const eife_grid_s* g, int axis, int mode, int outer, hipStream
   }
 }
 
+// The first reaction of a run is fused into the forward row pass of the
+// prologue (ROW_FWD_PHYS) wherever the specialised row kernels run.
+template <typename T>
+bool fused_first_row(const eife_grid_s* g) {
+  return g->transform == EIFE_TX_FFT && fast_len<T>(g->N[0]);
+}
+
 // A launch of one pass over `count` instances shaped like grid `g`.
 struct Batchlet {
   int count = 1;
@@ -656,7 +683,9 @@ int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, i
   const RowInst<T>* ri = static_cast<const RowInst<T>*>(B.rinst);
   const Cx<T>* tw = reinterpret_cast<const Cx<T>*>(g->tw[0]);
   const int pidx = prof_begin(g, mode == ROW_PHYS ? EIFE_PASS_ROW_PHYS
-                                 : mode == ROW_FWD_USER ? EIFE_PASS_ROW_FWD : EIFE_PASS_ROW_INV, s);
+                                 : (mode == ROW_FWD_USER || mode == ROW_FWD_PHYS) ? EIFE_PASS_ROW_FWD
+                                                                                   : EIFE_PASS_ROW_INV, s);
+  if (mode == ROW_FWD_PHYS && !fused_first_row<T>(g)) return fail(EIFE_EUNSUPPORTED, "fused first row pass");
   if (!(B.count == 1 && !ri && try_row_gemm<T>(g, mode, s, src, dst, dst2, rg, F)) &&
       !try_row_fast<T>(g, B.var_row, mode, B.count, s, src, dst, dst2, rg, tw, F, ri)) {
     const size_t shm = lds_bytes(g, rg.P, rg.pl.L);
@@ -733,13 +762,16 @@ int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipS
   const bool three = g->d == 3;
   const int last = three ? 2 : 1;
   const Forcing F0 = make_forcing(g, f_kind, t0);
-  // prologue: W = S_x u, H = S u
-  RET_IF(launch_row<T>(g, ROW_FWD_USER, u, g->n[0], W, g->pitch, H, F0, s));
+  // prologue: H = S u and W = S_x u, or W = S_x f(t0, u) when the first
+  // reaction is fused in
+  const bool fused = n_steps > 0 && fused_first_row<T>(g);
+  RET_IF(launch_row<T>(g, fused ? ROW_FWD_PHYS : ROW_FWD_USER, u, g->n[0], W, g->pitch, H, F0, s));
   if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, H, H, dg, s));
   RET_IF(launch_col<T>(g, last, COL_PLAIN, H, H, dg, s));
   for (int64_t st = 0; st < n_steps; ++st) {
     const double tn = t0 + double(st) * g->tau;
-    RET_IF(launch_row<T>(g, ROW_PHYS, W, g->pitch, W, g->pitch, nullptr, make_forcing(g, f_kind, tn), s));
+    if (!(fused && st == 0))
+      RET_IF(launch_row<T>(g, ROW_PHYS, W, g->pitch, W, g->pitch, nullptr, make_forcing(g, f_kind, tn), s));
     if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, W, H, dg, s));
     RET_IF(launch_col<T>(g, last, g->stages == 1 ? COL_ETD1 : COL_STAGE_A, W, H, dg, s));
     if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, W, H, dg, s));
@@ -1152,11 +1184,14 @@ Batchlet class_batchlet(const eife_batch_s::Class& c, bool on_h) {
 
 // One EIFE step (both stages) of class c at time tn.
 template <typename T>
-int class_step(eife_batch_s* b, const eife_batch_s::Class& c, int f_kind, double tn, hipStream_t s) {
+int class_step(eife_batch_s* b, const eife_batch_s::Class& c, int f_kind, double tn, hipStream_t s,
+               bool first_row_done = false) {
   eife_grid_s* g = b->inst[c.members[0]];
   const Batchlet B = class_batchlet(c, false);
   const Diag dg = make_diag(g);
-  RET_IF(launch_row<T>(g, ROW_PHYS, nullptr, g->pitch, nullptr, g->pitch, nullptr, make_forcing(g, f_kind, tn), s, B));
+  if (!first_row_done)
+    RET_IF(launch_row<T>(g, ROW_PHYS, nullptr, g->pitch, nullptr, g->pitch, nullptr, make_forcing(g, f_kind, tn), s,
+                         B));
   RET_IF(launch_col<T>(g, 1, g->stages == 1 ? COL_ETD1 : COL_STAGE_A, nullptr, nullptr, dg, s, B));
   if (g->stages == 2) {
     RET_IF(launch_row<T>(g, ROW_PHYS, nullptr, g->pitch, nullptr, g->pitch, nullptr,
@@ -1171,12 +1206,14 @@ int batch_enqueue(eife_batch_s* b, T* u, int64_t n_steps, int f_kind, double t0,
   for (auto& c : b->classes) {
     eife_grid_s* g = b->inst[c.members[0]];
     const Batchlet B = class_batchlet(c, false);
-    RET_IF(launch_row<T>(g, ROW_FWD_USER, u, g->n[0], nullptr, g->pitch, nullptr, make_forcing(g, f_kind, t0), s, B));
+    const int mode = (n_steps > 0 && fused_first_row<T>(g)) ? ROW_FWD_PHYS : ROW_FWD_USER;
+    RET_IF(launch_row<T>(g, mode, u, g->n[0], nullptr, g->pitch, nullptr, make_forcing(g, f_kind, t0), s, B));
     RET_IF(launch_col<T>(g, 1, COL_PLAIN, nullptr, nullptr, make_diag(g), s, class_batchlet(c, true)));
   }
   for (int64_t st = 0; st < n_steps; ++st) {
     const double tn = t0 + double(st) * b->inst[0]->tau;
-    for (auto& c : b->classes) RET_IF(class_step<T>(b, c, f_kind, tn, s));
+    for (auto& c : b->classes)
+      RET_IF(class_step<T>(b, c, f_kind, tn, s, st == 0 && fused_first_row<T>(b->inst[c.members[0]])));
   }
   for (auto& c : b->classes) {
     eife_grid_s* g = b->inst[c.members[0]];

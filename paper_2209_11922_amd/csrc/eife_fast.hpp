@@ -405,10 +405,10 @@ __global__ void __launch_bounds__((PB * Line<T, L>::LP), (MinWaves<T, L>::value)
   twl.load(tw, lane);
   Cx<T>* my = lds + p * BUF;
 
+  T va[RIT], vb[RIT];
   {
     const T* sa = src + int64_t(ra) * g.ld_src + lane;
     const T* sb = src + int64_t(rb) * g.ld_src + lane;
-    T va[RIT], vb[RIT];
 #pragma unroll
     for (int t = 0; t < RIT; ++t) {
       const bool in = lane + LP * t < n;
@@ -423,6 +423,37 @@ __global__ void __launch_bounds__((PB * Line<T, L>::LP), (MinWaves<T, L>::value)
 
   typename Ln::Regs v;
   Ln::transform(v, my, my, lane, twl, tw);
+
+  if (MODE == ROW_FWD_PHYS) {
+    // dst2 = S_x u; then the reaction of the loaded nodal values, forward
+    Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+    wave_sync();
+    {
+      T* ha = dst2 + int64_t(ra) * g.ld_dst + lane;
+      T* hb = dst2 + int64_t(rb) * g.ld_dst + lane;
+      Cx<T> hv[RIT];
+#pragma unroll
+      for (int t = 0; t < RIT; ++t) hv[t] = my[lane + LP * t];
+#pragma unroll
+      for (int t = 0; t < RIT; ++t) {
+        if (lane + LP * t < n) {
+          if (hasa) ha[LP * t] = hv[t].re;
+          if (hasb) hb[LP * t] = hv[t].im;
+        }
+      }
+    }
+    wave_sync();
+    const int iya = ra % g.ny, iza = ra / g.ny;
+    const int iyb = rb % g.ny, izb = rb / g.ny;
+#pragma unroll
+    for (int t = 0; t < RIT; ++t) {
+      const int m = lane + LP * t;
+      if (m < n)
+        my[m] = Cx<T>{reaction_k<T, RK>(F, va[t], m, iya, iza), reaction_k<T, RK>(F, vb[t], m, iyb, izb)};
+    }
+    wave_sync();
+    Ln::transform(v, my, my, lane, twl, tw);
+  }
 
   if (MODE == ROW_PHYS) {
     const int iya = ra % g.ny, iza = ra / g.ny;

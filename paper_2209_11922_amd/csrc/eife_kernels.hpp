@@ -270,7 +270,9 @@ __device__ __forceinline__ T reaction(const Forcing& F, T u, int ix, int iy, int
 // ---------------------------------------------------------------------------
 // Row passes: lines along x (contiguous).  A block handles 2P rows, pair p =
 // rows (r0 + 2p, r0 + 2p + 1).
-enum RowMode { ROW_PHYS = 0, ROW_FWD_USER = 1, ROW_INV_USER = 2 };
+// ROW_FWD_PHYS (specialised kernels only): from the nodal values u, dst2 =
+// S_x u and dst = S_x f(u) in one pass (the first reaction of a run).
+enum RowMode { ROW_PHYS = 0, ROW_FWD_USER = 1, ROW_INV_USER = 2, ROW_FWD_PHYS = 3 };
 
 struct RowGeom {
   int n;         // line length (interior nodes along x)
@@ -301,7 +303,7 @@ __device__ __forceinline__ void row_inst_ptrs(const RowInst<T>* insts, const T*&
   if (!insts) return;
   const RowInst<T>& I = insts[blockIdx.y];
   F.D = I.D;
-  if (MODE == ROW_FWD_USER) {
+  if (MODE == ROW_FWD_USER || MODE == ROW_FWD_PHYS) {
     src = src + I.uoff;
     dst = I.W;
     dst2 = I.H;

@@ -1,0 +1,226 @@
+"""Corrector kernels (eife_corr_*) against the FP64 NumPy reference.
+
+Tolerances come from the arithmetic: the 32 -> 32 layers round weights and
+activations to BF16 (relative 2^-9 per rounding), accumulate in FP32.
+Against the plain FP64 reference the network output agrees to a few 1e-3
+(relative 2-norm); against the same reference with BF16 rounding applied at
+the points where the kernels round (weights of the 32 -> 32 and output
+layers, the five stored activations) only accumulation order and rare rounding-boundary flips
+remain.  Gradients (BF16 backward) are compared per layer.
+"""
+import numpy as np
+import pytest
+
+import seeded_inputs
+from oracle import corrector as cr
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2209_11922_amd as eife
+    return eife
+
+
+def _bf16(a):
+    """Round to the nearest BF16 (ties to even), returned as float64."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _forward_bf16(p, un, uc):
+    """The reference forward with the kernels' rounding points."""
+    L = cr.unpack(p)
+    X0 = cr.features(un, uc)
+    W1, b1 = L[0]
+    Y = _bf16(np.maximum(b1 + sum(cr.shift(X0, dy, dx) @ W1[t] for t, (dy, dx) in enumerate(cr.TAPS)), 0))
+    for W, b in L[1:1 + cr.N_MID]:
+        Wb = _bf16(W)
+        Y = _bf16(np.maximum(b + sum(cr.shift(Y, dy, dx) @ Wb[t].T for t, (dy, dx) in enumerate(cr.TAPS)), 0))
+    W6, b6 = L[-1]
+    W6 = _bf16(W6)
+    return b6[0] + sum(cr.shift(Y, dy, dx) @ W6[t] for t, (dy, dx) in enumerate(cr.TAPS))
+
+
+def _smooth(rng, B, ny, nx, k=4):
+    """Random fields made of the first k x k sine modes (the shape of the
+    network's inputs: smooth states and smooth coarse changes)."""
+    y = (np.arange(ny) + 1) / (ny + 1)
+    x = (np.arange(nx) + 1) / (nx + 1)
+    out = np.zeros((B, ny, nx))
+    for b in range(B):
+        a = rng.standard_normal((k, k)) / (1 + np.add.outer(np.arange(k), np.arange(k)))
+        out[b] = np.sin(np.pi * np.outer(y, np.arange(1, k + 1))) @ a @ np.sin(np.pi * np.outer(np.arange(1, k + 1), x))
+    return out
+
+
+def _data(seed, B, ny, nx):
+    rng = np.random.default_rng(seed)
+    un = np.tanh(3 * _smooth(rng, B, ny, nx))
+    uc = un + 0.05 * _smooth(rng, B, ny, nx)
+    uf = uc + 1e-3 * _smooth(rng, B, ny, nx)
+    return un, uc, uf
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    return (cr.init_params(seed) + 0.02 * rng.standard_normal(cr.N_PARAMS)).astype(np.float32)
+
+
+def _dev(a):
+    return torch.tensor(np.asarray(a, np.float32), device="cuda")
+
+
+def _rel2(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+SHAPES = [pytest.param(2, 13, 37, id="b2-13x37-ragged"), pytest.param(1, 40, 64, id="b1-40x64"),
+          pytest.param(3, 5, 7, id="b3-5x7-tiny")]
+
+
+@pytest.mark.parametrize("B,ny,nx", SHAPES)
+def test_forward_matches_reference(B, ny, nx):
+    eife = _lib()
+    p = _params(1)
+    un, uc, _ = _data(2, B, ny, nx)
+    c = eife.Corrector(nx, ny, B)
+    c.set_params(p)
+    c.set_scale(0.01)
+    d = c.forward(_dev(un), _dev(uc))
+    torch.cuda.synchronize()
+    unf, ucf = np.float32(un).astype(np.float64), np.float32(uc).astype(np.float64)
+    got = d.cpu().numpy().astype(np.float64) / (0.01 * cr.change_scale(unf, ucf)[:, None, None])
+    ref64, _ = cr.forward(p.astype(np.float64), unf, ucf)
+    refbf = _forward_bf16(p.astype(np.float64), unf, ucf)
+    e64, ebf = _rel2(got, ref64), _rel2(got, refbf)
+    print(f"forward {B}x{ny}x{nx}: rel 2-norm vs FP64 {e64:.2e}, vs BF16-rounded reference {ebf:.2e}")
+    assert ebf <= 2e-3
+    assert e64 <= 2e-2
+    c.close()
+
+
+@pytest.mark.parametrize("B,ny,nx", SHAPES[:2])
+def test_gradient_matches_reference(B, ny, nx):
+    eife = _lib()
+    p = _params(3)
+    un, uc, uf = _data(4, B, ny, nx)
+    s = 0.02
+    c = eife.Corrector(nx, ny, B)
+    c.set_params(p)
+    c.set_scale(s)
+    loss, g = c.grad(_dev(un), _dev(uc), _dev(uf))
+    f = lambda a: np.float32(a).astype(np.float64)  # noqa: E731
+    rloss, rg = cr.loss_and_grad(p.astype(np.float64), f(un), f(uc), f(uf), s)
+    assert abs(loss - rloss) <= 2e-2 * rloss
+    bounds = np.cumsum([0] + cr.SIZES)
+    for k, (lo, hi) in enumerate(zip(bounds[:-1], bounds[1:])):
+        e = _rel2(g[lo:hi].astype(np.float64), rg[lo:hi])
+        print(f"grad block {k} ({hi - lo} values): rel 2-norm {e:.2e}")
+        assert e <= 5e-2, k
+    cos = float(np.dot(g, rg) / (np.linalg.norm(g) * np.linalg.norm(rg)))
+    assert cos >= 0.999
+    # deterministic: the same call gives the same bits
+    loss2, g2 = c.grad(_dev(un), _dev(uc), _dev(uf))
+    assert loss2 == loss and np.array_equal(g, g2)
+    c.close()
+
+
+def test_first_adam_step_closed_form():
+    """After set_params the first step moves each parameter by -lr g / (|g| + eps)."""
+    eife = _lib()
+    B, ny, nx = 2, 9, 20
+    p = _params(5)
+    un, uc, uf = (_dev(a) for a in _data(6, B, ny, nx))
+    c = eife.Corrector(nx, ny, B)
+    c.set_params(p)
+    c.set_scale(0.02)
+    _, g = c.grad(un, uc, uf)
+    c.train_step(un, uc, uf, 1e-3)
+    got = c.get_params().astype(np.float64)
+    g = g.astype(np.float64)
+    ref = p.astype(np.float64) - 1e-3 * g / (np.abs(g) + 1e-8)
+    assert np.max(np.abs(got - ref)) <= 1e-6
+    c.close()
+
+
+def test_training_reduces_the_loss():
+    eife = _lib()
+    B, ny, nx = 4, 24, 32
+    un, uc, uf = (_dev(a) for a in _data(7, B, ny, nx))
+    c = eife.Corrector(nx, ny, B)
+    c.set_params(cr.init_params(8).astype(np.float32))
+    c.set_scale(1e-3)
+    losses = [c.train_step(un, uc, uf, 2e-3, want_loss=True) for _ in range(60)]
+    print(f"loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    assert losses[-1] < 0.5 * losses[0]
+    c.close()
+
+
+def test_infer_step_accepts_and_falls_back():
+    eife = _lib()
+    n = 64
+    N, h = [n, n], [1.0 / n] * 2
+    D = 4e-4
+    coarse = eife.Grid(N, h, D, "f32")
+    coarse.set_phi(0.016, 2)
+    fine = eife.Grid(N, h, D, "f32")
+    fine.set_phi(0.002, 2)
+    u0 = _dev(seeded_inputs.uniform_field(9, N))
+    c = eife.Corrector(n - 1, n - 1, 1)
+    # zero network: delta = 0, the step is the plain coarse step and is accepted
+    c.set_params(np.zeros(cr.N_PARAMS, np.float32))
+    u = u0.clone()
+    fb, r, umax = c.infer_step(coarse, fine, u, 0.0, 8, 0.5)
+    ref = u0.clone()
+    coarse.step(ref, 1, eife.F_ALLEN_CAHN, 0.0)
+    torch.cuda.synchronize()
+    assert not fb and r == 0.0 and torch.equal(u, ref)
+    assert umax == pytest.approx(float(ref.abs().max()), rel=1e-7)
+    # a constant output bias: delta = c everywhere, r = 1 -> rejected -> 8 fine steps
+    p = np.zeros(cr.N_PARAMS, np.float32)
+    p[-1] = 1000.0
+    c.set_params(p)
+    u = u0.clone()
+    fb, r, _ = c.infer_step(coarse, fine, u, 0.0, 8, 0.5)
+    ref = u0.clone()
+    fine.step(ref, 8, eife.F_ALLEN_CAHN, 0.0)
+    torch.cuda.synchronize()
+    assert fb and r > 0.5 and torch.equal(u, ref)
+    # the transient guard: zero network but a tiny bound on the coarse change -> fine steps
+    c.set_params(np.zeros(cr.N_PARAMS, np.float32))
+    c.set_guard(1e-9)
+    u = u0.clone()
+    fb, r, _ = c.infer_step(coarse, fine, u, 0.0, 8, 0.5)
+    torch.cuda.synchronize()
+    assert fb and r == 0.0 and torch.equal(u, ref)
+    for g in (coarse, fine):
+        g.close()
+    c.close()
+
+
+def test_corrector_argument_errors():
+    eife = _lib()
+    with pytest.raises(eife.EIFEError):
+        eife.Corrector(0, 5, 1)
+    c = eife.Corrector(8, 6, 2)
+    with pytest.raises(eife.EIFEError):
+        c.set_params(np.zeros(10, np.float32))
+    bad = np.zeros(cr.N_PARAMS, np.float32)
+    bad[3] = np.nan
+    with pytest.raises(eife.EIFEError) as e:
+        c.set_params(bad)
+    assert e.value.code == -6
+    with pytest.raises(eife.EIFEError):
+        c.set_scale(0.0)
+    with pytest.raises(eife.EIFEError):
+        c.set_guard(-1.0)
+    x = torch.zeros(3, 6, 8, device="cuda")
+    with pytest.raises(eife.EIFEError):
+        c.forward(x, x)  # batch 3 > max_batch 2
+    with pytest.raises(ValueError):
+        c.forward(torch.zeros(6, 9, device="cuda"), torch.zeros(6, 9, device="cuda"))
+    c.close()

@@ -44,7 +44,8 @@ def test_forward_matches_scipy_correlate2d():
     o, acts = cr.forward(p, un, uc)
     L = cr.unpack(p)
     B = un.shape[0]
-    X = np.stack([un, uc], -1)
+    c = np.sqrt(np.mean((uc - un) ** 2, axis=(1, 2))) + 1e-30
+    X = np.stack([uc, (uc - un) / c[:, None, None]], -1)
     W1, b1 = L[0]
     Y = np.zeros(un.shape + (cr.C,))
     for b in range(B):
@@ -109,6 +110,18 @@ def test_indicator_hand_case():
     un = np.zeros((2, 2))
     uc = np.array([[0.5, 0.0], [0.0, 0.0]])
     delta = np.array([[0.0, 0.1], [0.0, 0.0]])
-    r, umax = cr.indicator(un, uc, delta, [0.25, 0.5])
+    r, umax, crms = cr.indicator(un, uc, delta)
     assert r == pytest.approx(0.1 / 0.5, rel=1e-10)
     assert umax == 0.5
+    assert crms == pytest.approx(0.25, rel=1e-12)
+
+
+def test_output_is_relative_to_the_coarse_change():
+    """Scaling the change u_c - u_n by k (same u_c) leaves the features but the
+    scale c, so delta scales by k."""
+    un, uc, _ = _data(9)
+    p = _params(10)
+    un2 = uc - 3.0 * (uc - un)
+    d1 = cr.delta(p, un, uc, 0.1)
+    d2 = cr.delta(p, un2, uc, 0.1)
+    assert np.allclose(d2, 3.0 * d1, rtol=1e-12, atol=1e-15)
