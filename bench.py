@@ -91,6 +91,27 @@ def cpu_baseline(u0, N, h, D, budget_s=15.0, max_steps=20):
                       f"(scipy.fft.dstn type-I, workers={cores}), {dt:.2f} s"}
 
 
+def corrector_comparison(nseeds):
+    """Learned corrector vs plain EIFE2 at equal L2 error (2D Allen-Cahn, eps 0.02,
+    511^2 DoFs, coarse tau 0.016, fine 0.002, 500 coarse steps, unseen seeds 1000...)."""
+    from paper_2209_11922_amd import corrector as cor
+    from paper_2209_11922_amd.binding import Corrector
+    path = os.path.join(ROOT, "paper_2209_11922_amd", "weights", "corrector_ac512.npz")
+    p, s_out, theta, guard = cor.load(path)
+    net = Corrector(511, 511, 1)
+    net.set_params(p)
+    net.set_scale(s_out)
+    t0 = time.perf_counter()
+    summ = cor.compare(net, list(range(1000, 1000 + nseeds)), 500, theta, guard)
+    net.close()
+    comp = summ.get("plain_competitor")
+    log(f"bench: corrector {summ['corrector']['fine_equiv_dof_steps_per_s']:.4e} fine-equivalent DoF-steps/s, "
+        f"max L2 {summ['corrector']['max_L2']:.2e}; competitor {comp} "
+        f"{summ[comp]['fine_equiv_dof_steps_per_s'] if comp else float('nan'):.4e}, "
+        f"max L2 {summ[comp]['max_L2'] if comp else float('nan'):.2e} ({time.perf_counter() - t0:.1f} s)")
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +122,9 @@ def main():
                     help="cube: 3D Allen-Cahn 255^3 (default line); batched: 512 independent 2D instances")
     ap.add_argument("--transform", choices=["fft", "gemm"], default="fft",
                     help="cube workload: FFT sine transforms (default) or split-BF16 matrix-core products")
+    ap.add_argument("--no-corrector", action="store_true",
+                    help="skip the learned-corrector comparison (2D Allen-Cahn 511^2, plain vs corrected EIFE2)")
+    ap.add_argument("--corr-seeds", type=int, default=3, help="unseen seeds of the corrector comparison")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain device copy of one work array's size (counter calibration)")
     args = ap.parse_args()
@@ -184,6 +208,10 @@ def main():
                         "frac": round(tfs / BF16_PEAK_TFS, 4), "flops_per_launch": flops}
         log(f"  dominant pass {dom[1]}: {tfs:.1f} TFLOP/s BF16 ({tfs / BF16_PEAK_TFS * 100:.1f}% of dense peak)")
 
+    corr = None
+    if not args.no_corrector and not gemm:
+        corr = corrector_comparison(args.corr_seeds)
+
     cpu = None
     if not args.no_cpu and not gemm:
         cpu = cpu_baseline(u0, N, h, D)
@@ -196,7 +224,7 @@ def main():
                                   "u0 uniform[-0.9,0.9] seed 0, EIFE2 c2=1/2 tau=0.005, "
                                   + ("split-BF16 matrix-core sine transforms" if gemm else "FP32 sine-transform path"),
                       "dofs": ndof, "tau": TAU, "scheme": "EIFE2", "transform": args.transform},
-           "roofline": roof, "cpu_baseline": cpu}
+           "roofline": roof, "cpu_baseline": cpu, "corrector": corr}
     print(json.dumps(out), flush=True)
     g.close()
 

@@ -298,6 +298,12 @@ int eife_corr_set_guard(eife_corr c, double max_change_rms);
 int eife_corr_infer_step(eife_corr c, eife_grid coarse, eife_grid fine, float* u, double t0, int64_t fine_steps,
                          double theta, int* fell_back, double* out2, void* stream);
 
+/* n_steps corrected steps of u (eife_corr_infer_step at t0 + k tau_coarse,
+ * k = 0 .. n_steps - 1) in one call; *fallbacks receives the number of steps
+ * that fell back to the fine steps.  Blocks the host once per step. */
+int eife_corr_run(eife_corr c, eife_grid coarse, eife_grid fine, float* u, double t0, double tau_coarse,
+                  int64_t n_steps, int64_t fine_steps, double theta, int64_t* fallbacks, void* stream);
+
 /* Message of the calling thread's most recent failed eife_corr_* call. */
 const char* eife_corr_last_error(void);
 

@@ -77,11 +77,13 @@ def load_library():
                                          ctypes.POINTER(c_double), c_void_p]
     lib.eife_corr_infer_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, ctypes.c_int64, c_double,
                                          ctypes.POINTER(c_int), ctypes.POINTER(c_double), c_void_p]
+    lib.eife_corr_run.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, ctypes.c_int64,
+                                  ctypes.c_int64, c_double, ctypes.POINTER(ctypes.c_int64), c_void_p]
     lib.eife_corr_last_error.restype = ctypes.c_char_p
     lib.eife_corr_last_error.argtypes = []
     for name in ("eife_corr_create", "eife_corr_destroy", "eife_corr_set_params", "eife_corr_get_params",
                  "eife_corr_set_scale", "eife_corr_set_guard", "eife_corr_forward", "eife_corr_grad", "eife_corr_train_step",
-                 "eife_corr_infer_step"):
+                 "eife_corr_infer_step", "eife_corr_run"):
         getattr(lib, name).restype = c_int
     lib.eife_last_error.restype = ctypes.c_char_p
     lib.eife_last_error.argtypes = []
@@ -365,3 +367,11 @@ class Corrector:
             self._c, coarse._g, fine._g, _f32_dev(u, (self.ny, self.nx)), float(t0), int(fine_steps), float(theta),
             ctypes.byref(fb), out2, _stream_ptr(stream)))
         return bool(fb.value), out2[0], out2[1]
+
+    def run(self, coarse, fine, u, t0, tau_coarse, n_steps, fine_steps, theta, stream=None):
+        """n_steps corrected steps of u in place (native loop); returns the number of fallbacks."""
+        fb = ctypes.c_int64()
+        _ccheck(self._lib, self._lib.eife_corr_run(
+            self._c, coarse._g, fine._g, _f32_dev(u, (self.ny, self.nx)), float(t0), float(tau_coarse),
+            int(n_steps), int(fine_steps), float(theta), ctypes.byref(fb), _stream_ptr(stream)))
+        return fb.value

@@ -260,10 +260,7 @@ def evaluate(net, seed, steps, theta, N=512, eps=0.02, tau_c=0.016, ratio=8, pla
     u = u0.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fbs = 0
-    for k in range(steps):
-        fb, _, _ = net.infer_step(coarse, fine, u, k * tau_c, ratio, theta)
-        fbs += int(fb)
+    fbs = net.run(coarse, fine, u, 0.0, tau_c, steps, ratio, theta)
     torch.cuda.synchronize()
     out["corrector"] = {"tau": tau_c, "max_L2": emax, "final_L2": efin, "wall_s": time.perf_counter() - t0,
                         "fallbacks": fbs, "fallbacks_in_error_run": fb_eval}
@@ -275,3 +272,31 @@ def evaluate(net, seed, steps, theta, N=512, eps=0.02, tau_c=0.016, ratio=8, pla
         if isinstance(rec, dict) and "wall_s" in rec:
             rec["fine_equiv_dof_steps_per_s"] = n * n * fine_steps / rec["wall_s"]
     return out
+
+
+def compare(net, seeds, steps, theta, guard, N=512, eps=0.02, tau_c=0.016, ratio=8, bound=1e-4):
+    """The corrector against plain EIFE2 at equal error over several seeds.
+
+    The plain competitor is the largest tau_c / r (r in 1, 2, 4) whose
+    max-over-time L2 error stays within `bound` on every seed; throughputs are
+    fine-equivalent DoF-steps/s (simulated time / tau_f fine steps per wall
+    second) of each seed's bare trajectory, averaged in time over the seeds."""
+    evs = [evaluate(net, s, steps, theta, N, eps, tau_c, ratio, guard=guard) for s in seeds]
+    keys = [k for k, v in evs[0].items() if isinstance(v, dict) and "max_L2" in v]
+    summ = {"seeds": list(seeds), "steps": steps, "T": steps * tau_c, "bound_L2": bound, "dofs": evs[0]["dofs"],
+            "tau_fine": tau_c / ratio, "tau_coarse": tau_c}
+    for k in keys:
+        wall = sum(e[k]["wall_s"] for e in evs)
+        summ[k] = {"tau": evs[0][k]["tau"], "max_L2": max(e[k]["max_L2"] for e in evs),
+                   "fine_equiv_dof_steps_per_s": evs[0]["dofs"] * steps * ratio * len(evs) / wall,
+                   "us_per_coarse_interval": wall / (len(evs) * steps) * 1e6}
+        if k == "corrector":
+            summ[k]["fallbacks"] = [e[k]["fallbacks"] for e in evs]
+    ok = [k for k in keys if k.startswith("plain") and summ[k]["max_L2"] <= bound]
+    comp = max(ok, key=lambda k: summ[k]["tau"]) if ok else None
+    summ["plain_competitor"] = comp
+    if comp:
+        summ["speedup_vs_competitor"] = (summ["corrector"]["fine_equiv_dof_steps_per_s"]
+                                         / summ[comp]["fine_equiv_dof_steps_per_s"])
+    summ["corrector_within_bound"] = summ["corrector"]["max_L2"] <= bound
+    return summ

@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -145,7 +146,10 @@ __global__ void __launch_bounds__(256) conv_in_fwd(const float* __restrict__ un,
 //              Wk rows 1..15 are zero)
 //   OUT_TRAIN  e = D[0] + b6 - (uf - uc) / (s_out c_b); out = 2 e / count;
 //              per-block sum of e^2 in loss_part[blockIdx.x]
-enum { CONV_FWD = 0, CONV_BWD = 1, OUT_INFER = 2, OUT_TRAIN = 3 };
+//   CONV_FIRST as CONV_FWD for the second layer, with the first layer (FP32,
+//              from un, uc, c_b and its weights w1) computed on the patch in
+//              LDS instead of read from memory
+enum { CONV_FWD = 0, CONV_BWD = 1, OUT_INFER = 2, OUT_TRAIN = 3, CONV_FIRST = 4 };
 
 constexpr int kPr = 4, kPx = 64;              // patch rows / nodes
 constexpr int kHr = kPr + 2, kHx = kPx + 2;   // with halo
@@ -158,25 +162,37 @@ __global__ void __launch_bounds__(256) conv_patch(const __bf16* __restrict__ X, 
                                                   const float* __restrict__ cs, const float* __restrict__ uc,
                                                   const float* __restrict__ uf,
                                                   double* __restrict__ loss_part, double inv_count, int nx, int ny,
-                                                  int64_t npatch) {
-  constexpr int NMT = (MODE == CONV_FWD || MODE == CONV_BWD) ? 2 : 1;
+                                                  int64_t npatch, const float* __restrict__ un,
+                                                  const float* __restrict__ w1) {
+  constexpr int NMT = (MODE == CONV_FWD || MODE == CONV_BWD || MODE == CONV_FIRST) ? 2 : 1;
+  constexpr bool FIRST = MODE == CONV_FIRST;
+  constexpr int FR = kHr + 2, FX = kHx + 2;  // nodal inputs around the halo patch (first layer)
   __shared__ __attribute__((aligned(16))) __bf16 sp[kHr * kHx * kNs];
+  __shared__ __attribute__((aligned(16))) __bf16 ws[9 * 16 * NMT * C];
+  __shared__ __attribute__((aligned(16))) float fs[FIRST ? 2 * FR * FX : 1];
+  __shared__ __attribute__((aligned(16))) float w1s[FIRST ? SZ_L1 : 1];
   __shared__ double red[256];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, q = lane >> 4;
+  // weights: staged once per block in LDS, then held in registers by every wave
+  for (int i = tid; i < 9 * 16 * NMT * C / 8; i += 256)
+    *reinterpret_cast<bf16x8*>(ws + 8 * i) = *reinterpret_cast<const bf16x8*>(Wk + 8 * i);
+  if (FIRST)
+    for (int i = tid; i < SZ_L1; i += 256) w1s[i] = w1[i];
+  __syncthreads();
   bf16x8 wa[9][NMT];
 #pragma unroll
   for (int t = 0; t < 9; ++t)
 #pragma unroll
     for (int mt = 0; mt < NMT; ++mt)
-      wa[t][mt] = *reinterpret_cast<const bf16x8*>(Wk + (t * 16 * NMT + mt * 16 + col) * C + 8 * q);
+      wa[t][mt] = *reinterpret_cast<const bf16x8*>(ws + (t * 16 * NMT + mt * 16 + col) * C + 8 * q);
   float bv[NMT][4];
 #pragma unroll
   for (int mt = 0; mt < NMT; ++mt)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      if (MODE == CONV_FWD)
+      if (MODE == CONV_FWD || MODE == CONV_FIRST)
         bv[mt][r] = bias[mt * 16 + 4 * q + r];
       else if (MODE == OUT_INFER || MODE == OUT_TRAIN)
         bv[mt][r] = bias[0];
@@ -202,11 +218,11 @@ __global__ void __launch_bounds__(256) conv_patch(const __bf16* __restrict__ X, 
       const int r = node / kHx, xi = node % kHx;
       const int gy = y0 + r - 1, gx = x0 + xi - 1;
       v[k] = bf16x8{};
-      if (pi < npatch && i < kHr * kHx * 4 && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
+      if (!FIRST && pi < npatch && i < kHr * kHx * 4 && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
         v[k] = *reinterpret_cast<const bf16x8*>(X + ((b * ny + gy) * nx + gx) * C + ch);
     }
   };
-  load(blockIdx.x);
+  if (!FIRST) load(blockIdx.x);
   for (int64_t pi = blockIdx.x; pi < npatch; pi += gridDim.x) {
     const int pxi = int(pi % npx);
     const int64_t rest = pi / npx;
@@ -214,13 +230,57 @@ __global__ void __launch_bounds__(256) conv_patch(const __bf16* __restrict__ X, 
     const int64_t b = rest / npy;
     const int x0 = pxi * kPx, y0 = pyi * kPr;
     __syncthreads();
+    if (FIRST) {
+      // first layer in FP32 on the halo patch: features (u_c, (u_c - u_n) / c_b)
+      // of the surrounding nodes, then Y1 = relu(b1 + W1 * features), zero off the grid
+      const float rc = 1.f / cs[b];
+      for (int i = tid; i < FR * FX; i += 256) {
+        const int r = i / FX, xi = i % FX;
+        const int gy = y0 + r - 2, gx = x0 + xi - 2;
+        float f0 = 0.f, f1 = 0.f;
+        if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
+          const int64_t g = (b * ny + gy) * nx + gx;
+          f0 = uc[g];
+          f1 = (uc[g] - un[g]) * rc;
+        }
+        fs[i] = f0;
+        fs[FR * FX + i] = f1;
+      }
+      __syncthreads();
+      for (int i = tid; i < kHr * kHx * 4; i += 256) {
+        const int node = i >> 2, og = (i & 3) * 8;
+        const int r = node / kHx, xi = node % kHx;
+        const int gy = y0 + r - 1, gx = x0 + xi - 1;
+        bf16x8 h = {};
+        if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
+          float a[9], d[9];
 #pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-      const int i = tid + 256 * k;
-      if (i < kHr * kHx * 4) *reinterpret_cast<bf16x8*>(sp + (i >> 2) * kNs + (i & 3) * 8) = v[k];
+          for (int t = 0; t < 9; ++t) {
+            const int fi = (r + tap_dy(t) + 1) * FX + xi + tap_dx(t) + 1;
+            a[t] = fs[fi];
+            d[t] = fs[FR * FX + fi];
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int o = og + j;
+            float acc = w1s[SZ_W1 + o];
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+              acc = fmaf(a[t], w1s[(t * 2) * C + o], fmaf(d[t], w1s[(t * 2 + 1) * C + o], acc));
+            h[j] = __bf16(fmaxf(acc, 0.f));
+          }
+        }
+        *reinterpret_cast<bf16x8*>(sp + node * kNs + og) = h;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NLD; ++k) {
+        const int i = tid + 256 * k;
+        if (i < kHr * kHx * 4) *reinterpret_cast<bf16x8*>(sp + (i >> 2) * kNs + (i & 3) * 8) = v[k];
+      }
     }
     __syncthreads();
-    load(pi + gridDim.x);
+    if (!FIRST) load(pi + gridDim.x);
     const int y = y0 + wave;
     if (y >= ny) continue;
     const int64_t rowoff = (b * ny + y) * nx;
@@ -241,13 +301,13 @@ __global__ void __launch_bounds__(256) conv_patch(const __bf16* __restrict__ X, 
       const int px = x0 + xl;
       if (px >= nx) continue;
       const int64_t p = rowoff + px;
-      if (MODE == CONV_FWD || MODE == CONV_BWD) {
+      if (MODE == CONV_FWD || MODE == CONV_BWD || MODE == CONV_FIRST) {
         __bf16* Y = static_cast<__bf16*>(out);
 #pragma unroll
         for (int mt = 0; mt < NMT; ++mt) {
           const int oc0 = mt * 16 + 4 * q;
           bf16x4 h;
-          if (MODE == CONV_FWD) {
+          if (MODE == CONV_FWD || MODE == CONV_FIRST) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) h[r] = __bf16(fmaxf(acc[mt][r] + bv[mt][r], 0.f));
           } else {
@@ -549,6 +609,20 @@ __global__ void adam_update(float* __restrict__ p, const float* __restrict__ g, 
 }
 
 // ---------------------------------------------------------------------------
+// a = b = u (the two copies a corrected step starts from), 16 bytes per thread.
+__global__ void __launch_bounds__(256) copy2(const float* __restrict__ u, float* __restrict__ a,
+                                             float* __restrict__ b, int64_t n, int vec) {
+  const int64_t i = (int64_t(blockIdx.x) * 256 + threadIdx.x) * 4;
+  if (vec && i + 4 <= n) {
+    const f32x4 v = *reinterpret_cast<const f32x4*>(u + i);
+    *reinterpret_cast<f32x4*>(a + i) = v;
+    *reinterpret_cast<f32x4*>(b + i) = v;
+  } else {
+    for (int64_t k = i; k < n; ++k) a[k] = b[k] = u[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Corrected step: u = u_c + delta, with per-block partial sums of delta^2,
 // (u_c - u_n)^2 and the maximum of |u| (double).
 __global__ void __launch_bounds__(256) apply_indicator(const float* __restrict__ un, const float* __restrict__ uc,
@@ -664,6 +738,7 @@ struct eife_corr_s {
   double* dpart = nullptr;
   double* dres = nullptr;
   double* hres = nullptr;  // pinned, 4 doubles
+  double* hres_dev = nullptr;  // its device address (kernels write the indicator there), or null
   float* un_copy = nullptr;
   float* uc = nullptr;
   float* cs = nullptr;      // per-image RMS coarse change [max_batch]
@@ -736,20 +811,28 @@ int check_batch(const eife_corr_s* c, int batch) {
   return EIFE_OK;
 }
 
-// Forward through the first five layers: act[1..5].
-int forward_body(eife_corr_s* c, const float* un, const float* uc, int batch, hipStream_t s) {
+// Forward through the first five layers: act[1..5] (keep_first: Y1 is stored,
+// as the backward pass needs it; otherwise the first layer is computed inside
+// the second layer's kernel and act[1] is not written).
+int forward_body(eife_corr_s* c, const float* un, const float* uc, int batch, hipStream_t s, bool keep_first) {
   const int64_t npix = c->npix1 * batch;
   hipLaunchKernelGGL(change_partial, dim3(kCsBlocks, batch), dim3(256), 0, s, un, uc, c->npix1, c->cpart);
   hipLaunchKernelGGL(change_final, dim3(batch), dim3(256), 0, s, c->cpart, c->npix1, c->cs);
-  hipLaunchKernelGGL(conv_in_fwd, dim3(grid1(npix, 256)), dim3(256), 0, s, un, uc, c->cs, c->prm, c->act[1], c->nx,
-                     c->ny, npix);
   const int64_t np = n_patches(c, batch);
   const int blocks = patch_blocks(np);
-  for (int l = 0; l < N_MID; ++l)
+  if (keep_first) {
+    hipLaunchKernelGGL(conv_in_fwd, dim3(grid1(npix, 256)), dim3(256), 0, s, un, uc, c->cs, c->prm, c->act[1],
+                       c->nx, c->ny, npix);
+  } else {
+    hipLaunchKernelGGL((conv_patch<CONV_FIRST>), dim3(blocks), dim3(256), 0, s, (const __bf16*)nullptr,
+                       (void*)c->act[2], c->wf, c->prm + OFF_MID + SZ_WM, (const __bf16*)nullptr, 0.f, c->cs, uc,
+                       (const float*)nullptr, (double*)nullptr, 0.0, c->nx, c->ny, np, un, c->prm);
+  }
+  for (int l = keep_first ? 0 : 1; l < N_MID; ++l)
     hipLaunchKernelGGL((conv_patch<CONV_FWD>), dim3(blocks), dim3(256), 0, s, c->act[l + 1], (void*)c->act[l + 2],
                        c->wf + l * SZ_WM, c->prm + OFF_MID + l * SZ_LM + SZ_WM, (const __bf16*)nullptr, 0.f,
                        (const float*)nullptr, (const float*)nullptr, (const float*)nullptr, (double*)nullptr, 0.0,
-                       c->nx, c->ny, np);
+                       c->nx, c->ny, np, (const float*)nullptr, (const float*)nullptr);
   CHIP(hipGetLastError());
   return EIFE_OK;
 }
@@ -757,12 +840,12 @@ int forward_body(eife_corr_s* c, const float* un, const float* uc, int batch, hi
 // Forward + backward of a batch: c->grad holds the gradient, the loss sum goes to dres[0].
 int grad_body(eife_corr_s* c, const float* un, const float* uc, const float* uf, int batch, hipStream_t s) {
   const int64_t npix = c->npix1 * batch;
-  CRET(forward_body(c, un, uc, batch, s));
+  CRET(forward_body(c, un, uc, batch, s, true));
   const int64_t np = n_patches(c, batch);
   const int blocks = patch_blocks(np);
   hipLaunchKernelGGL((conv_patch<OUT_TRAIN>), dim3(blocks), dim3(256), 0, s, c->act[5], (void*)c->gout, c->w6b,
                      c->prm + OFF_L6 + SZ_W6, (const __bf16*)nullptr, float(c->s_out), c->cs, uc, uf, c->dpart,
-                     1.0 / double(npix), c->nx, c->ny, np);
+                     1.0 / double(npix), c->nx, c->ny, np, (const float*)nullptr, (const float*)nullptr);
   hipLaunchKernelGGL(reduce_loss, dim3(1), dim3(256), 0, s, c->dpart, blocks, c->dres);
   // output layer
   const int64_t nseg = int64_t(batch) * c->ny * ((c->nx + kSeg - 1) / kSeg);
@@ -780,7 +863,8 @@ int grad_body(eife_corr_s* c, const float* un, const float* uc, const float* uf,
                        c->grad + OFF_MID + l * SZ_LM);
     hipLaunchKernelGGL((conv_patch<CONV_BWD>), dim3(blocks), dim3(256), 0, s, c->dz[cur], (void*)c->dz[1 - cur],
                        c->wb + l * SZ_WM, (const float*)nullptr, c->act[l + 1], 0.f, (const float*)nullptr,
-                       (const float*)nullptr, (const float*)nullptr, (double*)nullptr, 0.0, c->nx, c->ny, np);
+                       (const float*)nullptr, (const float*)nullptr, (double*)nullptr, 0.0, c->nx, c->ny, np,
+                       (const float*)nullptr, (const float*)nullptr);
     cur = 1 - cur;
   }
   hipLaunchKernelGGL(dw_in, dim3(kPartBlocks), dim3(640), 0, s, c->dz[cur], un, uc, c->cs, c->part, c->nx, c->ny,
@@ -824,7 +908,8 @@ int eife_corr_create(int nx, int ny, int max_batch, eife_corr* out) {
             hipMalloc(&c->gout, npix * 4) == hipSuccess &&
             hipMalloc(&c->part, size_t(kPartBlocks) * SZ_LM * 4) == hipSuccess &&
             hipMalloc(&c->dpart, size_t(std::max<int64_t>(grid1(npix, 256), 4096)) * 8) == hipSuccess &&
-            hipMalloc(&c->dres, 4 * 8) == hipSuccess && hipHostMalloc(&c->hres, 4 * 8, 0) == hipSuccess &&
+            hipMalloc(&c->dres, 4 * 8) == hipSuccess &&
+            hipHostMalloc(&c->hres, 4 * 8, hipHostMallocMapped) == hipSuccess &&
             hipMalloc(&c->un_copy, c->npix1 * 4) == hipSuccess && hipMalloc(&c->uc, c->npix1 * 4) == hipSuccess &&
             hipMalloc(&c->cs, size_t(max_batch) * 4) == hipSuccess &&
             hipMalloc(&c->cpart, size_t(max_batch) * kCsBlocks * 8) == hipSuccess;
@@ -832,6 +917,10 @@ int eife_corr_create(int nx, int ny, int max_batch, eife_corr* out) {
   if (!ok) {
     free_corr(c);
     return cfail(EIFE_ENOMEM, "corrector buffers allocation failed");
+  }
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hres_dev), c->hres, 0) != hipSuccess) {
+    c->hres_dev = nullptr;  // not mapped: the indicator goes through a copy
+    (void)hipGetLastError();
   }
   if (hipMemset(c->prm, 0, N_PARAMS * 4) != hipSuccess || hipMemset(c->grad, 0, N_PARAMS * 4) != hipSuccess ||
       hipMemset(c->m, 0, N_PARAMS * 4) != hipSuccess || hipMemset(c->v, 0, N_PARAMS * 4) != hipSuccess ||
@@ -891,11 +980,12 @@ int eife_corr_forward(eife_corr c, const float* un, const float* uc, float* delt
   if (!c || !un || !uc || !delta) return cfail(EIFE_EINVAL, "null argument");
   CRET(check_batch(c, batch));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  CRET(forward_body(c, un, uc, batch, s));
+  CRET(forward_body(c, un, uc, batch, s, false));
   const int64_t np = n_patches(c, batch);
   hipLaunchKernelGGL((conv_patch<OUT_INFER>), dim3(patch_blocks(np)), dim3(256), 0, s, c->act[5], (void*)delta,
                      c->w6b, c->prm + OFF_L6 + SZ_W6, (const __bf16*)nullptr, float(c->s_out), c->cs,
-                     (const float*)nullptr, (const float*)nullptr, (double*)nullptr, 0.0, c->nx, c->ny, np);
+                     (const float*)nullptr, (const float*)nullptr, (double*)nullptr, 0.0, c->nx, c->ny, np,
+                     (const float*)nullptr, (const float*)nullptr);
   CHIP(hipGetLastError());
   return EIFE_OK;
 }
@@ -936,16 +1026,18 @@ int eife_corr_infer_step(eife_corr c, eife_grid coarse, eife_grid fine, float* u
                  (long long)c->npix1);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t bytes = size_t(c->npix1) * 4;
-  CHIP(hipMemcpyAsync(c->un_copy, u, bytes, hipMemcpyDeviceToDevice, s));
-  CHIP(hipMemcpyAsync(c->uc, u, bytes, hipMemcpyDeviceToDevice, s));
+  const int vec = (reinterpret_cast<uintptr_t>(u) % 16) == 0;  // the library's own buffers are 256-byte aligned
+  hipLaunchKernelGGL(copy2, dim3(grid1((c->npix1 + 3) / 4, 256)), dim3(256), 0, s, u, c->un_copy, c->uc, c->npix1,
+                     vec);
   int r = eife_step(coarse, c->uc, 1, EIFE_F_ALLEN_CAHN, t0, stream);
   if (r != EIFE_OK) return cfail(r, "coarse step: %s", eife_last_error());
   CRET(eife_corr_forward(c, c->un_copy, c->uc, c->gout, 1, stream));
   hipLaunchKernelGGL(apply_indicator, dim3(kIndBlocks), dim3(256), 0, s, c->un_copy, c->uc, c->gout, u, c->npix1,
                      c->dpart);
-  hipLaunchKernelGGL(reduce_indicator, dim3(1), dim3(256), 0, s, c->dpart, kIndBlocks, c->dres);
+  hipLaunchKernelGGL(reduce_indicator, dim3(1), dim3(256), 0, s, c->dpart, kIndBlocks,
+                     c->hres_dev ? c->hres_dev : c->dres);
   CHIP(hipGetLastError());
-  CHIP(hipMemcpyAsync(c->hres, c->dres, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (!c->hres_dev) CHIP(hipMemcpyAsync(c->hres, c->dres, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   CHIP(hipStreamSynchronize(s));
   const double ind = std::sqrt(c->hres[0]) / (std::sqrt(c->hres[1]) + 1e-12);
   const double umax = c->hres[2];
@@ -960,6 +1052,20 @@ int eife_corr_infer_step(eife_corr c, eife_grid coarse, eife_grid fine, float* u
     CHIP(hipMemcpyAsync(u, c->un_copy, bytes, hipMemcpyDeviceToDevice, s));
     r = eife_step(fine, u, fine_steps, EIFE_F_ALLEN_CAHN, t0, stream);
     if (r != EIFE_OK) return cfail(r, "fine steps: %s", eife_last_error());
+  }
+  return EIFE_OK;
+}
+
+int eife_corr_run(eife_corr c, eife_grid coarse, eife_grid fine, float* u, double t0, double tau_coarse,
+                  int64_t n_steps, int64_t fine_steps, double theta, int64_t* fallbacks, void* stream) {
+  if (!c || !fallbacks) return cfail(EIFE_EINVAL, "null argument");
+  if (n_steps < 0 || !(tau_coarse > 0.0)) return cfail(EIFE_EINVAL, "n_steps must be >= 0 and tau_coarse > 0");
+  *fallbacks = 0;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    int fb = 0;
+    CRET(eife_corr_infer_step(c, coarse, fine, u, t0 + double(k) * tau_coarse, fine_steps, theta, &fb, nullptr,
+                              stream));
+    *fallbacks += fb;
   }
   return EIFE_OK;
 }

@@ -224,3 +224,33 @@ def test_corrector_argument_errors():
     with pytest.raises(ValueError):
         c.forward(torch.zeros(6, 9, device="cuda"), torch.zeros(6, 9, device="cuda"))
     c.close()
+
+
+def test_native_run_equals_single_steps():
+    """eife_corr_run gives, bit for bit, the same trajectory as repeated infer_step calls
+    (accepted steps and the transient guard's fallbacks alike)."""
+    eife = _lib()
+    n = 64
+    N, h = [n, n], [1.0 / n] * 2
+    coarse = eife.Grid(N, h, 4e-4, "f32")
+    coarse.set_phi(0.016, 2)
+    fine = eife.Grid(N, h, 4e-4, "f32")
+    fine.set_phi(0.002, 2)
+    c = eife.Corrector(n - 1, n - 1, 1)
+    p = cr.init_params(11).astype(np.float32)
+    c.set_params(p)
+    c.set_scale(1e-4)
+    c.set_guard(0.05)  # the first steps from random data fall back
+    u0 = _dev(seeded_inputs.uniform_field(12, N))
+    a = u0.clone()
+    fb_a = 0
+    for k in range(6):
+        fb_a += c.infer_step(coarse, fine, a, k * 0.016, 8, 10.0)[0]
+    b = u0.clone()
+    fb_b = c.run(coarse, fine, b, 0.0, 0.016, 6, 8, 10.0)
+    torch.cuda.synchronize()
+    assert fb_a == fb_b and 0 < fb_b < 6
+    assert torch.equal(a, b)
+    for g in (coarse, fine):
+        g.close()
+    c.close()
