@@ -820,7 +820,7 @@ int run_norms(eife_grid_s* g, const void* u, const void* uref, hipStream_t s) {
   hipLaunchKernelGGL((norm_partial<T>), dim3(nb), dim3(kNormThreads), 0, s, static_cast<const T*>(u),
                      static_cast<const T*>(uref), ng, g->partials);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(norm_final, dim3(1), dim3(kNormAcc), 0, s, g->partials, nb, g->out5);
+  hipLaunchKernelGGL(norm_final, dim3(1), dim3(kNormFinalThreads), 0, s, g->partials, nb, g->out5);
   HIP_TRY(hipGetLastError());
   return EIFE_OK;
 }

@@ -614,16 +614,31 @@ __global__ void __launch_bounds__(kNormThreads) norm_partial(const T* __restrict
   if (threadIdx.x < kNormAcc) partials[blockIdx.x * kNormAcc + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void __launch_bounds__(kNormAcc) norm_final(const double* __restrict__ partials, int nblocks,
-                                                       double* __restrict__ out5) {
-  const int k = threadIdx.x;
-  if (k >= kNormAcc) return;
-  double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) {
-    const double v = partials[b * kNormAcc + k];
-    s = (k == 2) ? fmax(s, v) : s + v;
+// Second level: 256 threads stride over the block partials, then a fixed-order
+// tree in LDS (deterministic); accumulator 2 is a maximum, the others sums.
+constexpr int kNormFinalThreads = 256;
+__global__ void __launch_bounds__(kNormFinalThreads) norm_final(const double* __restrict__ partials, int nblocks,
+                                                                double* __restrict__ out5) {
+  __shared__ double red[kNormAcc][kNormFinalThreads];
+  const int t = threadIdx.x;
+  double s[kNormAcc] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = t; b < nblocks; b += kNormFinalThreads)
+#pragma unroll
+    for (int k = 0; k < kNormAcc; ++k) {
+      const double v = partials[b * kNormAcc + k];
+      s[k] = (k == 2) ? fmax(s[k], v) : s[k] + v;
+    }
+#pragma unroll
+  for (int k = 0; k < kNormAcc; ++k) red[k][t] = s[k];
+  __syncthreads();
+  for (int h = kNormFinalThreads / 2; h > 0; h >>= 1) {
+    if (t < h)
+#pragma unroll
+      for (int k = 0; k < kNormAcc; ++k)
+        red[k][t] = (k == 2) ? fmax(red[k][t], red[k][t + h]) : red[k][t] + red[k][t + h];
+    __syncthreads();
   }
-  out5[k] = s;
+  if (t < kNormAcc) out5[t] = red[t][0];
 }
 
 }  // namespace eife
