@@ -98,11 +98,11 @@ struct FftShape {
 };
 
 // Occupancy hint (waves per SIMD) of the pass kernels: 4 keeps two 8-wave
-// blocks per CU for FP32 lines up to 512 points; longer or double lines
-// need more registers than that leaves.
+// blocks per CU for FP32 lines up to 512 points; longer, double or
+// three-subsequence lines need more registers than that leaves.
 template <typename T, int L>
 struct MinWaves {
-  static constexpr int value = (L >= 1024 || sizeof(T) == 8) ? 2 : 4;
+  static constexpr int value = (L >= 1024 || sizeof(T) == 8 || (L & (L - 1)) != 0) ? 2 : 4;
 };
 
 // The twiddle factors one lane needs, loaded once per kernel.
@@ -525,7 +525,21 @@ __device__ __forceinline__ void diag_fast(const Sep& s, double D, double tau, do
 template <typename T, int L, int PB, int PPW, int MODE, bool BAT>
 __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::value)) col_fast(T* W, T* H, ColGeom g, const Cx<T>* tw,
                                                                         Diag dg, const ColInst<T>* __restrict__ insts) {
-  if constexpr (BAT) col_inst_ptrs<T>(insts, W, H, dg);
+  // per-instance tables of a batched launch are held in separate locals (a
+  // modified copy of the Diag argument would live in private memory)
+  AxisTab ta0 = dg.ax[0], ta1 = dg.ax[1], ta2 = dg.ax[2];
+  double Dv = dg.D;
+  if constexpr (BAT) {
+    if (insts) {
+      const ColInst<T>& I = insts[blockIdx.z];
+      W = I.W;
+      H = I.H;
+      ta0 = I.ax[0];
+      ta1 = I.ax[1];
+      ta2 = I.ax[2];
+      Dv = I.D;
+    }
+  }
   using Ln = Line<T, L>;
   constexpr int N = L / 2;
   constexpr int n = N - 1;
@@ -576,21 +590,21 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
   if (MODE != COL_PLAIN) {
     __syncthreads();
     // diagonal stage over the tile: thread -> (row m, pair q), pair fixed per thread
-    const double tau = dg.tau, D = dg.D;
+    const double tau = dg.tau, D = Dv;
     const double rtc2 = 1.0 / (tau * dg.c2);
     const int q = tq;
     const int kx0 = c0 + 2 * q;
     Sep sxy[2];
     if (g.last_is_z) {
-      const Sep sy = sep_load(dg.ax[1], outer);
-      sxy[0] = sep_combine(sep_load(dg.ax[0], kx0), sy);
-      sxy[1] = sep_combine(sep_load(dg.ax[0], kx0 + 1), sy);
+      const Sep sy = sep_load(ta1, outer);
+      sxy[0] = sep_combine(sep_load(ta0, kx0), sy);
+      sxy[1] = sep_combine(sep_load(ta0, kx0 + 1), sy);
     } else {
-      const Sep sz = sep_load(dg.ax[2], 0);
-      sxy[0] = sep_combine(sep_load(dg.ax[0], kx0), sz);
-      sxy[1] = sep_combine(sep_load(dg.ax[0], kx0 + 1), sz);
+      const Sep sz = sep_load(ta2, 0);
+      sxy[0] = sep_combine(sep_load(ta0, kx0), sz);
+      sxy[1] = sep_combine(sep_load(ta0, kx0 + 1), sz);
     }
-    const AxisTab& line_tab = g.last_is_z ? dg.ax[2] : dg.ax[1];
+    const AxisTab line_tab = g.last_is_z ? ta2 : ta1;
     Cx<T>* hrow = reinterpret_cast<Cx<T>*>(H + base + m0 * ldl + 2 * q);
     constexpr int DIT = CIT;
     constexpr int BATCH = 4;

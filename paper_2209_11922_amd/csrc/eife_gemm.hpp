@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(Shape<KP>::THREADS) gemm_col(float* W, float* 
     // columns are combined once, the line-axis factor per mode
     const double tau = dg.tau, D = dg.D, rtc2 = 1.0 / (tau * dg.c2);
     const Sep so = g.last_is_z ? sep_load(dg.ax[1], outer) : sep_load(dg.ax[2], 0);
-    const AxisTab& line_tab = g.last_is_z ? dg.ax[2] : dg.ax[1];
+    const AxisTab line_tab = g.last_is_z ? dg.ax[2] : dg.ax[1];  // a copy: no private-memory struct
     Sep sx[Sh::LT];
 #pragma unroll
     for (int t = 0; t < Sh::LT; ++t) {
