@@ -146,10 +146,7 @@ __global__ void __launch_bounds__(256) conv_in_fwd(const float* __restrict__ un,
 //              Wk rows 1..15 are zero)
 //   OUT_TRAIN  e = D[0] + b6 - (uf - uc) / (s_out c_b); out = 2 e / count;
 //              per-block sum of e^2 in loss_part[blockIdx.x]
-//   CONV_FIRST as CONV_FWD for the second layer, with the first layer (FP32,
-//              from un, uc, c_b and its weights w1) computed on the patch in
-//              LDS instead of read from memory
-enum { CONV_FWD = 0, CONV_BWD = 1, OUT_INFER = 2, OUT_TRAIN = 3, CONV_FIRST = 4 };
+enum { CONV_FWD = 0, CONV_BWD = 1, OUT_INFER = 2, OUT_TRAIN = 3 };
 
 constexpr int kPr = 4, kPx = 64;              // patch rows / nodes
 constexpr int kHr = kPr + 2, kHx = kPx + 2;   // with halo
@@ -162,15 +159,10 @@ __global__ void __launch_bounds__(256) conv_patch(const __bf16* __restrict__ X, 
                                                   const float* __restrict__ cs, const float* __restrict__ uc,
                                                   const float* __restrict__ uf,
                                                   double* __restrict__ loss_part, double inv_count, int nx, int ny,
-                                                  int64_t npatch, const float* __restrict__ un,
-                                                  const float* __restrict__ w1) {
-  constexpr int NMT = (MODE == CONV_FWD || MODE == CONV_BWD || MODE == CONV_FIRST) ? 2 : 1;
-  constexpr bool FIRST = MODE == CONV_FIRST;
-  constexpr int FR = kHr + 2, FX = kHx + 2;  // nodal inputs around the halo patch (first layer)
+                                                  int64_t npatch) {
+  constexpr int NMT = (MODE == CONV_FWD || MODE == CONV_BWD) ? 2 : 1;
   __shared__ __attribute__((aligned(16))) __bf16 sp[kHr * kHx * kNs];
   __shared__ __attribute__((aligned(16))) __bf16 ws[9 * 16 * NMT * C];
-  __shared__ __attribute__((aligned(16))) float fs[FIRST ? 2 * FR * FX : 1];
-  __shared__ __attribute__((aligned(16))) float w1s[FIRST ? SZ_L1 : 1];
   __shared__ double red[256];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -178,8 +170,6 @@ __global__ void __launch_bounds__(256) conv_patch(const __bf16* __restrict__ X, 
   // weights: staged once per block in LDS, then held in registers by every wave
   for (int i = tid; i < 9 * 16 * NMT * C / 8; i += 256)
     *reinterpret_cast<bf16x8*>(ws + 8 * i) = *reinterpret_cast<const bf16x8*>(Wk + 8 * i);
-  if (FIRST)
-    for (int i = tid; i < SZ_L1; i += 256) w1s[i] = w1[i];
   __syncthreads();
   bf16x8 wa[9][NMT];
 #pragma unroll
@@ -192,7 +182,7 @@ __global__ void __launch_bounds__(256) conv_patch(const __bf16* __restrict__ X, 
   for (int mt = 0; mt < NMT; ++mt)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      if (MODE == CONV_FWD || MODE == CONV_FIRST)
+      if (MODE == CONV_FWD)
         bv[mt][r] = bias[mt * 16 + 4 * q + r];
       else if (MODE == OUT_INFER || MODE == OUT_TRAIN)
         bv[mt][r] = bias[0];
@@ -218,11 +208,11 @@ __global__ void __launch_bounds__(256) conv_patch(const __bf16* __restrict__ X, 
       const int r = node / kHx, xi = node % kHx;
       const int gy = y0 + r - 1, gx = x0 + xi - 1;
       v[k] = bf16x8{};
-      if (!FIRST && pi < npatch && i < kHr * kHx * 4 && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
+      if (pi < npatch && i < kHr * kHx * 4 && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
         v[k] = *reinterpret_cast<const bf16x8*>(X + ((b * ny + gy) * nx + gx) * C + ch);
     }
   };
-  if (!FIRST) load(blockIdx.x);
+  load(blockIdx.x);
   for (int64_t pi = blockIdx.x; pi < npatch; pi += gridDim.x) {
     const int pxi = int(pi % npx);
     const int64_t rest = pi / npx;
@@ -230,57 +220,13 @@ __global__ void __launch_bounds__(256) conv_patch(const __bf16* __restrict__ X, 
     const int64_t b = rest / npy;
     const int x0 = pxi * kPx, y0 = pyi * kPr;
     __syncthreads();
-    if (FIRST) {
-      // first layer in FP32 on the halo patch: features (u_c, (u_c - u_n) / c_b)
-      // of the surrounding nodes, then Y1 = relu(b1 + W1 * features), zero off the grid
-      const float rc = 1.f / cs[b];
-      for (int i = tid; i < FR * FX; i += 256) {
-        const int r = i / FX, xi = i % FX;
-        const int gy = y0 + r - 2, gx = x0 + xi - 2;
-        float f0 = 0.f, f1 = 0.f;
-        if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
-          const int64_t g = (b * ny + gy) * nx + gx;
-          f0 = uc[g];
-          f1 = (uc[g] - un[g]) * rc;
-        }
-        fs[i] = f0;
-        fs[FR * FX + i] = f1;
-      }
-      __syncthreads();
-      for (int i = tid; i < kHr * kHx * 4; i += 256) {
-        const int node = i >> 2, og = (i & 3) * 8;
-        const int r = node / kHx, xi = node % kHx;
-        const int gy = y0 + r - 1, gx = x0 + xi - 1;
-        bf16x8 h = {};
-        if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
-          float a[9], d[9];
 #pragma unroll
-          for (int t = 0; t < 9; ++t) {
-            const int fi = (r + tap_dy(t) + 1) * FX + xi + tap_dx(t) + 1;
-            a[t] = fs[fi];
-            d[t] = fs[FR * FX + fi];
-          }
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int o = og + j;
-            float acc = w1s[SZ_W1 + o];
-#pragma unroll
-            for (int t = 0; t < 9; ++t)
-              acc = fmaf(a[t], w1s[(t * 2) * C + o], fmaf(d[t], w1s[(t * 2 + 1) * C + o], acc));
-            h[j] = __bf16(fmaxf(acc, 0.f));
-          }
-        }
-        *reinterpret_cast<bf16x8*>(sp + node * kNs + og) = h;
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < NLD; ++k) {
-        const int i = tid + 256 * k;
-        if (i < kHr * kHx * 4) *reinterpret_cast<bf16x8*>(sp + (i >> 2) * kNs + (i & 3) * 8) = v[k];
-      }
+    for (int k = 0; k < NLD; ++k) {
+      const int i = tid + 256 * k;
+      if (i < kHr * kHx * 4) *reinterpret_cast<bf16x8*>(sp + (i >> 2) * kNs + (i & 3) * 8) = v[k];
     }
     __syncthreads();
-    if (!FIRST) load(pi + gridDim.x);
+    load(pi + gridDim.x);
     const int y = y0 + wave;
     if (y >= ny) continue;
     const int64_t rowoff = (b * ny + y) * nx;
@@ -301,13 +247,13 @@ __global__ void __launch_bounds__(256) conv_patch(const __bf16* __restrict__ X, 
       const int px = x0 + xl;
       if (px >= nx) continue;
       const int64_t p = rowoff + px;
-      if (MODE == CONV_FWD || MODE == CONV_BWD || MODE == CONV_FIRST) {
+      if (MODE == CONV_FWD || MODE == CONV_BWD) {
         __bf16* Y = static_cast<__bf16*>(out);
 #pragma unroll
         for (int mt = 0; mt < NMT; ++mt) {
           const int oc0 = mt * 16 + 4 * q;
           bf16x4 h;
-          if (MODE == CONV_FWD || MODE == CONV_FIRST) {
+          if (MODE == CONV_FWD) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) h[r] = __bf16(fmaxf(acc[mt][r] + bv[mt][r], 0.f));
           } else {
@@ -811,28 +757,20 @@ int check_batch(const eife_corr_s* c, int batch) {
   return EIFE_OK;
 }
 
-// Forward through the first five layers: act[1..5] (keep_first: Y1 is stored,
-// as the backward pass needs it; otherwise the first layer is computed inside
-// the second layer's kernel and act[1] is not written).
-int forward_body(eife_corr_s* c, const float* un, const float* uc, int batch, hipStream_t s, bool keep_first) {
+// Forward through the first five layers: the RMS coarse change, act[1..5].
+int forward_body(eife_corr_s* c, const float* un, const float* uc, int batch, hipStream_t s) {
   const int64_t npix = c->npix1 * batch;
   hipLaunchKernelGGL(change_partial, dim3(kCsBlocks, batch), dim3(256), 0, s, un, uc, c->npix1, c->cpart);
   hipLaunchKernelGGL(change_final, dim3(batch), dim3(256), 0, s, c->cpart, c->npix1, c->cs);
+  hipLaunchKernelGGL(conv_in_fwd, dim3(grid1(npix, 256)), dim3(256), 0, s, un, uc, c->cs, c->prm, c->act[1], c->nx,
+                     c->ny, npix);
   const int64_t np = n_patches(c, batch);
   const int blocks = patch_blocks(np);
-  if (keep_first) {
-    hipLaunchKernelGGL(conv_in_fwd, dim3(grid1(npix, 256)), dim3(256), 0, s, un, uc, c->cs, c->prm, c->act[1],
-                       c->nx, c->ny, npix);
-  } else {
-    hipLaunchKernelGGL((conv_patch<CONV_FIRST>), dim3(blocks), dim3(256), 0, s, (const __bf16*)nullptr,
-                       (void*)c->act[2], c->wf, c->prm + OFF_MID + SZ_WM, (const __bf16*)nullptr, 0.f, c->cs, uc,
-                       (const float*)nullptr, (double*)nullptr, 0.0, c->nx, c->ny, np, un, c->prm);
-  }
-  for (int l = keep_first ? 0 : 1; l < N_MID; ++l)
+  for (int l = 0; l < N_MID; ++l)
     hipLaunchKernelGGL((conv_patch<CONV_FWD>), dim3(blocks), dim3(256), 0, s, c->act[l + 1], (void*)c->act[l + 2],
                        c->wf + l * SZ_WM, c->prm + OFF_MID + l * SZ_LM + SZ_WM, (const __bf16*)nullptr, 0.f,
                        (const float*)nullptr, (const float*)nullptr, (const float*)nullptr, (double*)nullptr, 0.0,
-                       c->nx, c->ny, np, (const float*)nullptr, (const float*)nullptr);
+                       c->nx, c->ny, np);
   CHIP(hipGetLastError());
   return EIFE_OK;
 }
@@ -840,12 +778,12 @@ int forward_body(eife_corr_s* c, const float* un, const float* uc, int batch, hi
 // Forward + backward of a batch: c->grad holds the gradient, the loss sum goes to dres[0].
 int grad_body(eife_corr_s* c, const float* un, const float* uc, const float* uf, int batch, hipStream_t s) {
   const int64_t npix = c->npix1 * batch;
-  CRET(forward_body(c, un, uc, batch, s, true));
+  CRET(forward_body(c, un, uc, batch, s));
   const int64_t np = n_patches(c, batch);
   const int blocks = patch_blocks(np);
   hipLaunchKernelGGL((conv_patch<OUT_TRAIN>), dim3(blocks), dim3(256), 0, s, c->act[5], (void*)c->gout, c->w6b,
                      c->prm + OFF_L6 + SZ_W6, (const __bf16*)nullptr, float(c->s_out), c->cs, uc, uf, c->dpart,
-                     1.0 / double(npix), c->nx, c->ny, np, (const float*)nullptr, (const float*)nullptr);
+                     1.0 / double(npix), c->nx, c->ny, np);
   hipLaunchKernelGGL(reduce_loss, dim3(1), dim3(256), 0, s, c->dpart, blocks, c->dres);
   // output layer
   const int64_t nseg = int64_t(batch) * c->ny * ((c->nx + kSeg - 1) / kSeg);
@@ -863,8 +801,7 @@ int grad_body(eife_corr_s* c, const float* un, const float* uc, const float* uf,
                        c->grad + OFF_MID + l * SZ_LM);
     hipLaunchKernelGGL((conv_patch<CONV_BWD>), dim3(blocks), dim3(256), 0, s, c->dz[cur], (void*)c->dz[1 - cur],
                        c->wb + l * SZ_WM, (const float*)nullptr, c->act[l + 1], 0.f, (const float*)nullptr,
-                       (const float*)nullptr, (const float*)nullptr, (double*)nullptr, 0.0, c->nx, c->ny, np,
-                       (const float*)nullptr, (const float*)nullptr);
+                       (const float*)nullptr, (const float*)nullptr, (double*)nullptr, 0.0, c->nx, c->ny, np);
     cur = 1 - cur;
   }
   hipLaunchKernelGGL(dw_in, dim3(kPartBlocks), dim3(640), 0, s, c->dz[cur], un, uc, c->cs, c->part, c->nx, c->ny,
@@ -980,12 +917,11 @@ int eife_corr_forward(eife_corr c, const float* un, const float* uc, float* delt
   if (!c || !un || !uc || !delta) return cfail(EIFE_EINVAL, "null argument");
   CRET(check_batch(c, batch));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  CRET(forward_body(c, un, uc, batch, s, false));
+  CRET(forward_body(c, un, uc, batch, s));
   const int64_t np = n_patches(c, batch);
   hipLaunchKernelGGL((conv_patch<OUT_INFER>), dim3(patch_blocks(np)), dim3(256), 0, s, c->act[5], (void*)delta,
                      c->w6b, c->prm + OFF_L6 + SZ_W6, (const __bf16*)nullptr, float(c->s_out), c->cs,
-                     (const float*)nullptr, (const float*)nullptr, (double*)nullptr, 0.0, c->nx, c->ny, np,
-                     (const float*)nullptr, (const float*)nullptr);
+                     (const float*)nullptr, (const float*)nullptr, (double*)nullptr, 0.0, c->nx, c->ny, np);
   CHIP(hipGetLastError());
   return EIFE_OK;
 }

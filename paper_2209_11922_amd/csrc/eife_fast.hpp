@@ -564,11 +564,21 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
   const int ldl = int(g.ld_line);  // tile offsets stay below 2^31 elements
   const Cx<T>* gsrc = reinterpret_cast<const Cx<T>*>(W + base + m0 * ldl + 2 * tq);
   Cx<T>* ltile = lds + tq * BUF + m0;
+  // narrow tiles (small grids, one wave per block): the stage's H values are
+  // loaded together with the tile, so their latency overlaps the first FFT
+  constexpr bool PREH = MODE != COL_PLAIN && PB <= 2;
+  Cx<T> hpre[PREH ? CIT : 1];
   {
     Cx<T> tmp[CIT];
 #pragma unroll
     for (int it = 0; it < CIT; ++it)
       if (m0 + MS * it < n) tmp[it] = gsrc[(MS * it * ldl) / 2];
+    if constexpr (PREH) {
+      const Cx<T>* hsrc = reinterpret_cast<const Cx<T>*>(H + base + m0 * ldl + 2 * tq);
+#pragma unroll
+      for (int it = 0; it < CIT; ++it)
+        if (m0 + MS * it < n) hpre[it] = hsrc[(MS * it * ldl) / 2];
+    }
 #pragma unroll
     for (int it = 0; it < CIT; ++it)
       if (m0 + MS * it < n) ltile[MS * it] = mask_pad(tmp[it], c0 + 2 * tq, g.ncols);
@@ -614,7 +624,12 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
 #pragma unroll
       for (int it = 0; it < BATCH; ++it) {
         const int m = m0 + (b0 + it) * MS;
-        if (b0 + it < DIT && m < n) hv[it] = hrow[(MS * (b0 + it) * ldl) / 2];
+        if (b0 + it < DIT && m < n) {
+          if constexpr (PREH)
+            hv[it] = hpre[b0 + it];
+          else
+            hv[it] = hrow[(MS * (b0 + it) * ldl) / 2];
+        }
       }
 #pragma unroll
       for (int it = 0; it < BATCH; ++it) {
