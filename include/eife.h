@@ -238,11 +238,11 @@ int eife_version(void);
  * fastest), channels 2 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, ReLU after the
  * first five, zero padding (the homogeneous Dirichlet boundary).  Tap
  * t = 3 (dy + 1) + (dx + 1) reads the input at (y + dy, x + dx).  The four
- * 32 -> 32 layers run on the matrix cores with BF16 weights and activations
- * and FP32 accumulation; the first and last layers in FP32.
+ * 32 -> 32 layers and the output layer run on the matrix cores with BF16
+ * weights and activations and FP32 accumulation; the first layer in FP32.
  *
  * Parameters: EIFE_CORR_PARAMS floats, in order W1 [9][2][32] (tap, input
- * (u_n, u_c), output), b1 [32]; four times W [9][32][32] (tap, output,
+ * channel (u_c, (u_c - u_n) / c), output), b1 [32]; four times W [9][32][32] (tap, output,
  * input), b [32]; W6 [9][32] (tap, input), b6 [1].
  *
  * Device arrays (un, uc, uf, delta, u) are FP32, [batch][ny][nx] contiguous;
@@ -266,7 +266,7 @@ int eife_corr_get_params(eife_corr c, float* host, int64_t count);
 /* Output scale s_out > 0 (default 1e-3). */
 int eife_corr_set_scale(eife_corr c, double s_out);
 
-/* delta = s_out * o(un, uc) for `batch` images. */
+/* delta = s_out * c * o(un, uc) for `batch` images (c per image, as above). */
 int eife_corr_forward(eife_corr c, const float* un, const float* uc, float* delta, int batch, void* stream);
 
 /* Loss = mean over the batch's nodes of (o - (uf - uc) / (s_out c))^2 and its

@@ -56,6 +56,7 @@ constexpr size_t kLdsBudget = 80 * 1024;  // per block, two blocks per CU fit in
 constexpr int kNormBlocksMax = 1024;
 constexpr int kTabArrays = 5;  // lam, w, M, Q, Mc per axis
 constexpr int kPipeBlocksPerCu = 4;  // resident blocks of the pipelined column pass (LDS permitting)
+constexpr int kStagePipeMinTiles = 2;  // tiles per resident block from which the stage pass is pipelined
 int g_cus = 256;                     // compute units of the device (set at grid creation)
 
 bool factor_plan(int L, FftPlan* pl) {
@@ -405,7 +406,29 @@ void col_fast_go(int mode, int pitch, int outer, int count, bool pipe, hipStream
     } else {
       hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_PLAIN, BAT>), grid, dim3(NT), 0, s, W, H, cg, tw, dg, ci);
     }
-  } else if (mode == COL_STAGE_A) {
+    return;
+  }
+  if constexpr (!BAT) {
+    // many tiles per resident block: the persistent pipelined stage pass
+    const int ntx = pitch / (2 * PB);
+    const int ntiles = ntx * outer;
+    constexpr int lds = PB * fast::Line<T, L>::BUF * int(sizeof(Cx<T>));
+    constexpr int per_cu = std::max(1, std::min(kPipeBlocksPerCu, 160 * 1024 / lds));
+    const int nblk = g_cus * per_cu;
+    if (pipe && ntiles >= kStagePipeMinTiles * nblk) {
+      if (mode == COL_STAGE_A)
+        hipLaunchKernelGGL((fast::col_stage_pipe<T, L, PB, PPW, COL_STAGE_A>), dim3(nblk), dim3(NT), 0, s, W, H, cg,
+                           tw, dg, ntx, ntiles);
+      else if (mode == COL_STAGE_B)
+        hipLaunchKernelGGL((fast::col_stage_pipe<T, L, PB, PPW, COL_STAGE_B>), dim3(nblk), dim3(NT), 0, s, W, H, cg,
+                           tw, dg, ntx, ntiles);
+      else
+        hipLaunchKernelGGL((fast::col_stage_pipe<T, L, PB, PPW, COL_ETD1>), dim3(nblk), dim3(NT), 0, s, W, H, cg,
+                           tw, dg, ntx, ntiles);
+      return;
+    }
+  }
+  if (mode == COL_STAGE_A) {
     hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_STAGE_A, BAT>), grid, dim3(NT), 0, s, W, H, cg, tw, dg, ci);
   } else if (mode == COL_STAGE_B) {
     hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_STAGE_B, BAT>), grid, dim3(NT), 0, s, W, H, cg, tw, dg, ci);
@@ -1055,6 +1078,14 @@ int eife_profile(eife_grid g, int on) {
   g->prof_on = on != 0;
   return EIFE_OK;
 }
+
+}  // extern "C"
+
+// Library-internal (not exported through the header): whether a grid records
+// per-pass timing events, which must not be captured into a graph.
+bool eife_grid_profiling(eife_grid g) { return g && g->prof_on; }
+
+extern "C" {
 
 int eife_profile_read(eife_grid g, double* ms, int64_t* launches) {
   RET_IF(check_grid(g));

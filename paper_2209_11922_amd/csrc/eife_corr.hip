@@ -9,11 +9,11 @@
 // coarse change c = sqrt(mean((u_c - u_n)^2)) + 1e-30, the input channels are
 // (u_c, (u_c - u_n) / c) and delta = s_out c o for the network output o.
 //
-// Precision: FP32 master parameters; the four 32 -> 32 layers run on the
-// matrix cores with BF16 weights and BF16 activations, FP32 accumulation
-// (forward, backward-data, backward-weight); the 2 -> 32 input layer and the
-// 32 -> 1 output layer run in FP32 on the vector units.  Activations are
-// stored [B][ny][nx][32] BF16 (64 bytes per node).
+// Precision: FP32 master parameters; the four 32 -> 32 layers and the output
+// layer's forward run on the matrix cores with BF16 weights and BF16
+// activations, FP32 accumulation; the 2 -> 32 input layer and the output
+// layer's gradients run in FP32 on the vector units.  Activations are stored
+// [B][ny][nx][32] BF16 (64 bytes per node).
 //
 // Parameter vector (FP32), in order: W1 [9][2][32] (tap, input, output), b1
 // [32]; four times W [9][32][32] (tap, output, input), b [32]; W6 [9][32] (tap,
@@ -30,6 +30,9 @@
 #include <vector>
 
 #include "../../include/eife.h"
+
+// Defined with the grids: whether a grid records per-pass timing events.
+bool eife_grid_profiling(eife_grid g);
 
 namespace {
 
@@ -690,6 +693,7 @@ struct eife_corr_s {
   float* cs = nullptr;      // per-image RMS coarse change [max_batch]
   double* cpart = nullptr;  // its partial sums [max_batch][kCsBlocks]
   double guard = INFINITY;  // fall back when the RMS coarse change exceeds this
+  hipStream_t cap = nullptr;  // capture stream of eife_corr_run
 };
 
 namespace {
@@ -715,6 +719,7 @@ void free_corr(eife_corr_s* c) {
   hipFree(c->uc);
   hipFree(c->cs);
   hipFree(c->cpart);
+  if (c->cap) hipStreamDestroy(c->cap);
   delete c;
 }
 
@@ -949,9 +954,12 @@ int eife_corr_train_step(eife_corr c, const float* un, const float* uc, const fl
   return read_loss(c, batch, loss, s);
 }
 
-int eife_corr_infer_step(eife_corr c, eife_grid coarse, eife_grid fine, float* u, double t0, int64_t fine_steps,
-                         double theta, int* fell_back, double* out2, void* stream) {
-  if (!c || !coarse || !fine || !u || !fell_back) return cfail(EIFE_EINVAL, "null argument");
+}  // extern "C"
+
+namespace {
+
+int check_infer_args(eife_corr c, eife_grid coarse, eife_grid fine, float* u, int64_t fine_steps, double theta) {
+  if (!c || !coarse || !fine || !u) return cfail(EIFE_EINVAL, "null argument");
   if (fine_steps < 1) return cfail(EIFE_EINVAL, "fine_steps must be >= 1");
   if (!(theta >= 0.0)) return cfail(EIFE_EINVAL, "theta must be >= 0");
   int64_t nc = 0, nf = 0;
@@ -960,19 +968,30 @@ int eife_corr_infer_step(eife_corr c, eife_grid coarse, eife_grid fine, float* u
   if (nc != c->npix1 || nf != c->npix1)
     return cfail(EIFE_EINVAL, "grids hold %lld / %lld nodes, the corrector %lld", (long long)nc, (long long)nf,
                  (long long)c->npix1);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t bytes = size_t(c->npix1) * 4;
+  return EIFE_OK;
+}
+
+// The device work of one corrected step up to the indicator: copies of u, the
+// coarse step, the network, u = u_c + delta and the indicator sums (into the
+// mapped host buffer, or dres).
+int enqueue_corrected(eife_corr_s* c, eife_grid coarse, float* u, double t0, hipStream_t s) {
   const int vec = (reinterpret_cast<uintptr_t>(u) % 16) == 0;  // the library's own buffers are 256-byte aligned
   hipLaunchKernelGGL(copy2, dim3(grid1((c->npix1 + 3) / 4, 256)), dim3(256), 0, s, u, c->un_copy, c->uc, c->npix1,
                      vec);
-  int r = eife_step(coarse, c->uc, 1, EIFE_F_ALLEN_CAHN, t0, stream);
+  const int r = eife_step(coarse, c->uc, 1, EIFE_F_ALLEN_CAHN, t0, s);
   if (r != EIFE_OK) return cfail(r, "coarse step: %s", eife_last_error());
-  CRET(eife_corr_forward(c, c->un_copy, c->uc, c->gout, 1, stream));
+  CRET(eife_corr_forward(c, c->un_copy, c->uc, c->gout, 1, s));
   hipLaunchKernelGGL(apply_indicator, dim3(kIndBlocks), dim3(256), 0, s, c->un_copy, c->uc, c->gout, u, c->npix1,
                      c->dpart);
   hipLaunchKernelGGL(reduce_indicator, dim3(1), dim3(256), 0, s, c->dpart, kIndBlocks,
                      c->hres_dev ? c->hres_dev : c->dres);
   CHIP(hipGetLastError());
+  return EIFE_OK;
+}
+
+// Read the indicator (after the enqueued work) and fall back if it fails.
+int decide_corrected(eife_corr_s* c, eife_grid fine, float* u, double t0, int64_t fine_steps, double theta,
+                     int* fell_back, double* out2, hipStream_t s) {
   if (!c->hres_dev) CHIP(hipMemcpyAsync(c->hres, c->dres, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   CHIP(hipStreamSynchronize(s));
   const double ind = std::sqrt(c->hres[0]) / (std::sqrt(c->hres[1]) + 1e-12);
@@ -985,25 +1004,76 @@ int eife_corr_infer_step(eife_corr c, eife_grid coarse, eife_grid fine, float* u
   *fell_back = 0;
   if (!(ind <= theta) || !(umax <= 1.0 + kMbpTol) || !(crms <= c->guard)) {
     *fell_back = 1;
-    CHIP(hipMemcpyAsync(u, c->un_copy, bytes, hipMemcpyDeviceToDevice, s));
-    r = eife_step(fine, u, fine_steps, EIFE_F_ALLEN_CAHN, t0, stream);
+    CHIP(hipMemcpyAsync(u, c->un_copy, size_t(c->npix1) * 4, hipMemcpyDeviceToDevice, s));
+    const int r = eife_step(fine, u, fine_steps, EIFE_F_ALLEN_CAHN, t0, s);
     if (r != EIFE_OK) return cfail(r, "fine steps: %s", eife_last_error());
   }
   return EIFE_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int eife_corr_infer_step(eife_corr c, eife_grid coarse, eife_grid fine, float* u, double t0, int64_t fine_steps,
+                         double theta, int* fell_back, double* out2, void* stream) {
+  CRET(check_infer_args(c, coarse, fine, u, fine_steps, theta));
+  if (!fell_back) return cfail(EIFE_EINVAL, "null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CRET(enqueue_corrected(c, coarse, u, t0, s));
+  return decide_corrected(c, fine, u, t0, fine_steps, theta, fell_back, out2, s);
+}
+
 int eife_corr_run(eife_corr c, eife_grid coarse, eife_grid fine, float* u, double t0, double tau_coarse,
                   int64_t n_steps, int64_t fine_steps, double theta, int64_t* fallbacks, void* stream) {
-  if (!c || !fallbacks) return cfail(EIFE_EINVAL, "null argument");
+  if (!fallbacks) return cfail(EIFE_EINVAL, "null argument");
+  CRET(check_infer_args(c, coarse, fine, u, fine_steps, theta));
   if (n_steps < 0 || !(tau_coarse > 0.0)) return cfail(EIFE_EINVAL, "n_steps must be >= 0 and tau_coarse > 0");
   *fallbacks = 0;
-  for (int64_t k = 0; k < n_steps; ++k) {
+  if (n_steps == 0) return EIFE_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (eife_grid_profiling(coarse)) {
+    // timing events cannot live in a graph: step eagerly
+    for (int64_t k = 0; k < n_steps; ++k) {
+      int fb = 0;
+      const double tk = t0 + double(k) * tau_coarse;
+      CRET(enqueue_corrected(c, coarse, u, tk, s));
+      CRET(decide_corrected(c, fine, u, tk, fine_steps, theta, &fb, nullptr, s));
+      *fallbacks += fb;
+    }
+    return EIFE_OK;
+  }
+  // The accepted path of a step is captured once per call into a graph and
+  // replayed (its kernels do not depend on the step's time: the Allen-Cahn
+  // reaction is autonomous); the fallback runs eagerly.  The graph lives for
+  // this call only, so later changes to the grids or the network are seen.
+  if (!c->cap) CHIP(hipStreamCreate(&c->cap));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  CHIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+  const int rc = enqueue_corrected(c, coarse, u, t0, c->cap);
+  const hipError_t ec = hipStreamEndCapture(c->cap, &graph);
+  if (rc != EIFE_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ec != hipSuccess) return cfail(EIFE_EHIP, "graph capture: %s", hipGetErrorString(ec));
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (ei != hipSuccess) return cfail(EIFE_EHIP, "graph instantiation: %s", hipGetErrorString(ei));
+  int r = EIFE_OK;
+  for (int64_t k = 0; k < n_steps && r == EIFE_OK; ++k) {
+    const double tk = t0 + double(k) * tau_coarse;
+    if (hipGraphLaunch(exec, s) != hipSuccess) {
+      r = cfail(EIFE_EHIP, "graph launch failed");
+      break;
+    }
     int fb = 0;
-    CRET(eife_corr_infer_step(c, coarse, fine, u, t0 + double(k) * tau_coarse, fine_steps, theta, &fb, nullptr,
-                              stream));
+    r = decide_corrected(c, fine, u, tk, fine_steps, theta, &fb, nullptr, s);
     *fallbacks += fb;
   }
-  return EIFE_OK;
+  hipGraphExecDestroy(exec);
+  return r;
 }
 
 }  // extern "C"

@@ -734,5 +734,121 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
   }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent, software-pipelined column pass with the diagonal stage (single
+// grids with many column tiles).  Per tile: forward transform, stage, inverse
+// transform, as in col_fast.  After the stage, the W values of the block's next
+// tile are loaded into registers, so their latency hides behind the inverse
+// transform and the tile's stores.  H is read inside the stage: holding the
+// next tile's H values too exceeds the 128 registers per lane that 4 waves per
+// SIMD leave (the FP64 stage spills), and measured slower.
+template <typename T, int L, int PB, int PPW, int MODE>
+__global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::value))
+    col_stage_pipe(T* __restrict__ W, T* __restrict__ H, ColGeom g, const Cx<T>* tw, Diag dg, int ntx, int ntiles) {
+  using Ln = Line<T, L>;
+  constexpr int N = L / 2;
+  constexpr int n = N - 1;
+  constexpr int LP = Ln::LP;
+  constexpr int BUF = Ln::BUF;
+  constexpr int SLOTS = PB / PPW;
+  constexpr int NT = SLOTS * LP;
+  constexpr int MS = NT / PB;
+  constexpr int CIT = (n + MS - 1) / MS;
+  __shared__ Cx<T> lds[PB * BUF];
+  const int tid = threadIdx.x;
+  const int slot = tid / LP;
+  const int lane = tid - slot * LP;
+  const int tq = tid % PB;
+  const int m0 = tid / PB;
+  const int ldl = int(g.ld_line);
+  const T scale = T(1.0 / sqrt(double(L)));
+  const double tau = dg.tau, D = dg.D;
+  const double rtc2 = 1.0 / (tau * dg.c2);
+  const AxisTab ta0 = dg.ax[0], ta1 = dg.ax[1], ta2 = dg.ax[2];
+  const AxisTab line_tab = g.last_is_z ? ta2 : ta1;
+  Cx<T>* ltile = lds + tq * BUF + m0;
+  // element offset of this thread's first tile value (pair tq, row m0) in tile t
+  auto offset = [&](int t) -> int64_t {
+    return int64_t(t / ntx) * g.ld_outer + ((t % ntx) * 2 * PB + m0 * ldl + 2 * tq);
+  };
+  Cx<T> pw[CIT];
+  int t = blockIdx.x;
+  if (t < ntiles) {
+    const Cx<T>* gw = reinterpret_cast<const Cx<T>*>(W + offset(t));
+#pragma unroll
+    for (int it = 0; it < CIT; ++it)
+      if (m0 + MS * it < n) pw[it] = gw[(MS * it * ldl) / 2];
+  }
+  for (; t < ntiles; t += gridDim.x) {
+    const int outer = t / ntx;
+    const int kx0 = (t % ntx) * 2 * PB + 2 * tq;  // first column of this thread's pair
+    const int64_t off = offset(t);
+#pragma unroll
+    for (int it = 0; it < CIT; ++it)
+      if (m0 + MS * it < n) ltile[MS * it] = mask_pad(pw[it], kx0, g.ncols);
+    __syncthreads();
+    const int tn = t + gridDim.x;
+    typename Ln::Regs v;
+    {
+      // the twiddles are reloaded per transform phase (L1 hits), so they do
+      // not occupy registers during the stage
+      typename Ln::Tw twl;
+      twl.load(tw, lane);
+#pragma unroll 1
+      for (int r = 0; r < PPW; ++r) {
+        Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
+        Ln::transform(v, my, my, lane, twl, tw);
+        Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+      }
+    }
+    __syncthreads();
+    {
+      // diagonal stage: thread -> (rows m0 + MS it, pair tq)
+      Sep sxy[2];
+      const Sep so = g.last_is_z ? sep_load(ta1, outer) : sep_load(ta2, 0);
+      sxy[0] = sep_combine(sep_load(ta0, kx0), so);
+      sxy[1] = sep_combine(sep_load(ta0, kx0 + 1), so);
+      Cx<T>* hrow = reinterpret_cast<Cx<T>*>(H + off);
+#pragma unroll
+      for (int it = 0; it < CIT; ++it) {
+        const int m = m0 + MS * it;
+        if (m < n) {
+          const Sep sl = sep_load(line_tab, m);
+          const Cx<T> gv = ltile[MS * it];
+          double o0, o1, n0, n1;
+          const Cx<T> hh = hrow[(MS * it * ldl) / 2];
+          diag_fast<MODE>(sep_combine(sxy[0], sl), D, tau, rtc2, double(gv.re), double(hh.re), &o0, &n0);
+          diag_fast<MODE>(sep_combine(sxy[1], sl), D, tau, rtc2, double(gv.im), double(hh.im), &o1, &n1);
+          hrow[(MS * it * ldl) / 2] = mask_pad(Cx<T>{T(n0), T(n1)}, kx0, g.ncols);
+          ltile[MS * it] = Cx<T>{T(o0), T(o1)};
+        }
+      }
+    }
+    if (tn < ntiles) {
+      const Cx<T>* gw = reinterpret_cast<const Cx<T>*>(W + offset(tn));
+#pragma unroll
+      for (int it = 0; it < CIT; ++it)
+        if (m0 + MS * it < n) pw[it] = gw[(MS * it * ldl) / 2];
+    }
+    __syncthreads();
+    {
+      typename Ln::Tw twl;
+      twl.load(tw, lane);
+#pragma unroll 1
+      for (int r = 0; r < PPW; ++r) {
+        Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
+        Ln::transform(v, my, my, lane, twl, tw);
+        Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+      }
+    }
+    __syncthreads();
+    Cx<T>* gd = reinterpret_cast<Cx<T>*>(W + off);
+#pragma unroll
+    for (int it = 0; it < CIT; ++it)
+      if (m0 + MS * it < n) gd[(MS * it * ldl) / 2] = mask_pad(ltile[MS * it], kx0, g.ncols);
+    __syncthreads();
+  }
+}
+
 }  // namespace fast
 }  // namespace eife

@@ -251,6 +251,16 @@ def test_native_run_equals_single_steps():
     torch.cuda.synchronize()
     assert fb_a == fb_b and 0 < fb_b < 6
     assert torch.equal(a, b)
+    # with per-pass timing on, the run loop steps eagerly: same trajectory,
+    # and the coarse passes are all counted
+    coarse.profile(True)
+    d = u0.clone()
+    fb_d = c.run(coarse, fine, d, 0.0, 0.016, 6, 8, 10.0)
+    torch.cuda.synchronize()
+    counts = coarse.profile_read()
+    coarse.profile(False)
+    assert fb_d == fb_b and torch.equal(d, b)
+    assert sum(n for _, n in counts.values()) > 0
     for g in (coarse, fine):
         g.close()
     c.close()
