@@ -300,7 +300,11 @@ int eife_corr_infer_step(eife_corr c, eife_grid coarse, eife_grid fine, float* u
 
 /* n_steps corrected steps of u (eife_corr_infer_step at t0 + k tau_coarse,
  * k = 0 .. n_steps - 1) in one call; *fallbacks receives the number of steps
- * that fell back to the fine steps.  Blocks the host once per step. */
+ * that fell back to the fine steps.  The result equals n_steps calls of
+ * eife_corr_infer_step bit for bit.  Step k + 1 is enqueued before the host
+ * reads step k's indicator (assuming acceptance) and enqueued again after a
+ * fallback, so the device does not idle while the host decides; the host
+ * still waits once per step. */
 int eife_corr_run(eife_corr c, eife_grid coarse, eife_grid fine, float* u, double t0, double tau_coarse,
                   int64_t n_steps, int64_t fine_steps, double theta, int64_t* fallbacks, void* stream);
 

@@ -408,7 +408,10 @@ void col_fast_go(int mode, int pitch, int outer, int count, bool pipe, hipStream
     }
     return;
   }
-  if constexpr (!BAT) {
+  // FP32 power-of-two lines up to 512 points: the persistent pipelined stage
+  // pass fits 4 waves per SIMD without spilling; longer, radix-3 or FP64 lines
+  // keep one tile per block
+  if constexpr (!BAT && sizeof(T) == 4 && fast::IsPow2<L>::value && L <= 512) {
     // many tiles per resident block: the persistent pipelined stage pass
     const int ntx = pitch / (2 * PB);
     const int ntiles = ntx * outer;
@@ -1078,14 +1081,6 @@ int eife_profile(eife_grid g, int on) {
   g->prof_on = on != 0;
   return EIFE_OK;
 }
-
-}  // extern "C"
-
-// Library-internal (not exported through the header): whether a grid records
-// per-pass timing events, which must not be captured into a graph.
-bool eife_grid_profiling(eife_grid g) { return g && g->prof_on; }
-
-extern "C" {
 
 int eife_profile_read(eife_grid g, double* ms, int64_t* launches) {
   RET_IF(check_grid(g));

@@ -31,9 +31,6 @@
 
 #include "../../include/eife.h"
 
-// Defined with the grids: whether a grid records per-pass timing events.
-bool eife_grid_profiling(eife_grid g);
-
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -685,15 +682,18 @@ struct eife_corr_s {
   float* gout = nullptr;  // dloss/do or delta
   float* part = nullptr;
   double* dpart = nullptr;
-  double* dres = nullptr;
-  double* hres = nullptr;  // pinned, 4 doubles
+  double* dres = nullptr;      // device indicator sums, 2 slots x 4 doubles
+  double* hres = nullptr;      // pinned host copy of them, 2 slots x 4 doubles
   double* hres_dev = nullptr;  // its device address (kernels write the indicator there), or null
-  float* un_copy = nullptr;
-  float* uc = nullptr;
+  // per-slot state of a corrected step: the copy of u_n, the coarse state, and
+  // the event after its indicator; two slots let eife_corr_run enqueue step
+  // k + 1 while the host still decides step k
+  float* un_copy[2] = {nullptr, nullptr};
+  float* uc[2] = {nullptr, nullptr};
+  hipEvent_t ind_ev[2] = {nullptr, nullptr};
   float* cs = nullptr;      // per-image RMS coarse change [max_batch]
   double* cpart = nullptr;  // its partial sums [max_batch][kCsBlocks]
   double guard = INFINITY;  // fall back when the RMS coarse change exceeds this
-  hipStream_t cap = nullptr;  // capture stream of eife_corr_run
 };
 
 namespace {
@@ -715,11 +715,13 @@ void free_corr(eife_corr_s* c) {
   hipFree(c->dpart);
   hipFree(c->dres);
   if (c->hres) hipHostFree(c->hres);
-  hipFree(c->un_copy);
-  hipFree(c->uc);
+  for (int k = 0; k < 2; ++k) {
+    hipFree(c->un_copy[k]);
+    hipFree(c->uc[k]);
+    if (c->ind_ev[k]) hipEventDestroy(c->ind_ev[k]);
+  }
   hipFree(c->cs);
   hipFree(c->cpart);
-  if (c->cap) hipStreamDestroy(c->cap);
   delete c;
 }
 
@@ -850,12 +852,14 @@ int eife_corr_create(int nx, int ny, int max_batch, eife_corr* out) {
             hipMalloc(&c->gout, npix * 4) == hipSuccess &&
             hipMalloc(&c->part, size_t(kPartBlocks) * SZ_LM * 4) == hipSuccess &&
             hipMalloc(&c->dpart, size_t(std::max<int64_t>(grid1(npix, 256), 4096)) * 8) == hipSuccess &&
-            hipMalloc(&c->dres, 4 * 8) == hipSuccess &&
-            hipHostMalloc(&c->hres, 4 * 8, hipHostMallocMapped) == hipSuccess &&
-            hipMalloc(&c->un_copy, c->npix1 * 4) == hipSuccess && hipMalloc(&c->uc, c->npix1 * 4) == hipSuccess &&
+            hipMalloc(&c->dres, 8 * 8) == hipSuccess &&
+            hipHostMalloc(&c->hres, 8 * 8, hipHostMallocMapped) == hipSuccess &&
             hipMalloc(&c->cs, size_t(max_batch) * 4) == hipSuccess &&
             hipMalloc(&c->cpart, size_t(max_batch) * kCsBlocks * 8) == hipSuccess;
   for (int l = 1; ok && l <= 5; ++l) ok = hipMalloc(&c->act[l], npix * C * 2) == hipSuccess;
+  for (int k = 0; ok && k < 2; ++k)
+    ok = hipMalloc(&c->un_copy[k], c->npix1 * 4) == hipSuccess && hipMalloc(&c->uc[k], c->npix1 * 4) == hipSuccess &&
+         hipEventCreateWithFlags(&c->ind_ev[k], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     free_corr(c);
     return cfail(EIFE_ENOMEM, "corrector buffers allocation failed");
@@ -971,32 +975,39 @@ int check_infer_args(eife_corr c, eife_grid coarse, eife_grid fine, float* u, in
   return EIFE_OK;
 }
 
-// The device work of one corrected step up to the indicator: copies of u, the
-// coarse step, the network, u = u_c + delta and the indicator sums (into the
-// mapped host buffer, or dres).
-int enqueue_corrected(eife_corr_s* c, eife_grid coarse, float* u, double t0, hipStream_t s) {
+// The device work of one corrected step up to the indicator, in state slot
+// `slot`: copies of u, the coarse step, the network, u = u_c + delta, the
+// indicator sums (into the mapped host buffer, else copied there), and the
+// slot's event.
+int enqueue_corrected(eife_corr_s* c, eife_grid coarse, float* u, double t0, int slot, hipStream_t s) {
   const int vec = (reinterpret_cast<uintptr_t>(u) % 16) == 0;  // the library's own buffers are 256-byte aligned
-  hipLaunchKernelGGL(copy2, dim3(grid1((c->npix1 + 3) / 4, 256)), dim3(256), 0, s, u, c->un_copy, c->uc, c->npix1,
-                     vec);
-  const int r = eife_step(coarse, c->uc, 1, EIFE_F_ALLEN_CAHN, t0, s);
+  float* un = c->un_copy[slot];
+  float* uc = c->uc[slot];
+  hipLaunchKernelGGL(copy2, dim3(grid1((c->npix1 + 3) / 4, 256)), dim3(256), 0, s, u, un, uc, c->npix1, vec);
+  const int r = eife_step(coarse, uc, 1, EIFE_F_ALLEN_CAHN, t0, s);
   if (r != EIFE_OK) return cfail(r, "coarse step: %s", eife_last_error());
-  CRET(eife_corr_forward(c, c->un_copy, c->uc, c->gout, 1, s));
-  hipLaunchKernelGGL(apply_indicator, dim3(kIndBlocks), dim3(256), 0, s, c->un_copy, c->uc, c->gout, u, c->npix1,
-                     c->dpart);
+  CRET(eife_corr_forward(c, un, uc, c->gout, 1, s));
+  hipLaunchKernelGGL(apply_indicator, dim3(kIndBlocks), dim3(256), 0, s, un, uc, c->gout, u, c->npix1, c->dpart);
   hipLaunchKernelGGL(reduce_indicator, dim3(1), dim3(256), 0, s, c->dpart, kIndBlocks,
-                     c->hres_dev ? c->hres_dev : c->dres);
+                     (c->hres_dev ? c->hres_dev : c->dres) + 4 * slot);
   CHIP(hipGetLastError());
+  if (!c->hres_dev)
+    CHIP(hipMemcpyAsync(c->hres + 4 * slot, c->dres + 4 * slot, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  CHIP(hipEventRecord(c->ind_ev[slot], s));
   return EIFE_OK;
 }
 
-// Read the indicator (after the enqueued work) and fall back if it fails.
-int decide_corrected(eife_corr_s* c, eife_grid fine, float* u, double t0, int64_t fine_steps, double theta,
-                     int* fell_back, double* out2, hipStream_t s) {
-  if (!c->hres_dev) CHIP(hipMemcpyAsync(c->hres, c->dres, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-  CHIP(hipStreamSynchronize(s));
-  const double ind = std::sqrt(c->hres[0]) / (std::sqrt(c->hres[1]) + 1e-12);
-  const double umax = c->hres[2];
-  const double crms = std::sqrt(c->hres[1] / double(c->npix1));
+// Wait for the indicator of the step in `slot` and fall back if it fails:
+// u is restored from the slot's copy of u_n and advanced by the fine steps.
+// Work enqueued after that step (a speculative next step) is overwritten in
+// stream order by the restore.
+int decide_corrected(eife_corr_s* c, eife_grid fine, float* u, double t0, int slot, int64_t fine_steps,
+                     double theta, int* fell_back, double* out2, hipStream_t s) {
+  CHIP(hipEventSynchronize(c->ind_ev[slot]));
+  const double* hr = c->hres + 4 * slot;
+  const double ind = std::sqrt(hr[0]) / (std::sqrt(hr[1]) + 1e-12);
+  const double umax = hr[2];
+  const double crms = std::sqrt(hr[1] / double(c->npix1));
   if (out2) {
     out2[0] = ind;
     out2[1] = umax;
@@ -1004,7 +1015,7 @@ int decide_corrected(eife_corr_s* c, eife_grid fine, float* u, double t0, int64_
   *fell_back = 0;
   if (!(ind <= theta) || !(umax <= 1.0 + kMbpTol) || !(crms <= c->guard)) {
     *fell_back = 1;
-    CHIP(hipMemcpyAsync(u, c->un_copy, size_t(c->npix1) * 4, hipMemcpyDeviceToDevice, s));
+    CHIP(hipMemcpyAsync(u, c->un_copy[slot], size_t(c->npix1) * 4, hipMemcpyDeviceToDevice, s));
     const int r = eife_step(fine, u, fine_steps, EIFE_F_ALLEN_CAHN, t0, s);
     if (r != EIFE_OK) return cfail(r, "fine steps: %s", eife_last_error());
   }
@@ -1020,8 +1031,8 @@ int eife_corr_infer_step(eife_corr c, eife_grid coarse, eife_grid fine, float* u
   CRET(check_infer_args(c, coarse, fine, u, fine_steps, theta));
   if (!fell_back) return cfail(EIFE_EINVAL, "null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  CRET(enqueue_corrected(c, coarse, u, t0, s));
-  return decide_corrected(c, fine, u, t0, fine_steps, theta, fell_back, out2, s);
+  CRET(enqueue_corrected(c, coarse, u, t0, 0, s));
+  return decide_corrected(c, fine, u, t0, 0, fine_steps, theta, fell_back, out2, s);
 }
 
 int eife_corr_run(eife_corr c, eife_grid coarse, eife_grid fine, float* u, double t0, double tau_coarse,
@@ -1032,48 +1043,22 @@ int eife_corr_run(eife_corr c, eife_grid coarse, eife_grid fine, float* u, doubl
   *fallbacks = 0;
   if (n_steps == 0) return EIFE_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (eife_grid_profiling(coarse)) {
-    // timing events cannot live in a graph: step eagerly
-    for (int64_t k = 0; k < n_steps; ++k) {
-      int fb = 0;
-      const double tk = t0 + double(k) * tau_coarse;
-      CRET(enqueue_corrected(c, coarse, u, tk, s));
-      CRET(decide_corrected(c, fine, u, tk, fine_steps, theta, &fb, nullptr, s));
-      *fallbacks += fb;
-    }
-    return EIFE_OK;
-  }
-  // The accepted path of a step is captured once per call into a graph and
-  // replayed (its kernels do not depend on the step's time: the Allen-Cahn
-  // reaction is autonomous); the fallback runs eagerly.  The graph lives for
-  // this call only, so later changes to the grids or the network are seen.
-  if (!c->cap) CHIP(hipStreamCreate(&c->cap));
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  CHIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
-  const int rc = enqueue_corrected(c, coarse, u, t0, c->cap);
-  const hipError_t ec = hipStreamEndCapture(c->cap, &graph);
-  if (rc != EIFE_OK) {
-    if (graph) hipGraphDestroy(graph);
-    return rc;
-  }
-  if (ec != hipSuccess) return cfail(EIFE_EHIP, "graph capture: %s", hipGetErrorString(ec));
-  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
-  if (ei != hipSuccess) return cfail(EIFE_EHIP, "graph instantiation: %s", hipGetErrorString(ei));
-  int r = EIFE_OK;
-  for (int64_t k = 0; k < n_steps && r == EIFE_OK; ++k) {
+  // Step k + 1 is enqueued (into the other state slot) before the host reads
+  // step k's indicator, assuming step k is accepted, so the GPU does not wait
+  // for the host's decision; when step k falls back, the fine steps overwrite
+  // u in stream order and step k + 1 is enqueued again from their result.
+  CRET(enqueue_corrected(c, coarse, u, t0, 0, s));
+  for (int64_t k = 0; k < n_steps; ++k) {
+    const int slot = int(k & 1);
     const double tk = t0 + double(k) * tau_coarse;
-    if (hipGraphLaunch(exec, s) != hipSuccess) {
-      r = cfail(EIFE_EHIP, "graph launch failed");
-      break;
-    }
+    const bool ahead = k + 1 < n_steps;
+    if (ahead) CRET(enqueue_corrected(c, coarse, u, tk + tau_coarse, slot ^ 1, s));
     int fb = 0;
-    r = decide_corrected(c, fine, u, tk, fine_steps, theta, &fb, nullptr, s);
+    CRET(decide_corrected(c, fine, u, tk, slot, fine_steps, theta, &fb, nullptr, s));
+    if (fb && ahead) CRET(enqueue_corrected(c, coarse, u, tk + tau_coarse, slot ^ 1, s));
     *fallbacks += fb;
   }
-  hipGraphExecDestroy(exec);
-  return r;
+  return EIFE_OK;
 }
 
 }  // extern "C"

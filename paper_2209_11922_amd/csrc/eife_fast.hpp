@@ -766,6 +766,8 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
   const double rtc2 = 1.0 / (tau * dg.c2);
   const AxisTab ta0 = dg.ax[0], ta1 = dg.ax[1], ta2 = dg.ax[2];
   const AxisTab line_tab = g.last_is_z ? ta2 : ta1;
+  typename Ln::Tw twl;
+  twl.load(tw, lane);
   Cx<T>* ltile = lds + tq * BUF + m0;
   // element offset of this thread's first tile value (pair tq, row m0) in tile t
   auto offset = [&](int t) -> int64_t {
@@ -789,17 +791,11 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
     __syncthreads();
     const int tn = t + gridDim.x;
     typename Ln::Regs v;
-    {
-      // the twiddles are reloaded per transform phase (L1 hits), so they do
-      // not occupy registers during the stage
-      typename Ln::Tw twl;
-      twl.load(tw, lane);
 #pragma unroll 1
-      for (int r = 0; r < PPW; ++r) {
-        Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
-        Ln::transform(v, my, my, lane, twl, tw);
-        Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
-      }
+    for (int r = 0; r < PPW; ++r) {
+      Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
+      Ln::transform(v, my, my, lane, twl, tw);
+      Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
     }
     __syncthreads();
     {
@@ -831,15 +827,11 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
         if (m0 + MS * it < n) pw[it] = gw[(MS * it * ldl) / 2];
     }
     __syncthreads();
-    {
-      typename Ln::Tw twl;
-      twl.load(tw, lane);
 #pragma unroll 1
-      for (int r = 0; r < PPW; ++r) {
-        Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
-        Ln::transform(v, my, my, lane, twl, tw);
-        Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
-      }
+    for (int r = 0; r < PPW; ++r) {
+      Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
+      Ln::transform(v, my, my, lane, twl, tw);
+      Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
     }
     __syncthreads();
     Cx<T>* gd = reinterpret_cast<Cx<T>*>(W + off);

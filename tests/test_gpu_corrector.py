@@ -227,8 +227,9 @@ def test_corrector_argument_errors():
 
 
 def test_native_run_equals_single_steps():
-    """eife_corr_run gives, bit for bit, the same trajectory as repeated infer_step calls
-    (accepted steps and the transient guard's fallbacks alike)."""
+    """eife_corr_run (which enqueues each next step before reading the indicator) gives, bit
+    for bit, the same trajectory as repeated infer_step calls: accepted steps, the transient
+    guard's fallbacks, and a run where every step falls back."""
     eife = _lib()
     n = 64
     N, h = [n, n], [1.0 / n] * 2
@@ -261,6 +262,15 @@ def test_native_run_equals_single_steps():
     coarse.profile(False)
     assert fb_d == fb_b and torch.equal(d, b)
     assert sum(n for _, n in counts.values()) > 0
+    # theta = 0: every step falls back (each speculative next step is redone)
+    e = u0.clone()
+    fb_e = 0
+    for k in range(4):
+        fb_e += c.infer_step(coarse, fine, e, k * 0.016, 8, 0.0)[0]
+    f = u0.clone()
+    assert c.run(coarse, fine, f, 0.0, 0.016, 4, 8, 0.0) == fb_e == 4
+    torch.cuda.synchronize()
+    assert torch.equal(e, f)
     for g in (coarse, fine):
         g.close()
     c.close()
