@@ -287,7 +287,9 @@ def compare(net, seeds, steps, theta, guard, N=512, eps=0.02, tau_c=0.016, ratio
             "tau_fine": tau_c / ratio, "tau_coarse": tau_c}
     for k in keys:
         wall = sum(e[k]["wall_s"] for e in evs)
-        summ[k] = {"tau": evs[0][k]["tau"], "max_L2": max(e[k]["max_L2"] for e in evs),
+        per_seed = [e[k]["max_L2"] for e in evs]
+        summ[k] = {"tau": evs[0][k]["tau"], "max_L2": max(per_seed),
+                   "max_L2_per_seed": per_seed, "seeds_within_bound": sum(x <= bound for x in per_seed),
                    "fine_equiv_dof_steps_per_s": evs[0]["dofs"] * steps * ratio * len(evs) / wall,
                    "us_per_coarse_interval": wall / (len(evs) * steps) * 1e6}
         if k == "corrector":
