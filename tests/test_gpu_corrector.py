@@ -312,7 +312,7 @@ def test_trained_corrector_gain_over_plain_coarse_steps():
 
 
 def test_trainer_pipeline_small():
-    """Data generation, scale, training and calibration of the driver on a small grid."""
+    """Data generation, scale, training and calibration of the training script on a small grid."""
     from paper_2209_11922_amd import corrector as cor
     eife = _lib()
     N, windows = 64, 12
