@@ -247,7 +247,10 @@ int eife_version(void);
  *
  * Device arrays (un, uc, uf, delta, u) are FP32, [batch][ny][nx] contiguous;
  * the library keeps no pointer to them after a call.  Calls are asynchronous
- * on `stream` (NULL = default stream) unless they return host values. */
+ * on `stream` (NULL = default stream) unless they return host values.  A
+ * corrector's calls share its workspaces: use one corrector from one host
+ * thread and one stream at a time (work of two calls on different streams
+ * would race on the activations and indicator buffers). */
 #define EIFE_CORR_PARAMS 37889
 typedef struct eife_corr_s* eife_corr;
 
