@@ -173,6 +173,22 @@ def main():
     value = ndof * args.steps / dt
     log(f"bench: {dt * 1e3 / args.steps:.3f} ms/step, {value:.4e} DoF-steps/s")
 
+    # achievable streaming bandwidth: a plain device copy of one work array's
+    # size (read + write), event-timed after the measured run
+    a = torch.ones(ndof, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 2 * ndof * 4 * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    log(f"bench: plain device copy {copy_gbs:.1f} GB/s ({copy_gbs / HBM_PEAK_GBS * 100:.1f}% of HBM peak)")
+
     # per-pass event timing over a second run of the same K steps
     g.profile(True)
     g.step(u, args.steps, eife.F_ALLEN_CAHN, t_start + args.steps * TAU)
@@ -198,7 +214,8 @@ def main():
             "frac": round(dom[4] / HBM_PEAK_GBS, 4), "traffic": None if gemm else measured_traffic(dom[1]),
             "kernel": dom[1], "kernel_avg_us": round(dom[3] * 1e3, 2),
             "bytes_per_launch": BYTES_PER_DOF[dom[1]] * ndof,
-            "step_achieved_GBs": round(step_bytes / (dt / args.steps) / 1e9, 1)}
+            "step_achieved_GBs": round(step_bytes / (dt / args.steps) / 1e9, 1),
+            "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(dom[4] / copy_gbs, 4)}
     if gemm:
         # matrix-core view: 3 BF16 products of 2 (N-1) flops per DoF per transform
         gemms = GEMMS_PER_PASS[dom[1]]
