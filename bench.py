@@ -86,7 +86,13 @@ def cpu_baseline(u0, N, h, D, budget_s=15.0, max_steps=20):
     stepper.run(basis, U, problems.allen_cahn(), TAU, steps, 2, t0=TAU)
     dt = time.perf_counter() - t0
     ndof = int(np.prod([n - 1 for n in N]))
-    return {"value": ndof * steps / dt, "unit": "DoF-steps/s", "cores": cores, "kind": "oracle",
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
+    return {"value": ndof * steps / dt, "unit": "DoF-steps/s", "cores": cores, "cpu_model": model, "kind": "oracle",
             "sample": f"{steps} EIFE2 steps of the same 255^3 problem (after 1 untimed step), FP64 oracle tier C "
                       f"(scipy.fft.dstn type-I, workers={cores}), {dt:.2f} s"}
 
