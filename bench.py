@@ -97,6 +97,30 @@ def cpu_baseline(u0, N, h, D, budget_s=15.0, max_steps=20):
                       f"(scipy.fft.dstn type-I, workers={cores}), {dt:.2f} s"}
 
 
+def accuracy_vs_f64(torch, eife, u0, N, h, D, steps):
+    """Relative max-norm error of the benchmark problem after `steps` EIFE2 steps for the FP32
+    sine-transform path and the split-BF16 matrix-core path, against the FP64 sine-transform
+    path (itself held to the FP64 oracle at 1e-12 by the parity tests)."""
+    def run(dtype, kind):
+        g = eife.Grid(N, h, D, dtype)
+        if kind == "gemm":
+            g.set_transform(eife.binding.TX_GEMM_SPLITBF16)
+        g.set_phi(TAU, 2)
+        u = torch.tensor(u0, dtype=torch.float64 if dtype == "f64" else torch.float32, device="cuda")
+        g.step(u, steps, eife.F_ALLEN_CAHN, 0.0)
+        torch.cuda.synchronize()
+        g.close()
+        return u.double()
+    ref = run("f64", "fft")
+    scale = float(ref.abs().max())
+    out = {"steps": steps, "reference": "FP64 sine-transform path"}
+    for key, dtype, kind in (("fft_f32", "f32", "fft"), ("gemm_bf16x3", "f32", "gemm")):
+        out[key] = float((run(dtype, kind) - ref).abs().max()) / scale
+    log(f"bench: after {steps} steps, rel max error vs FP64: FFT FP32 {out['fft_f32']:.2e}, "
+        f"split-BF16 GEMM {out['gemm_bf16x3']:.2e}")
+    return out
+
+
 def corrector_comparison(nseeds):
     """Learned corrector vs plain EIFE2 at equal L2 error (2D Allen-Cahn, eps 0.02,
     511^2 DoFs, coarse tau 0.016, fine 0.002, 500 coarse steps, unseen seeds 1000...)."""
@@ -302,6 +326,10 @@ def main():
                         "frac": round(tfs / BF16_PEAK_TFS, 4), "flops_per_launch": flops}
         log(f"  dominant pass {dom[1]}: {tfs:.1f} TFLOP/s BF16 ({tfs / BF16_PEAK_TFS * 100:.1f}% of dense peak)")
 
+    g.close()
+    del u
+    acc = accuracy_vs_f64(torch, eife, u0, N, h, D, args.steps)
+
     corr = None
     if not args.no_corrector and not gemm:
         corr = corrector_comparison(args.corr_seeds)
@@ -318,9 +346,8 @@ def main():
                                   "u0 uniform[-0.9,0.9] seed 0, EIFE2 c2=1/2 tau=0.005, "
                                   + ("split-BF16 matrix-core sine transforms" if gemm else "FP32 sine-transform path"),
                       "dofs": ndof, "tau": TAU, "scheme": "EIFE2", "transform": args.transform},
-           "roofline": roof, "cpu_baseline": cpu, "corrector": corr}
+           "roofline": roof, "cpu_baseline": cpu, "accuracy": acc, "corrector": corr}
     print(json.dumps(out), flush=True)
-    g.close()
 
 
 def bench_batched(args, torch, eife):
