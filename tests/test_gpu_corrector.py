@@ -271,6 +271,13 @@ def test_native_run_equals_single_steps():
     assert c.run(coarse, fine, f, 0.0, 0.016, 4, 8, 0.0) == fb_e == 4
     torch.cuda.synchronize()
     assert torch.equal(e, f)
+    # one step (nothing enqueued ahead) and zero steps
+    g1, g2 = b.clone(), b.clone()
+    fb1 = c.infer_step(coarse, fine, g1, 0.096, 8, 10.0)[0]
+    assert c.run(coarse, fine, g2, 0.096, 0.016, 1, 8, 10.0) == fb1
+    assert c.run(coarse, fine, g2, 0.112, 0.016, 0, 8, 10.0) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
     for g in (coarse, fine):
         g.close()
     c.close()
