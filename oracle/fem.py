@@ -4,6 +4,11 @@ Unknowns are the nodal values at interior nodes of the uniform partition of
 each axis (Section 2.1, the space V_h of eq. (2.4)); Dirichlet nodes are
 dropped.  Arrays of nodal values have shape (n_{d-1}, ..., n_0) with axis 0
 (x) fastest, n_a = N_a - 1, so a flat index is sum_a i_a * prod_{b<a} n_b.
+
+With periodic boundary conditions (the variant discussed at the end of
+Section 4) the space is spanned by the periodic extensions of the hat
+functions: node N_a coincides with node 0, the unknowns are the N_a nodes
+j = 0 .. N_a - 1 of every axis and n_a = N_a.
 """
 import itertools
 
@@ -23,15 +28,28 @@ def p1_element_matrices(h):
     return me, ke
 
 
-def assemble_1d(N, h):
-    """1D interior mass matrix A and stiffness matrix B (dense, (N-1)x(N-1)).
+def assemble_1d(N, h, bc="dirichlet"):
+    """1D mass matrix A and stiffness matrix B (dense).
 
     Built by summing element matrices over the N elements of the uniform
-    partition and removing the two boundary nodes (homogeneous Dirichlet
-    data, eq. (2.1)).  Section 4 states the result as A = (h/6) R and
-    B = (1/h) G^D; the tests check that independently.
+    partition.  Dirichlet: the two boundary nodes are removed (homogeneous
+    data, eq. (2.1)), (N-1)x(N-1); Section 4 states the result as A = (h/6) R
+    and B = (1/h) G^D.  Periodic: element N-1 joins node N-1 to node 0, NxN;
+    Section 4 states B = (1/h) G^P.  The tests check both independently.
     """
     me, ke = p1_element_matrices(h)
+    if bc == "periodic":
+        m = np.zeros((N, N))
+        k = np.zeros((N, N))
+        for e in range(N):
+            idx = [e, (e + 1) % N]
+            for a in range(2):
+                for b in range(2):
+                    m[idx[a], idx[b]] += me[a, b]
+                    k[idx[a], idx[b]] += ke[a, b]
+        return m, k
+    if bc != "dirichlet":
+        raise ValueError(bc)
     full_m = np.zeros((N + 1, N + 1))
     full_k = np.zeros((N + 1, N + 1))
     for e in range(N):
@@ -43,6 +61,11 @@ def assemble_1d(N, h):
     return full_m[1:N, 1:N].copy(), full_k[1:N, 1:N].copy()
 
 
+def n_unknowns(N, bc="dirichlet"):
+    """Unknowns per axis: N - 1 (Dirichlet) or N (periodic)."""
+    return N if bc == "periodic" else N - 1
+
+
 def _kron_list(mats):
     out = sp.csr_matrix(mats[0])
     for m in mats[1:]:
@@ -50,7 +73,7 @@ def _kron_list(mats):
     return out
 
 
-def mass_stiffness(N, h, D):
+def mass_stiffness(N, h, D, bc="dirichlet"):
     """Global mass M and stiffness K (sparse CSR) of the tensor Q1 space.
 
     Section 4, eq. (4.1): M = A_z (x) A_y (x) A_x and
@@ -59,7 +82,7 @@ def mass_stiffness(N, h, D):
     fastest index, matching the array layout of this package.
     """
     d = len(N)
-    ones = [assemble_1d(N[a], h[a]) for a in range(d)]
+    ones = [assemble_1d(N[a], h[a], bc) for a in range(d)]
     A = [ones[a][0] for a in range(d)]
     B = [ones[a][1] for a in range(d)]
     M = _kron_list([A[a] for a in reversed(range(d))])
@@ -71,7 +94,7 @@ def mass_stiffness(N, h, D):
     return M, (D * K).tocsr()
 
 
-def q1_quadrature_assembly(N, h, D, origin=None):
+def q1_quadrature_assembly(N, h, D, origin=None, bc="dirichlet"):
     """Mass and stiffness by Gauss quadrature over each Q1 element (dense).
 
     Independent of the Kronecker formula: for every box element, the 2^d
@@ -82,7 +105,8 @@ def q1_quadrature_assembly(N, h, D, origin=None):
     Only meant for tiny grids.
     """
     d = len(N)
-    n = [N[a] - 1 for a in range(d)]
+    periodic = bc == "periodic"
+    n = [n_unknowns(N[a], bc) for a in range(d)]
     ndof = int(np.prod(n))
     strides = [int(np.prod(n[:a])) for a in range(d)]
     gp = np.array([-1.0, 1.0]) / np.sqrt(3.0)  # on [-1, 1]
@@ -97,7 +121,9 @@ def q1_quadrature_assembly(N, h, D, origin=None):
         gidx = []
         for c in corners:
             node = [elem[a] + c[a] for a in range(d)]
-            if any(node[a] == 0 or node[a] == N[a] for a in range(d)):
+            if periodic:
+                gidx.append(sum((node[a] % N[a]) * strides[a] for a in range(d)))
+            elif any(node[a] == 0 or node[a] == N[a] for a in range(d)):
                 gidx.append(-1)
             else:
                 gidx.append(sum((node[a] - 1) * strides[a] for a in range(d)))
@@ -131,24 +157,25 @@ def q1_quadrature_assembly(N, h, D, origin=None):
     return M, K
 
 
-def node_coords(N, h, origin=None):
-    """Coordinates of the interior nodes, one 1-D array per axis.
+def node_coords(N, h, origin=None, bc="dirichlet"):
+    """Coordinates of the unknown nodes, one 1-D array per axis.
 
-    Node j of axis a sits at a_a + j * h_a (Section 2.1); interior nodes are
-    j = 1 .. N_a - 1.
+    Node j of axis a sits at a_a + j * h_a (Section 2.1); the unknowns are
+    j = 1 .. N_a - 1 (Dirichlet) or j = 0 .. N_a - 1 (periodic).
     """
     d = len(N)
     origin = [0.0] * d if origin is None else list(origin)
-    return [origin[a] + h[a] * np.arange(1, N[a]) for a in range(d)]
+    first = 0 if bc == "periodic" else 1
+    return [origin[a] + h[a] * np.arange(first, N[a]) for a in range(d)]
 
 
-def mesh(N, h, origin=None):
+def mesh(N, h, origin=None, bc="dirichlet"):
     """Broadcastable coordinate arrays shaped like a nodal array (x fastest)."""
     d = len(N)
-    xs = node_coords(N, h, origin)
+    xs = node_coords(N, h, origin, bc)
     out = []
     for a in range(d):
         shape = [1] * d
-        shape[d - 1 - a] = N[a] - 1
+        shape[d - 1 - a] = len(xs[a])
         out.append(xs[a].reshape(shape))
     return out

@@ -14,9 +14,9 @@ import numpy as np
 from . import fem
 
 
-def discrete_norms(N, h, e):
+def discrete_norms(N, h, e, bc="dirichlet"):
     """Return (L2, H1, max) of the finite element function with nodal values e."""
-    M, K1 = fem.mass_stiffness(N, h, 1.0)
+    M, K1 = fem.mass_stiffness(N, h, 1.0, bc)
     v = np.asarray(e, dtype=np.float64).reshape(-1)
     m2 = float(v @ (M @ v))
     k2 = float(v @ (K1 @ v))
@@ -35,6 +35,18 @@ def allen_cahn_energy(N, h, D, U):
     grad = 0.5 * D * float(v @ (K1 @ v))
     pot = float(np.prod(h)) * float(np.sum(0.25 * (v * v - 1.0) ** 2))
     return grad + pot
+
+
+def flory_huggins_energy(N, h, D, U, theta, theta_c, bc="periodic"):
+    """Discrete Example 5.3 energy: (D/2) U^T K_1 U + prod(h) sum_i F(U_i) with
+    F(u) = (theta/2)((1 + u) ln(1 + u) + (1 - u) ln(1 - u)) - (theta_c/2) u^2,
+    the gradient term from the stiffness matrix and the potential by nodal
+    quadrature (Section 5.2 states the continuous functional)."""
+    _, K1 = fem.mass_stiffness(N, h, 1.0, bc)
+    v = np.asarray(U, dtype=np.float64).reshape(-1)
+    grad = 0.5 * D * float(v @ (K1 @ v))
+    F = 0.5 * theta * ((1.0 + v) * np.log1p(v) + (1.0 - v) * np.log1p(-v)) - 0.5 * theta_c * v * v
+    return grad + float(np.prod(h)) * float(np.sum(F))
 
 
 def quadrature_errors_2d(N, h, origin, U, exact, exact_grad, t, chunk_rows=64):

@@ -25,6 +25,27 @@ def allen_cahn():
     return lambda t, X, U: U - U ** 3
 
 
+def flory_huggins(theta, theta_c):
+    """Example 5.3 reaction (theta/2) ln((1 - u)/(1 + u)) + theta_c u, |u| < 1.
+
+    Its positive root gamma (f(gamma) = 0) is the maximum bound of the
+    solution; theta = 0.8, theta_c = 1.6 give gamma = 0.9575..."""
+    return lambda t, X, U: 0.5 * theta * np.log((1.0 - U) / (1.0 + U)) + theta_c * U
+
+
+def flory_huggins_bound(theta, theta_c):
+    """Positive root of (theta/2) ln((1 - g)/(1 + g)) + theta_c g = 0 (bisection)."""
+    lo, hi = 1e-12, 1.0 - 1e-15
+    f = lambda g: 0.5 * theta * np.log((1.0 - g) / (1.0 + g)) + theta_c * g
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid) > 0.0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
 def _sine_product(X):
     s = 1.0
     for x in X:

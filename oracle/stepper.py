@@ -44,7 +44,7 @@ def run(basis, u0, f, tau, n_steps, stages, c2=0.5, t0=0.0, load="lumped",
         raise ValueError("stages must be 1 or 2")
     if not (0.0 < c2 <= 1.0):
         raise ValueError("c2 must lie in (0, 1]")
-    X = fem.mesh(basis.N, basis.h, origin)
+    X = fem.mesh(basis.N, basis.h, origin, getattr(basis, "bc", "dirichlet"))
     z = -tau * basis.lam
     E = phi(0, z)
     P1 = phi(1, z)
