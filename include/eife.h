@@ -18,9 +18,10 @@
  *     Nothing is thrown across the ABI.  eife_last_error() returns a message
  *     for the calling thread's most recent failure.
  *   - Nodal arrays ("u") live in device memory owned by the caller: the
- *     values at interior nodes, (N_{d-1}-1) x ... x (N_0-1) contiguous
- *     elements of the grid's dtype, axis 0 (x) fastest, boundary nodes not
- *     stored.  The library keeps no pointer to them after a call returns.
+ *     values at the unknown nodes, n_{d-1} x ... x n_0 contiguous elements
+ *     of the grid's dtype (n_a = N_a - 1 interior nodes, boundary nodes not
+ *     stored; n_a = N_a for periodic grids), axis 0 (x) fastest.  The
+ *     library keeps no pointer to them after a call returns.
  *   - The grid owns its device workspaces (spectral state, work array,
  *     tables), allocated by eife_create_grid and released by
  *     eife_destroy_grid.  A grid may be used from one host thread at a time.
@@ -61,7 +62,9 @@ enum eife_fkind {
   EIFE_F_EX51 = 3,       /* Section 5.1, Example 5.1 (d = 2):
                             f = -(pi^2/2) u + (pi^2/2) e^{-pi^2 t} sin(pi x) sin(pi y) */
   EIFE_F_CONST = 4,      /* f = c0, independent of u, x and t (c0 from eife_set_forcing) */
-  EIFE_F_AFFINE_T = 5    /* f = c0 + c1 t, independent of u and x */
+  EIFE_F_AFFINE_T = 5,   /* f = c0 + c1 t, independent of u and x */
+  EIFE_F_FLORY_HUGGINS = 6 /* Section 5.2, Example 5.3: f = (theta/2) ln((1 - u)/(1 + u)) + theta_c u,
+                              theta = c0, theta_c = c1 from eife_set_forcing; needs |u| < 1 */
 };
 
 /* How P_h f(t, u_h) is formed from the nodal values of f (the paper's load
@@ -71,10 +74,14 @@ enum eife_load {
   EIFE_LOAD_NODAL = 1   /* P_h f replaced by the interpolant of the nodal values f(t, u_i) */
 };
 
-/* Create a grid: d in {1,2,3}; N[a] >= 2 intervals on axis a (N[a]-1 interior
- * nodes, N[a] <= 4096 and of the form 2^i 3^j); h[a] > 0 the mesh
- * width; D > 0 the diffusion coefficient (eq. (1.1)); bc must be
- * EIFE_BC_DIRICHLET (EIFE_BC_PERIODIC returns EIFE_EUNSUPPORTED); dtype is
+/* Create a grid: d in {1,2,3}; N[a] >= 2 intervals on axis a (N[a] <= 4096
+ * and of the form 2^i 3^j); h[a] > 0 the mesh width; D > 0 the diffusion
+ * coefficient (eq. (1.1)); bc is EIFE_BC_DIRICHLET (unknowns: the N[a] - 1
+ * interior nodes of each axis, the sine basis of Section 4) or
+ * EIFE_BC_PERIODIC (the variant at the end of Section 4: unknowns at the
+ * N[a] nodes j h[a], j = 0 .. N[a] - 1, of each axis, circulant matrices
+ * diagonalised by the real orthonormal Fourier basis; generic passes only,
+ * no split-BF16 transform, no batches, no EIFE_F_MMS_U2 / EIFE_F_EX51); dtype is
  * EIFE_F32 or EIFE_F64, the precision of nodal arrays and transforms
  * (eigenvalue and phi factors are always formed in double).  The origin
  * defaults to 0, c2 to 1/2 and the load to EIFE_LOAD_LUMPED.  On success
@@ -124,7 +131,7 @@ enum eife_transform {
  * selection.  Unknown kind: EIFE_EINVAL.  Batches ignore this setting. */
 int eife_set_transform(eife_grid g, int kind);
 
-/* Parameters c0, c1 of EIFE_F_CONST / EIFE_F_AFFINE_T. */
+/* Parameters c0, c1 of EIFE_F_CONST / EIFE_F_AFFINE_T / EIFE_F_FLORY_HUGGINS. */
 int eife_set_forcing(eife_grid g, double c0, double c1);
 
 /* Advance the nodal values u (device pointer, in place) by n_steps >= 0
@@ -217,7 +224,7 @@ int eife_batch_autotune(eife_batch b, const char* cache_path, void* stream);
  * class. */
 int eife_batch_class_info(eife_batch b, int k, int32_t* out);
 
-/* Number of interior nodes of the grid (elements of a nodal array). */
+/* Number of unknown nodes of the grid (elements of a nodal array). */
 int eife_grid_size(eife_grid g, int64_t* count);
 
 /* Message describing the calling thread's most recent failed call. */

@@ -6,6 +6,8 @@ PyTorch only for device memory and streams.  There is no fallback: without
 the built library every entry point raises.
 """
 from .binding import (  # noqa: F401
+    BC_DIRICHLET,
+    BC_PERIODIC,
     Batch,
     Corrector,
     EIFEError,
@@ -16,6 +18,7 @@ from .binding import (  # noqa: F401
     F_ALLEN_CAHN,
     F_CONST,
     F_EX51,
+    F_FLORY_HUGGINS,
     F_MMS_U2,
     F_ZERO,
     library_path,

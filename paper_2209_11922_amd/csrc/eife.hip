@@ -83,7 +83,8 @@ bool factor_plan(int L, FftPlan* pl) {
 struct eife_grid_s {
   int d = 0;
   int N[3] = {2, 2, 2};
-  int n[3] = {1, 1, 1};  // interior nodes per axis (virtual axes: 1)
+  int n[3] = {1, 1, 1};  // unknowns per axis: N - 1 (Dirichlet), N (periodic); virtual axes: 1
+  bool per[3] = {false, false, false};  // periodic axis (real axes of a periodic grid)
   double h[3] = {1, 1, 1};
   double a[3] = {0, 0, 0};
   double D = 1;
@@ -195,8 +196,10 @@ int upload_tables(eife_grid_s* g) {
         lam[k] = 1.0;
         continue;
       }
-      lam[k] = lam1d(g->N[ax], g->h[ax], k + 1);
-      w[k] = (g->load == EIFE_LOAD_LUMPED) ? g->h[ax] / lamA1d(g->N[ax], g->h[ax], k + 1) : 1.0;
+      // sine index k + 1 (angle (k + 1) pi / N); periodic position k (angle 2 k pi / N)
+      const int kk = g->per[ax] ? 2 * k : k + 1;
+      lam[k] = lam1d(g->N[ax], g->h[ax], kk);
+      w[k] = (g->load == EIFE_LOAD_LUMPED) ? g->h[ax] / lamA1d(g->N[ax], g->h[ax], kk) : 1.0;
       if (g->phi_ready) {
         const double z = -g->tau * g->D * lam[k];
         M[k] = std::expm1(z);
@@ -462,7 +465,7 @@ void col_fast_launch(int var, int mode, int pitch, int outer, int count, hipStre
 template <typename T>
 bool try_row_fast(const eife_grid_s* g, int var, int mode, int count, hipStream_t s, const T* src, T* dst, T* dst2,
                   const RowGeom& rg, const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
-  if (g->transform != EIFE_TX_FFT || !fast_len<T>(g->N[0])) return false;
+  if (g->transform != EIFE_TX_FFT || g->per[0] || !fast_len<T>(g->N[0])) return false;
   switch (g->N[0]) {
     case 64: row_fast_launch<T, 128>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
     case 128: row_fast_launch<T, 256>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
@@ -482,7 +485,7 @@ bool try_row_fast(const eife_grid_s* g, int var, int mode, int count, hipStream_
 template <typename T>
 bool try_col_fast(const eife_grid_s* g, int var, int axis, int mode, int outer, int count, hipStream_t s, T* W, T* H,
                   const ColGeom& cg, const Cx<T>* tw, const Diag& dg, const ColInst<T>* ci) {
-  if (g->transform != EIFE_TX_FFT || !fast_len<T>(g->N[axis])) return false;
+  if (g->transform != EIFE_TX_FFT || g->per[axis] || !fast_len<T>(g->N[axis])) return false;
   switch (g->N[axis]) {
     case 64: col_fast_launch<T, 128>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
     case 128: col_fast_launch<T, 256>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
@@ -521,6 +524,33 @@ void col_generic_go(int mode, dim3 grid, size_t shm, hipStream_t s, T* W, T* H, 
     hipLaunchKernelGGL((col_pass<T, COL_STAGE_B, BATC>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
   else
     hipLaunchKernelGGL((col_pass<T, COL_ETD1, BATC>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+}
+
+// Periodic lines (generic passes only).
+template <typename T>
+void row_periodic_go(int mode, dim3 grid, size_t shm, hipStream_t s, const T* src, T* dst, T* dst2,
+                     const RowGeom& rg, const Cx<T>* tw, const Forcing& F) {
+  if (mode == ROW_PHYS)
+    hipLaunchKernelGGL((row_pass_per<T, ROW_PHYS>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F);
+  else if (mode == ROW_FWD_USER)
+    hipLaunchKernelGGL((row_pass_per<T, ROW_FWD_USER>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F);
+  else
+    hipLaunchKernelGGL((row_pass_per<T, ROW_INV_USER>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F);
+}
+
+template <typename T>
+void col_periodic_go(int mode, dim3 grid, size_t shm, hipStream_t s, T* W, T* H, const ColGeom& cg,
+                     const Cx<T>* tw, const Diag& dg) {
+  if (mode == COL_PLAIN)
+    hipLaunchKernelGGL((col_pass_per<T, COL_PLAIN>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+  else if (mode == COL_PLAIN_INV)
+    hipLaunchKernelGGL((col_pass_per<T, COL_PLAIN_INV>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+  else if (mode == COL_STAGE_A)
+    hipLaunchKernelGGL((col_pass_per<T, COL_STAGE_A>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+  else if (mode == COL_STAGE_B)
+    hipLaunchKernelGGL((col_pass_per<T, COL_STAGE_B>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+  else
+    hipLaunchKernelGGL((col_pass_per<T, COL_ETD1>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
 }
 
 // ---------------------------------------------------------------------------
@@ -682,7 +712,7 @@ bool try_col_gemm(const eife_grid_s* g, int axis, int mode, int outer, hipStream
 // prologue (ROW_FWD_PHYS) wherever the specialised row kernels run.
 template <typename T>
 bool fused_first_row(const eife_grid_s* g) {
-  return g->transform == EIFE_TX_FFT && fast_len<T>(g->N[0]);
+  return g->transform == EIFE_TX_FFT && !g->per[0] && fast_len<T>(g->N[0]);
 }
 
 // A launch of one pass over `count` instances shaped like grid `g`.
@@ -716,7 +746,10 @@ int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, i
       !try_row_fast<T>(g, B.var_row, mode, B.count, s, src, dst, dst2, rg, tw, F, ri)) {
     const size_t shm = lds_bytes(g, rg.P, rg.pl.L);
     dim3 grid((rg.nrows + 2 * rg.P - 1) / (2 * rg.P), B.count);
-    if (ri)
+    if (g->per[0]) {
+      if (ri || mode == ROW_FWD_PHYS) return fail(EIFE_EUNSUPPORTED, "periodic row pass variant");
+      row_periodic_go<T>(mode, grid, shm, s, src, dst, dst2, rg, tw, F);
+    } else if (ri)
       row_generic_go<T, true>(mode, grid, shm, s, src, dst, dst2, rg, tw, F, ri);
     else
       row_generic_go<T, false>(mode, grid, shm, s, src, dst, dst2, rg, tw, F, ri);
@@ -764,7 +797,10 @@ int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, h
       !try_col_fast<T>(g, B.var_col, axis, mode, outer, B.count, s, W, H, cg, tw, dg, ci)) {
     const size_t shm = lds_bytes(g, cg.P, cg.pl.L);
     dim3 grid(g->pitch / (2 * cg.P), outer, B.count);
-    if (ci)
+    if (g->per[axis]) {
+      if (ci) return fail(EIFE_EUNSUPPORTED, "periodic batched column pass");
+      col_periodic_go<T>(mode, grid, shm, s, W, H, cg, tw, dg);
+    } else if (ci)
       col_generic_go<T, true>(mode, grid, shm, s, W, H, cg, tw, dg, ci);
     else
       col_generic_go<T, false>(mode, grid, shm, s, W, H, cg, tw, dg, ci);
@@ -787,6 +823,9 @@ int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipS
   const Diag dg = make_diag(g);
   const bool three = g->d == 3;
   const int last = three ? 2 : 1;
+  // the y pass after the last-axis pass goes back to nodal y (the sine
+  // transform is its own inverse, the real Fourier transform is not)
+  const int inv_plain = g->per[1] ? COL_PLAIN_INV : COL_PLAIN;
   const Forcing F0 = make_forcing(g, f_kind, t0);
   // prologue: H = S u and W = S_x u, or W = S_x f(t0, u) when the first
   // reaction is fused in
@@ -800,13 +839,13 @@ int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipS
       RET_IF(launch_row<T>(g, ROW_PHYS, W, g->pitch, W, g->pitch, nullptr, make_forcing(g, f_kind, tn), s));
     if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, W, H, dg, s));
     RET_IF(launch_col<T>(g, last, g->stages == 1 ? COL_ETD1 : COL_STAGE_A, W, H, dg, s));
-    if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, W, H, dg, s));
+    if (three) RET_IF(launch_col<T>(g, 1, inv_plain, W, H, dg, s));
     if (g->stages == 2) {
       RET_IF(launch_row<T>(g, ROW_PHYS, W, g->pitch, W, g->pitch, nullptr,
                            make_forcing(g, f_kind, tn + g->c2 * g->tau), s));
       if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, W, H, dg, s));
       RET_IF(launch_col<T>(g, last, COL_STAGE_B, W, H, dg, s));
-      if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, W, H, dg, s));
+      if (three) RET_IF(launch_col<T>(g, 1, inv_plain, W, H, dg, s));
     }
   }
   // epilogue: u = S_x^{-1} W
@@ -820,6 +859,7 @@ NormGeom make_norm_geom(const eife_grid_s* g) {
   ng.cellvol = 1.0;
   for (int a = 0; a < 3; ++a) {
     ng.n[a] = g->n[a];
+    ng.per[a] = g->per[a] ? 1 : 0;
     if (a < g->d) {
       const double h = g->h[a];
       ng.ad[a] = 4.0 * h / 6.0;
@@ -890,8 +930,7 @@ int eife_create_grid(int d, const int32_t* N, const double* h, double D, int bc,
   if (d < 1 || d > 3) return fail(EIFE_EINVAL, "d must be 1, 2 or 3 (got %d)", d);
   if (!N || !h) return fail(EIFE_EINVAL, "N and h must not be null");
   if (!(D > 0.0) || !std::isfinite(D)) return fail(EIFE_EINVAL, "D must be a positive finite number");
-  if (bc == EIFE_BC_PERIODIC) return fail(EIFE_EUNSUPPORTED, "periodic boundary conditions are not implemented");
-  if (bc != EIFE_BC_DIRICHLET) return fail(EIFE_EINVAL, "unknown boundary condition %d", bc);
+  if (bc != EIFE_BC_DIRICHLET && bc != EIFE_BC_PERIODIC) return fail(EIFE_EINVAL, "unknown boundary condition %d", bc);
   if (dtype != EIFE_F32 && dtype != EIFE_F64) return fail(EIFE_EINVAL, "unknown dtype %d", dtype);
   eife_grid_s* g = new eife_grid_s();
   g->d = d;
@@ -912,11 +951,13 @@ int eife_create_grid(int d, const int32_t* N, const double* h, double D, int bc,
       return fail(EIFE_EINVAL, "h[%d] must be a positive finite number", a);
     }
     g->N[a] = N[a];
-    g->n[a] = N[a] - 1;
+    g->per[a] = bc == EIFE_BC_PERIODIC;
+    g->n[a] = g->per[a] ? N[a] : N[a] - 1;
     g->h[a] = h[a];
   }
   for (int a = 0; a < 3; ++a) {
-    if (!factor_plan(2 * g->N[a], &g->plan[a])) {
+    // FFT length: the odd extension (2N) of a sine line, the line itself (N) when periodic
+    if (!factor_plan(g->per[a] ? g->N[a] : 2 * g->N[a], &g->plan[a])) {
       const int bad = g->N[a];
       delete g;
       return fail(EIFE_EUNSUPPORTED, "N = %d is not of the form 2^i 3^j", bad);
@@ -1041,6 +1082,7 @@ int eife_set_transform(eife_grid g, int kind) {
     return fail(EIFE_EINVAL, "unknown transform kind %d", kind);
   if (kind == EIFE_TX_GEMM_SPLITBF16) {
     if (g->dtype != EIFE_F32) return fail(EIFE_EUNSUPPORTED, "the split-BF16 transform takes FP32 grids only");
+    if (g->per[0]) return fail(EIFE_EUNSUPPORTED, "the split-BF16 transform takes Dirichlet grids only");
     for (int a = 0; a < g->d; ++a)
       if (g->N[a] > 1024) return fail(EIFE_EUNSUPPORTED, "the split-BF16 transform takes N <= 1024 (N = %d)", g->N[a]);
     RET_IF(gemm_attrs_all());
@@ -1104,8 +1146,10 @@ int eife_step(eife_grid g, void* u, int64_t n_steps, int f_kind, double t0, void
   RET_IF(check_grid(g));
   if (!u) return fail(EIFE_EINVAL, "u is null");
   if (n_steps < 0) return fail(EIFE_EINVAL, "n_steps must be >= 0");
-  if (f_kind < EIFE_F_ZERO || f_kind > EIFE_F_AFFINE_T) return fail(EIFE_EINVAL, "unknown f_kind %d", f_kind);
+  if (f_kind < EIFE_F_ZERO || f_kind > EIFE_F_FLORY_HUGGINS) return fail(EIFE_EINVAL, "unknown f_kind %d", f_kind);
   if (f_kind == EIFE_F_EX51 && g->d != 2) return fail(EIFE_EINVAL, "EIFE_F_EX51 is a 2D problem");
+  if ((f_kind == EIFE_F_MMS_U2 || f_kind == EIFE_F_EX51) && g->per[0])
+    return fail(EIFE_EUNSUPPORTED, "f_kind %d is a Dirichlet problem", f_kind);
   if (!std::isfinite(t0)) return fail(EIFE_EINVAL, "t0 must be finite");
   if (!g->phi_ready) return fail(EIFE_ESTATE, "eife_set_phi must be called before eife_step");
   if (n_steps == 0) return EIFE_OK;

@@ -182,6 +182,18 @@ template <int MODE>
 __device__ __forceinline__ void diag_apply(const Sep& s, double D, double tau, double c2, double g, double h,
                                            double* out, double* nh) {
   const double G = g * s.w;
+  if (s.lam == 0.0) {
+    // the zero mode of a periodic grid (Lam = 0): e^0 = 1, phi_1(0) = 1, phi_2(0) = 1/2
+    if (MODE == DIAG_ETD1) {
+      *out = *nh = h + tau * G;
+    } else if (MODE == DIAG_A) {
+      *out = h + c2 * tau * G;
+      *nh = h + tau * (1.0 - 0.5 / c2) * G;
+    } else {
+      *out = *nh = h + 0.5 * tau / c2 * G;
+    }
+    return;
+  }
   const double rL = 1.0 / (D * s.lam);
   if (MODE == DIAG_ETD1) {
     const double un = h + s.M * h - s.M * rL * G;
@@ -215,7 +227,7 @@ struct Forcing {
   double h[3];
 };
 
-enum FKind { FK_ZERO = 0, FK_AC = 1, FK_MMS = 2, FK_EX51 = 3, FK_CONST = 4, FK_AFFINE = 5 };
+enum FKind { FK_ZERO = 0, FK_AC = 1, FK_MMS = 2, FK_EX51 = 3, FK_CONST = 4, FK_AFFINE = 5, FK_FH = 6 };
 
 // Per-instance data of a batched launch (instances of one size class share
 // geometry and launch shape; blockIdx.y (row passes) or blockIdx.z (column
@@ -247,6 +259,8 @@ __device__ __forceinline__ T reaction(const Forcing& F, T u, int ix, int iy, int
       return T(F.c0);
     case FK_AFFINE:
       return T(F.c0 + F.c1 * F.t);
+    case FK_FH:  // Example 5.3: (theta/2) ln((1 - u)/(1 + u)) + theta_c u, theta = c0, theta_c = c1
+      return T(0.5) * T(F.c0) * log((T(1) - u) / (T(1) + u)) + T(F.c1) * u;
     case FK_MMS: {
       double s = sinpi(F.a[0] + (ix + 1) * F.h[0]);
       if (F.d > 1) s *= sinpi(F.a[1] + (iy + 1) * F.h[1]);
@@ -527,12 +541,228 @@ __global__ void __launch_bounds__(256) col_pass(T* W, T* H, ColGeom g, const Cx<
 }
 
 // ---------------------------------------------------------------------------
+// Periodic lines (the variant at the end of Section 4).  The 1D matrices are
+// circulant, diagonalised by the real orthonormal Fourier basis; position r of
+// a line holds the coefficient of the constant (r = 0), of sqrt(2/N) cos(2 pi k j/N)
+// (r = k, 1 <= k < N/2), of sqrt(2/N) sin(2 pi k j/N) (r = N - k) and, for even
+// N, of (-1)^j / sqrt(N) (r = N/2); its eigenvalues depend on cos(2 pi r/N)
+// only.  Two real lines a, b are packed as c = a + i b of FFT length L = N.
+// With Z = FFT(c) (unnormalised) and k < N - k:
+//   a_k = (Z_k.re + Z_{N-k}.re) / sqrt(2N),      b_k = (Z_k.im + Z_{N-k}.im) / sqrt(2N),
+//   a_{N-k} = (Z_{N-k}.im - Z_k.im) / sqrt(2N),  b_{N-k} = (Z_k.re - Z_{N-k}.re) / sqrt(2N),
+// and a_r = Z_r.re / sqrt(N), b_r = Z_r.im / sqrt(N) for r = 0 and r = N/2.  The
+// inverse rebuilds the Hermitian pair spectrum Z^ (Z^_k = a^_k + i b^_k) and,
+// since c = conj(FFT(conj(Z^))) / sqrt(N), runs the same forward FFT.
+
+// Forward: Z in the line -> (a_r, b_r) at position r, in place.  Each pair
+// (k, N - k) is read and written by one thread.
+template <typename T>
+__device__ __forceinline__ void per_unpack(Cx<T>* lds, int ls, int P, int N) {
+  const int half = N / 2 + 1;  // k = 0 .. N/2
+  const T s1 = T(1.0 / sqrt(double(N)));
+  const T s2 = T(1.0 / sqrt(2.0 * double(N)));
+  for (int i = threadIdx.x; i < P * half; i += blockDim.x) {
+    const int p = i / half;
+    const int k = i - p * half;
+    Cx<T>* line = lds + p * ls;
+    const int km = N - k;
+    if (k == 0 || 2 * k == N) {
+      const Cx<T> z = line[k];
+      line[k] = Cx<T>{z.re * s1, z.im * s1};
+    } else {
+      const Cx<T> zp = line[k], zm = line[km];
+      line[k] = Cx<T>{(zp.re + zm.re) * s2, (zp.im + zm.im) * s2};
+      line[km] = Cx<T>{(zm.im - zp.im) * s2, (zp.re - zm.re) * s2};
+    }
+  }
+}
+
+// Inverse, first half: (a_r, b_r) at position r -> conj(Z^) in the line, in place.
+template <typename T>
+__device__ __forceinline__ void per_pack(Cx<T>* lds, int ls, int P, int N) {
+  const int half = N / 2 + 1;
+  const T r2 = T(1.0 / sqrt(2.0));
+  for (int i = threadIdx.x; i < P * half; i += blockDim.x) {
+    const int p = i / half;
+    const int k = i - p * half;
+    Cx<T>* line = lds + p * ls;
+    const int km = N - k;
+    if (k == 0 || 2 * k == N) {
+      const Cx<T> c = line[k];
+      line[k] = Cx<T>{c.re, -c.im};
+    } else {
+      const Cx<T> ck = line[k], cm = line[km];  // (a_k, b_k), (a_{N-k}, b_{N-k})
+      // Z^_k = ((a_k + b_{N-k}) + i (b_k - a_{N-k})) / sqrt 2,
+      // Z^_{N-k} = ((a_k - b_{N-k}) + i (b_k + a_{N-k})) / sqrt 2; stored conjugated
+      line[k] = Cx<T>{(ck.re + cm.im) * r2, (cm.re - ck.im) * r2};
+      line[km] = Cx<T>{(ck.re - cm.im) * r2, -(ck.im + cm.re) * r2};
+    }
+  }
+}
+
+// Inverse, second half: after the FFT of conj(Z^), nodal (a_j, b_j) = (X.re, -X.im) / sqrt(N).
+template <typename T>
+__device__ __forceinline__ Cx<T> per_nodal(Cx<T> X, T s1) {
+  return Cx<T>{X.re * s1, -X.im * s1};
+}
+
+// Row pass of periodic lines (x): ROW_FWD_USER, ROW_INV_USER or ROW_PHYS.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) row_pass_per(const T* src, T* dst, T* dst2, RowGeom g,
+                                                    const Cx<T>* __restrict__ tw, Forcing F) {
+  extern __shared__ unsigned char smem_raw[];
+  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem_raw);
+  const int n = g.n;  // = N, the FFT length
+  const int P = g.P;
+  const int r0 = blockIdx.x * 2 * P;
+  const T s1 = T(1.0 / sqrt(double(n)));
+  for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+    const int p = i / n;
+    const int m = i - p * n;
+    const int ra = r0 + 2 * p, rb = ra + 1;
+    const T a = ra < g.nrows ? src[ra * g.ld_src + m] : T(0);
+    const T b = rb < g.nrows ? src[rb * g.ld_src + m] : T(0);
+    lds[p * g.ls + m] = Cx<T>{a, b};
+  }
+  __syncthreads();
+  if (MODE != ROW_FWD_USER) {
+    // inverse transform to nodal values
+    per_pack(lds, g.ls, P, n);
+    __syncthreads();
+    fft_lines(lds, g.ls, P, g.pl, tw);
+    for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+      const int p = i / n;
+      const int m = i - p * n;
+      const int ra = r0 + 2 * p, rb = ra + 1;
+      const Cx<T> u = per_nodal(lds[p * g.ls + m], s1);
+      if (MODE == ROW_INV_USER) {
+        if (ra < g.nrows) dst[ra * g.ld_dst + m] = u.re;
+        if (rb < g.nrows) dst[rb * g.ld_dst + m] = u.im;
+      } else {
+        T fa = T(0), fb = T(0);
+        if (ra < g.nrows) fa = reaction<T>(F, u.re, m - 1, ra % g.ny, ra / g.ny);
+        if (rb < g.nrows) fb = reaction<T>(F, u.im, m - 1, rb % g.ny, rb / g.ny);
+        lds[p * g.ls + m] = Cx<T>{fa, fb};
+      }
+    }
+    if (MODE == ROW_INV_USER) return;
+    __syncthreads();
+  }
+  // forward transform
+  fft_lines(lds, g.ls, P, g.pl, tw);
+  per_unpack(lds, g.ls, P, n);
+  __syncthreads();
+  for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+    const int p = i / n;
+    const int m = i - p * n;
+    const int ra = r0 + 2 * p, rb = ra + 1;
+    const Cx<T> c = lds[p * g.ls + m];
+    if (ra < g.nrows) {
+      dst[ra * g.ld_dst + m] = c.re;
+      if (MODE == ROW_FWD_USER) dst2[ra * g.ld_dst + m] = c.re;
+    }
+    if (rb < g.nrows) {
+      dst[rb * g.ld_dst + m] = c.im;
+      if (MODE == ROW_FWD_USER) dst2[rb * g.ld_dst + m] = c.im;
+    }
+  }
+}
+
+// Column pass of periodic lines: COL_PLAIN (forward), COL_PLAIN_INV (inverse)
+// or a stage (forward, diagonal stage, inverse).  Tiles as col_pass.
+enum { COL_PLAIN_INV = 4 };
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) col_pass_per(T* W, T* H, ColGeom g, const Cx<T>* __restrict__ tw, Diag dg) {
+  extern __shared__ unsigned char smem_raw[];
+  Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem_raw);
+  const int n = g.n;  // = N, the FFT length
+  const int P = g.P;
+  const int c0 = blockIdx.x * 2 * P;
+  const int outer = blockIdx.y;
+  const int64_t base = int64_t(outer) * g.ld_outer + c0;
+  const T s1 = T(1.0 / sqrt(double(n)));
+  for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+    const int m = i / P;
+    const int p = i - m * P;
+    lds[p * g.ls + m] =
+        mask_pad(*reinterpret_cast<const Cx<T>*>(W + base + m * g.ld_line + 2 * p), c0 + 2 * p, g.ncols);
+  }
+  __syncthreads();
+  if (MODE == COL_PLAIN_INV) {
+    per_pack(lds, g.ls, P, n);
+    __syncthreads();
+    fft_lines(lds, g.ls, P, g.pl, tw);
+    for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+      const int m = i / P;
+      const int p = i - m * P;
+      *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) =
+          mask_pad(per_nodal(lds[p * g.ls + m], s1), c0 + 2 * p, g.ncols);
+    }
+    return;
+  }
+  fft_lines(lds, g.ls, P, g.pl, tw);
+  per_unpack(lds, g.ls, P, n);
+  __syncthreads();
+  if (MODE == COL_PLAIN) {
+    for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+      const int m = i / P;
+      const int p = i - m * P;
+      *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) = mask_pad(lds[p * g.ls + m], c0 + 2 * p, g.ncols);
+    }
+    return;
+  }
+  // diagonal stage at position m of this axis, then the inverse transform
+  const double tau = dg.tau, c2 = dg.c2, D = dg.D;
+  for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+    const int m = i / P;
+    const int p = i - m * P;
+    Cx<T>* line = lds + p * g.ls;
+    const Cx<T> gv = line[m];
+    const int ky = g.last_is_z ? outer : m;
+    const int kz = g.last_is_z ? m : 0;
+    const Sep syz = sep_combine(sep_load(dg.ax[1], ky), sep_load(dg.ax[2], kz));
+    T* hp = H + base + m * g.ld_line + 2 * p;
+    const Cx<T> hv = *reinterpret_cast<Cx<T>*>(hp);
+    const T gin[2] = {gv.re, gv.im};
+    const T hin[2] = {hv.re, hv.im};
+    T outv[2], newh[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const Sep sp = sep_combine(sep_load(dg.ax[0], c0 + 2 * p + q), syz);
+      double o, nh;
+      if (MODE == COL_ETD1)
+        diag_apply<DIAG_ETD1>(sp, D, tau, c2, double(gin[q]), double(hin[q]), &o, &nh);
+      else if (MODE == COL_STAGE_A)
+        diag_apply<DIAG_A>(sp, D, tau, c2, double(gin[q]), double(hin[q]), &o, &nh);
+      else
+        diag_apply<DIAG_B>(sp, D, tau, c2, double(gin[q]), double(hin[q]), &o, &nh);
+      outv[q] = T(o);
+      newh[q] = T(nh);
+    }
+    *reinterpret_cast<Cx<T>*>(hp) = mask_pad(Cx<T>{newh[0], newh[1]}, c0 + 2 * p, g.ncols);
+    line[m] = Cx<T>{outv[0], outv[1]};
+  }
+  __syncthreads();
+  per_pack(lds, g.ls, P, n);
+  __syncthreads();
+  fft_lines(lds, g.ls, P, g.pl, tw);
+  for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+    const int m = i / P;
+    const int p = i - m * P;
+    *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) =
+        mask_pad(per_nodal(lds[p * g.ls + m], s1), c0 + 2 * p, g.ncols);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Norm reduction: per node, (M e)_i and (K_1 e)_i by the 3^d tensor stencil of
 // the 1D matrices A = (h/6) tridiag(1,4,1), B = (1/h) tridiag(-1,2,-1)
 // (Section 4, eq. (4.1)), accumulated in double.
 struct NormGeom {
   int d;
   int n[3];
+  int per[3];  // periodic axis: the stencil wraps around
   double ad[3], ao[3];  // A diagonal / off-diagonal
   double bd[3], bo[3];  // B diagonal / off-diagonal
   double cellvol;
@@ -562,17 +792,20 @@ __global__ void __launch_bounds__(kNormThreads) norm_partial(const T* __restrict
     const int iz = int(i / sz);
     double Me = 0.0, Ke = 0.0, Ku = 0.0;
     for (int oz = -1; oz <= 1; ++oz) {
-      const int jz = iz + oz;
+      int jz = iz + oz;
+      if (g.per[2]) jz = (jz + g.n[2]) % g.n[2];
       if (jz < 0 || jz >= g.n[2]) continue;
       const double az = oz ? g.ao[2] : g.ad[2];
       const double bz = oz ? g.bo[2] : g.bd[2];
       for (int oy = -1; oy <= 1; ++oy) {
-        const int jy = iy + oy;
+        int jy = iy + oy;
+        if (g.per[1]) jy = (jy + g.n[1]) % g.n[1];
         if (jy < 0 || jy >= g.n[1]) continue;
         const double ay = oy ? g.ao[1] : g.ad[1];
         const double by = oy ? g.bo[1] : g.bd[1];
         for (int ox = -1; ox <= 1; ++ox) {
-          const int jx = ix + ox;
+          int jx = ix + ox;
+          if (g.per[0]) jx = (jx + g.n[0]) % g.n[0];
           if (jx < 0 || jx >= g.n[0]) continue;
           const double axv = ox ? g.ao[0] : g.ad[0];
           const double bxv = ox ? g.bo[0] : g.bd[0];

@@ -53,7 +53,8 @@ def test_version_and_error_string_without_gpu(libpath):
     h = (ctypes.c_double * 2)(0.1, 0.1)
     assert lib.eife_create_grid(4, N, h, ctypes.c_double(1.0), 0, 1, ctypes.byref(out)) == -1
     assert b"d must be" in lib.eife_last_error()
-    assert lib.eife_create_grid(2, N, h, ctypes.c_double(1.0), 1, 1, ctypes.byref(out)) == -3
+    assert lib.eife_create_grid(2, N, h, ctypes.c_double(1.0), 7, 1, ctypes.byref(out)) == -1  # unknown bc
+    assert b"boundary condition" in lib.eife_last_error()
     assert lib.eife_step(None, None, 1, 1, ctypes.c_double(0.0), None) == -1
 
 

@@ -225,7 +225,10 @@ def test_abi_errors():
         eife.Grid([8, 8], [0.1, -0.1], 1.0)
     assert e.value.code == -1
     with pytest.raises(eife.EIFEError) as e:
-        eife.Grid([8, 8], [0.1, 0.1], 1.0, bc=1)
+        eife.Grid([8, 8], [0.1, 0.1], 1.0, bc=7)  # no such boundary condition
+    assert e.value.code == -1
+    with pytest.raises(eife.EIFEError) as e:
+        eife.Grid([10, 8], [0.1, 0.1], 1.0, bc=eife.BC_PERIODIC)  # periodic N = 10 has a factor 5
     assert e.value.code == -3
     g = eife.Grid([8, 8], [0.1, 0.1], 1.0)
     u = torch.zeros(7, 7, dtype=torch.float64, device="cuda")

@@ -1,0 +1,152 @@
+"""GPU parity for periodic grids (the variant at the end of Section 4) and the
+Flory-Huggins reaction of Example 5.3, against the FP64 oracle.
+
+The oracle's periodic basis (real Fourier transform with closed-form
+eigenvalues, tier C) is pinned to the dense and Kronecker tiers and to the
+assembled circulant matrices by the CPU tests.  Tolerances as everywhere:
+relative max-norm 1e-12 (FP64), 1e-5 (FP32).
+"""
+import numpy as np
+import pytest
+
+import seeded_inputs
+from oracle import fem, norms, problems, spectral, stepper
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+THETA, THETA_C = 0.8, 1.6
+
+
+def _eife():
+    import paper_2209_11922_amd as eife
+    return eife
+
+
+def _rel(got, ref):
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def _gpu(N, D, u0, tau, steps, stages, fkind, dtype, load=0, forcing=None):
+    eife = _eife()
+    g = eife.Grid(N, [1.0 / n for n in N], D, dtype, bc=eife.BC_PERIODIC)
+    g.set_load(load)
+    if forcing is not None:
+        g.set_forcing(*forcing)
+    g.set_phi(tau, stages)
+    u = torch.tensor(np.ascontiguousarray(u0), dtype=g.torch_dtype, device="cuda")
+    g.step(u, steps, fkind)
+    torch.cuda.synchronize()
+    out = u.double().cpu().numpy()
+    g.close()
+    return out
+
+
+def _oracle(N, D, u0, f, tau, steps, stages, load="lumped", tier="C"):
+    b = spectral.make_basis(tier, N, [1.0 / n for n in N], D, bc="periodic")
+    return stepper.run(b, u0, f, tau, steps, stages, load=load)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("stages", [2, 1])
+@pytest.mark.parametrize("N", [[64], [64, 48], [27, 9], [16, 12, 18], [8, 32, 6]],
+                         ids=["1d", "2d-mixed-radix", "2d-odd", "3d", "3d-ragged"])
+def test_periodic_allen_cahn_matches_oracle(N, stages, dtype):
+    eife = _eife()
+    u0 = seeded_inputs.uniform_field(31, [n + 1 for n in N])  # N^d nodes (one more interval per axis)
+    u0 = np.asarray(u0).reshape(tuple(reversed(N)))
+    got = _gpu(N, 2.5e-3, u0, 0.02, 8, stages, eife.F_ALLEN_CAHN, dtype)
+    ref = _oracle(N, 2.5e-3, u0, problems.allen_cahn(), 0.02, 8, stages)
+    err = _rel(got, ref)
+    print(f"periodic {N} EIFE{stages} {dtype}: {err:.2e}")
+    assert err <= TOL[dtype]
+
+
+def test_periodic_nodal_load_matches_oracle():
+    eife = _eife()
+    N = [24, 16]
+    u0 = np.random.default_rng(5).uniform(-0.9, 0.9, (16, 24))
+    got = _gpu(N, 1e-2, u0, 0.05, 6, 2, eife.F_ALLEN_CAHN, "f64", load=eife.LOAD_NODAL)
+    ref = _oracle(N, 1e-2, u0, problems.allen_cahn(), 0.05, 6, 2, load="nodal", tier="B")
+    assert _rel(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_flory_huggins_matches_oracle(dtype):
+    """Example 5.3's reaction and parameters (eps = 0.01, tau = 5/512) on a 2D periodic grid."""
+    eife = _eife()
+    N = [32, 48]
+    u0 = np.random.default_rng(7).uniform(-0.9, 0.9, (48, 32))
+    got = _gpu(N, 1e-4, u0, 5 / 512, 20, 2, eife.F_FLORY_HUGGINS, dtype, forcing=(THETA, THETA_C))
+    ref = _oracle(N, 1e-4, u0, problems.flory_huggins(THETA, THETA_C), 5 / 512, 20, 2)
+    assert _rel(got, ref) <= TOL[dtype]
+
+
+def test_constant_forcing_raises_the_mean_exactly():
+    """The constant is the zero mode (lambda = 0): the mean grows by exactly c tau per step."""
+    eife = _eife()
+    N, tau, c, steps = [16, 16, 8], 0.1, 0.3, 5
+    u0 = np.random.default_rng(2).uniform(-1, 1, (8, 16, 16))
+    got = _gpu(N, 0.05, u0, tau, steps, 2, eife.F_CONST, "f64", forcing=(c, 0.0))
+    assert abs((got.mean() - u0.mean()) - c * tau * steps) < 1e-13
+    ref = _oracle(N, 0.05, u0, problems.constant(c), tau, steps, 2)
+    assert _rel(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("N", [[48, 36], [6, 12, 8]])
+def test_periodic_norms_match_oracle(N):
+    eife = _eife()
+    h = [1.0 / n for n in N]
+    rng = np.random.default_rng(11)
+    shape = tuple(reversed(N))
+    u, r = rng.standard_normal(shape), rng.standard_normal(shape)
+    g = eife.Grid(N, h, 0.3, "f64", bc=eife.BC_PERIODIC)
+    l2, h1, mx, _ = g.norms(torch.tensor(u, device="cuda"), torch.tensor(r, device="cuda"))
+    g.close()
+    rl2, rh1, rmx = norms.discrete_norms(N, h, u - r, bc="periodic")
+    assert abs(l2 - rl2) <= 1e-12 * rl2 and abs(h1 - rh1) <= 1e-12 * rh1 and mx == rmx
+
+
+def test_periodic_unsupported_combinations():
+    eife = _eife()
+    g = eife.Grid([32, 32], [1 / 32, 1 / 32], 1e-3, "f32", bc=eife.BC_PERIODIC)
+    with pytest.raises(eife.EIFEError) as e:
+        g.set_transform(eife.binding.TX_GEMM_SPLITBF16)
+    assert e.value.code == -3
+    g.set_phi(0.01, 2)
+    u = torch.zeros(32 * 32, dtype=torch.float32, device="cuda")
+    with pytest.raises(eife.EIFEError) as e:
+        g.step(u, 1, eife.F_MMS_U2)
+    assert e.value.code == -3
+    assert g.size() == 32 * 32
+    g.close()
+
+
+def test_example_53_maximum_bound_and_energy_decay_3d():
+    """Example 5.3 on a 3D periodic grid (64^3 here; the bench runs the paper's 128^3 to T = 20):
+    EIFE2 with eps = 0.01, theta = 0.8, theta_c = 1.6, tau = 5/512 keeps max|u| within
+    gamma = 0.9575 and the discrete energy decreases between checkpoints."""
+    eife = _eife()
+    n, steps, every = 64, 400, 40
+    N = [n, n, n]
+    h = [1.0 / n] * 3
+    gamma = problems.flory_huggins_bound(THETA, THETA_C)
+    g = eife.Grid(N, h, 1e-4, "f64", bc=eife.BC_PERIODIC)
+    g.set_forcing(THETA, THETA_C)
+    g.set_phi(5 / 512, 2)
+    u0 = np.random.default_rng(53).uniform(-0.9, 0.9, (n, n, n))
+    u = torch.tensor(u0, device="cuda")
+    energies, maxima = [], []
+    for k in range(steps // every):
+        g.step(u, every, eife.F_FLORY_HUGGINS, k * every * 5 / 512)
+        torch.cuda.synchronize()
+        U = u.cpu().numpy()
+        maxima.append(float(np.abs(U).max()))
+        energies.append(norms.flory_huggins_energy(N, h, 1e-4, U, THETA, THETA_C))
+    g.close()
+    print("max|u|", maxima[-1], "energies", energies[0], energies[-1])
+    assert max(maxima) <= gamma
+    assert np.all(np.diff(energies) < 0)
+    assert maxima[-1] > 0.95  # separated towards +-gamma
