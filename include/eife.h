@@ -157,6 +157,19 @@ int eife_step(eife_grid g, void* u, int64_t n_steps, int f_kind, double t0, void
  * finite. */
 int eife_norms(eife_grid g, const void* u, const void* uref, double* out, void* stream);
 
+/* Discrete energy of the nodal values u (device array in the grid's layout
+ * and dtype) for the reaction f_kind, f = -F'(u):
+ *   out[0] = (D/2) u^T K_1 u + prod(h) sum_i F(u_i)
+ * with F(u) = (u^2 - 1)^2 / 4 for EIFE_F_ALLEN_CAHN and, for
+ * EIFE_F_FLORY_HUGGINS (Example 5.3, Section 5.2),
+ *   F(u) = (theta/2)((1 + u) ln(1 + u) + (1 - u) ln(1 - u)) - (theta_c/2) u^2
+ * with theta = c0, theta_c = c1 of eife_set_forcing.  The gradient term uses
+ * the Q1 stiffness matrix, the potential nodal quadrature.  Accumulated in
+ * double; blocks the host until `stream` has produced it (host out[1]).
+ * Errors: EIFE_EINVAL (null pointers, any other f_kind), EIFE_ENONFINITE
+ * (value still written; e.g. some |u_i| >= 1 for Flory-Huggins). */
+int eife_energy(eife_grid g, const void* u, int f_kind, double* out, void* stream);
+
 /* Pass kinds of eife_step, for per-pass timing. */
 enum eife_pass {
   EIFE_PASS_ROW_PHYS = 0,   /* inverse x-transform -> f -> forward x-transform */

@@ -52,6 +52,7 @@ def load_library():
     lib.eife_set_transform.argtypes = [c_void_p, c_int]
     lib.eife_step.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_int, c_double, c_void_p]
     lib.eife_norms.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]
+    lib.eife_energy.argtypes = [c_void_p, c_void_p, c_int, ctypes.POINTER(c_double), c_void_p]
     lib.eife_grid_size.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_int64)]
     lib.eife_profile.argtypes = [c_void_p, c_int]
     lib.eife_profile_read.argtypes = [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -89,7 +90,7 @@ def load_library():
     lib.eife_last_error.argtypes = []
     lib.eife_version.argtypes = []
     for name in ("eife_create_grid", "eife_destroy_grid", "eife_set_phi", "eife_set_c2", "eife_set_origin",
-                 "eife_set_load", "eife_set_forcing", "eife_step", "eife_norms", "eife_grid_size",
+                 "eife_set_load", "eife_set_forcing", "eife_step", "eife_norms", "eife_energy", "eife_grid_size",
                  "eife_version", "eife_profile", "eife_profile_read", "eife_set_transform", "eife_create_batch",
                  "eife_destroy_batch", "eife_batch_offsets", "eife_batch_set_phi", "eife_batch_step",
                  "eife_batch_autotune", "eife_batch_class_info"):
@@ -203,6 +204,15 @@ class Grid:
         code = self._lib.eife_norms(self._g, ctypes.c_void_p(u.data_ptr()), ref, out, _stream_ptr(stream))
         _check(self._lib, code)
         return tuple(out)
+
+    def energy(self, u, f_kind, stream=None):
+        """Discrete energy (D/2) u^T K_1 u + prod(h) sum F(u_i) of the reaction f_kind, in double."""
+        self._check_array(u, "u")
+        out = ctypes.c_double()
+        code = self._lib.eife_energy(self._g, ctypes.c_void_p(u.data_ptr()), int(f_kind), ctypes.byref(out),
+                                     _stream_ptr(stream))
+        _check(self._lib, code)
+        return out.value
 
 
 class Batch:

@@ -853,10 +853,13 @@ int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipS
   return EIFE_OK;
 }
 
-NormGeom make_norm_geom(const eife_grid_s* g) {
+NormGeom make_norm_geom(const eife_grid_s* g, int pot = NORM_POT_DOUBLE_WELL) {
   NormGeom ng;
   ng.d = g->d;
   ng.cellvol = 1.0;
+  ng.pot = pot;
+  ng.th = g->c0;
+  ng.thc = g->c1;
   for (int a = 0; a < 3; ++a) {
     ng.n[a] = g->n[a];
     ng.per[a] = g->per[a] ? 1 : 0;
@@ -878,8 +881,8 @@ NormGeom make_norm_geom(const eife_grid_s* g) {
 }
 
 template <typename T>
-int run_norms(eife_grid_s* g, const void* u, const void* uref, hipStream_t s) {
-  const NormGeom ng = make_norm_geom(g);
+int run_norms(eife_grid_s* g, const void* u, const void* uref, hipStream_t s, int pot = NORM_POT_DOUBLE_WELL) {
+  const NormGeom ng = make_norm_geom(g, pot);
   const int64_t total = int64_t(g->n[0]) * g->n[1] * g->n[2];
   int nb = int(std::min<int64_t>(kNormBlocksMax, (total + kNormThreads - 1) / kNormThreads));
   nb = std::max(nb, 1);
@@ -1174,6 +1177,27 @@ int eife_norms(eife_grid g, const void* u, const void* uref, double* out, void* 
   out[3] = 0.5 * g->D * r[3] + cellvol * r[4];
   for (int k = 0; k < 4; ++k)
     if (!std::isfinite(out[k])) return fail(EIFE_ENONFINITE, "norm %d is not finite", k);
+  return EIFE_OK;
+}
+
+int eife_energy(eife_grid g, const void* u, int f_kind, double* out, void* stream) {
+  RET_IF(check_grid(g));
+  if (!u || !out) return fail(EIFE_EINVAL, "u and out must not be null");
+  int pot;
+  if (f_kind == EIFE_F_ALLEN_CAHN)
+    pot = NORM_POT_DOUBLE_WELL;
+  else if (f_kind == EIFE_F_FLORY_HUGGINS)
+    pot = NORM_POT_FH;
+  else
+    return fail(EIFE_EINVAL, "f_kind %d has no energy (Allen-Cahn or Flory-Huggins only)", f_kind);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RET_IF(g->dtype == EIFE_F32 ? run_norms<float>(g, u, nullptr, s, pot) : run_norms<double>(g, u, nullptr, s, pot));
+  HIP_TRY(hipMemcpyAsync(g->host5, g->out5, kNormAcc * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double cellvol = 1.0;
+  for (int a = 0; a < g->d; ++a) cellvol *= g->h[a];
+  out[0] = 0.5 * g->D * g->host5[3] + cellvol * g->host5[4];
+  if (!std::isfinite(out[0])) return fail(EIFE_ENONFINITE, "energy is not finite");
   return EIFE_OK;
 }
 

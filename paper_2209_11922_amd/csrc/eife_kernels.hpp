@@ -352,8 +352,8 @@ __global__ void __launch_bounds__(256) row_pass(const T* src, T* dst, T* dst2, R
     const int m = i - p * n;
     const int ra = r0 + 2 * p, rb = ra + 1;
     T a = T(0), b = T(0);
-    if (ra < g.nrows) a = src[ra * g.ld_src + m];
-    if (rb < g.nrows) b = src[rb * g.ld_src + m];
+    if (ra < g.nrows) a = src[int64_t(ra) * g.ld_src + m];
+    if (rb < g.nrows) b = src[int64_t(rb) * g.ld_src + m];
     put_odd(lds + p * g.ls, L, m + 1, a, b);
   }
   __syncthreads();
@@ -365,8 +365,8 @@ __global__ void __launch_bounds__(256) row_pass(const T* src, T* dst, T* dst2, R
       const int m = i - p * n;
       const int ra = r0 + 2 * p, rb = ra + 1;
       const Cx<T> Z = lds[p * g.ls + m + 1];
-      if (ra < g.nrows) dst[ra * g.ld_dst + m] = -Z.im * scale;
-      if (rb < g.nrows) dst[rb * g.ld_dst + m] = Z.re * scale;
+      if (ra < g.nrows) dst[int64_t(ra) * g.ld_dst + m] = -Z.im * scale;
+      if (rb < g.nrows) dst[int64_t(rb) * g.ld_dst + m] = Z.re * scale;
     }
     return;
   }
@@ -378,12 +378,12 @@ __global__ void __launch_bounds__(256) row_pass(const T* src, T* dst, T* dst2, R
       const Cx<T> Z = lds[p * g.ls + m + 1];
       const T va = -Z.im * scale, vb = Z.re * scale;
       if (ra < g.nrows) {
-        dst[ra * g.ld_dst + m] = va;
-        dst2[ra * g.ld_dst + m] = va;
+        dst[int64_t(ra) * g.ld_dst + m] = va;
+        dst2[int64_t(ra) * g.ld_dst + m] = va;
       }
       if (rb < g.nrows) {
-        dst[rb * g.ld_dst + m] = vb;
-        dst2[rb * g.ld_dst + m] = vb;
+        dst[int64_t(rb) * g.ld_dst + m] = vb;
+        dst2[int64_t(rb) * g.ld_dst + m] = vb;
       }
     }
     return;
@@ -412,8 +412,8 @@ __global__ void __launch_bounds__(256) row_pass(const T* src, T* dst, T* dst2, R
     const int m = i - p * n;
     const int ra = r0 + 2 * p, rb = ra + 1;
     const Cx<T> Z = lds[p * g.ls + m + 1];
-    if (ra < g.nrows) dst[ra * g.ld_dst + m] = -Z.im * scale;
-    if (rb < g.nrows) dst[rb * g.ld_dst + m] = Z.re * scale;
+    if (ra < g.nrows) dst[int64_t(ra) * g.ld_dst + m] = -Z.im * scale;
+    if (rb < g.nrows) dst[int64_t(rb) * g.ld_dst + m] = Z.re * scale;
   }
 }
 
@@ -475,7 +475,7 @@ __global__ void __launch_bounds__(256) col_pass(T* W, T* H, ColGeom g, const Cx<
   for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
     const int m = i / P;
     const int p = i - m * P;
-    const Cx<T> v = mask_pad(*reinterpret_cast<const Cx<T>*>(W + base + m * g.ld_line + 2 * p), c0 + 2 * p, g.ncols);
+    const Cx<T> v = mask_pad(*reinterpret_cast<const Cx<T>*>(W + base + int64_t(m) * g.ld_line + 2 * p), c0 + 2 * p, g.ncols);
     put_odd(lds + p * g.ls, L, m + 1, v.re, v.im);
   }
   __syncthreads();
@@ -486,7 +486,7 @@ __global__ void __launch_bounds__(256) col_pass(T* W, T* H, ColGeom g, const Cx<
       const int m = i / P;
       const int p = i - m * P;
       const Cx<T> Z = lds[p * g.ls + m + 1];
-      *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) =
+      *reinterpret_cast<Cx<T>*>(W + base + int64_t(m) * g.ld_line + 2 * p) =
           mask_pad(Cx<T>{-Z.im * scale, Z.re * scale}, c0 + 2 * p, g.ncols);
     }
     return;
@@ -503,7 +503,7 @@ __global__ void __launch_bounds__(256) col_pass(T* W, T* H, ColGeom g, const Cx<
     const int ky = g.last_is_z ? outer : m;
     const int kz = g.last_is_z ? m : 0;
     const Sep syz = sep_combine(sep_load(dg.ax[1], ky), sep_load(dg.ax[2], kz));
-    T* hp = H + base + m * g.ld_line + 2 * p;
+    T* hp = H + base + int64_t(m) * g.ld_line + 2 * p;
     Cx<T> hv = *reinterpret_cast<Cx<T>*>(hp);
     T outv[2];
     T newh[2];
@@ -535,7 +535,7 @@ __global__ void __launch_bounds__(256) col_pass(T* W, T* H, ColGeom g, const Cx<
     const int m = i / P;
     const int p = i - m * P;
     const Cx<T> Z = lds[p * g.ls + m + 1];
-    *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) =
+    *reinterpret_cast<Cx<T>*>(W + base + int64_t(m) * g.ld_line + 2 * p) =
         mask_pad(Cx<T>{-Z.im * scale, Z.re * scale}, c0 + 2 * p, g.ncols);
   }
 }
@@ -620,8 +620,8 @@ __global__ void __launch_bounds__(256) row_pass_per(const T* src, T* dst, T* dst
     const int p = i / n;
     const int m = i - p * n;
     const int ra = r0 + 2 * p, rb = ra + 1;
-    const T a = ra < g.nrows ? src[ra * g.ld_src + m] : T(0);
-    const T b = rb < g.nrows ? src[rb * g.ld_src + m] : T(0);
+    const T a = ra < g.nrows ? src[int64_t(ra) * g.ld_src + m] : T(0);
+    const T b = rb < g.nrows ? src[int64_t(rb) * g.ld_src + m] : T(0);
     lds[p * g.ls + m] = Cx<T>{a, b};
   }
   __syncthreads();
@@ -636,8 +636,8 @@ __global__ void __launch_bounds__(256) row_pass_per(const T* src, T* dst, T* dst
       const int ra = r0 + 2 * p, rb = ra + 1;
       const Cx<T> u = per_nodal(lds[p * g.ls + m], s1);
       if (MODE == ROW_INV_USER) {
-        if (ra < g.nrows) dst[ra * g.ld_dst + m] = u.re;
-        if (rb < g.nrows) dst[rb * g.ld_dst + m] = u.im;
+        if (ra < g.nrows) dst[int64_t(ra) * g.ld_dst + m] = u.re;
+        if (rb < g.nrows) dst[int64_t(rb) * g.ld_dst + m] = u.im;
       } else {
         T fa = T(0), fb = T(0);
         if (ra < g.nrows) fa = reaction<T>(F, u.re, m - 1, ra % g.ny, ra / g.ny);
@@ -658,12 +658,12 @@ __global__ void __launch_bounds__(256) row_pass_per(const T* src, T* dst, T* dst
     const int ra = r0 + 2 * p, rb = ra + 1;
     const Cx<T> c = lds[p * g.ls + m];
     if (ra < g.nrows) {
-      dst[ra * g.ld_dst + m] = c.re;
-      if (MODE == ROW_FWD_USER) dst2[ra * g.ld_dst + m] = c.re;
+      dst[int64_t(ra) * g.ld_dst + m] = c.re;
+      if (MODE == ROW_FWD_USER) dst2[int64_t(ra) * g.ld_dst + m] = c.re;
     }
     if (rb < g.nrows) {
-      dst[rb * g.ld_dst + m] = c.im;
-      if (MODE == ROW_FWD_USER) dst2[rb * g.ld_dst + m] = c.im;
+      dst[int64_t(rb) * g.ld_dst + m] = c.im;
+      if (MODE == ROW_FWD_USER) dst2[int64_t(rb) * g.ld_dst + m] = c.im;
     }
   }
 }
@@ -686,7 +686,7 @@ __global__ void __launch_bounds__(256) col_pass_per(T* W, T* H, ColGeom g, const
     const int m = i / P;
     const int p = i - m * P;
     lds[p * g.ls + m] =
-        mask_pad(*reinterpret_cast<const Cx<T>*>(W + base + m * g.ld_line + 2 * p), c0 + 2 * p, g.ncols);
+        mask_pad(*reinterpret_cast<const Cx<T>*>(W + base + int64_t(m) * g.ld_line + 2 * p), c0 + 2 * p, g.ncols);
   }
   __syncthreads();
   if (MODE == COL_PLAIN_INV) {
@@ -696,7 +696,7 @@ __global__ void __launch_bounds__(256) col_pass_per(T* W, T* H, ColGeom g, const
     for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
       const int m = i / P;
       const int p = i - m * P;
-      *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) =
+      *reinterpret_cast<Cx<T>*>(W + base + int64_t(m) * g.ld_line + 2 * p) =
           mask_pad(per_nodal(lds[p * g.ls + m], s1), c0 + 2 * p, g.ncols);
     }
     return;
@@ -708,7 +708,7 @@ __global__ void __launch_bounds__(256) col_pass_per(T* W, T* H, ColGeom g, const
     for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
       const int m = i / P;
       const int p = i - m * P;
-      *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) = mask_pad(lds[p * g.ls + m], c0 + 2 * p, g.ncols);
+      *reinterpret_cast<Cx<T>*>(W + base + int64_t(m) * g.ld_line + 2 * p) = mask_pad(lds[p * g.ls + m], c0 + 2 * p, g.ncols);
     }
     return;
   }
@@ -722,7 +722,7 @@ __global__ void __launch_bounds__(256) col_pass_per(T* W, T* H, ColGeom g, const
     const int ky = g.last_is_z ? outer : m;
     const int kz = g.last_is_z ? m : 0;
     const Sep syz = sep_combine(sep_load(dg.ax[1], ky), sep_load(dg.ax[2], kz));
-    T* hp = H + base + m * g.ld_line + 2 * p;
+    T* hp = H + base + int64_t(m) * g.ld_line + 2 * p;
     const Cx<T> hv = *reinterpret_cast<Cx<T>*>(hp);
     const T gin[2] = {gv.re, gv.im};
     const T hin[2] = {hv.re, hv.im};
@@ -750,7 +750,7 @@ __global__ void __launch_bounds__(256) col_pass_per(T* W, T* H, ColGeom g, const
   for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
     const int m = i / P;
     const int p = i - m * P;
-    *reinterpret_cast<Cx<T>*>(W + base + m * g.ld_line + 2 * p) =
+    *reinterpret_cast<Cx<T>*>(W + base + int64_t(m) * g.ld_line + 2 * p) =
         mask_pad(per_nodal(lds[p * g.ls + m], s1), c0 + 2 * p, g.ncols);
   }
 }
@@ -766,10 +766,14 @@ struct NormGeom {
   double ad[3], ao[3];  // A diagonal / off-diagonal
   double bd[3], bo[3];  // B diagonal / off-diagonal
   double cellvol;
+  int pot;           // potential summed in accumulator 4: NORM_POT_DOUBLE_WELL or NORM_POT_FH
+  double th, thc;    // Flory-Huggins theta, theta_c
 };
 
+enum { NORM_POT_DOUBLE_WELL = 0, NORM_POT_FH = 1 };
+
 constexpr int kNormThreads = 256;
-constexpr int kNormAcc = 5;  // eMe, eK1e, max|e|, uK1u, sum (u^2-1)^2/4
+constexpr int kNormAcc = 5;  // eMe, eK1e, max|e|, uK1u, sum F(u_i)
 
 template <typename T>
 __device__ __forceinline__ double ld_err(const T* u, const T* ur, int64_t i) {
@@ -826,8 +830,13 @@ __global__ void __launch_bounds__(kNormThreads) norm_partial(const T* __restrict
     acc[1] += ei * Ke;
     acc[2] = fmax(acc[2], fabs(ei));
     acc[3] += ui * Ku;
-    const double q = ui * ui - 1.0;
-    acc[4] += 0.25 * q * q;
+    if (g.pot == NORM_POT_FH) {
+      // F(u) = (theta/2)((1+u) ln(1+u) + (1-u) ln(1-u)) - (theta_c/2) u^2 (Example 5.3)
+      acc[4] += 0.5 * g.th * ((1.0 + ui) * log1p(ui) + (1.0 - ui) * log1p(-ui)) - 0.5 * g.thc * ui * ui;
+    } else {
+      const double q = ui * ui - 1.0;
+      acc[4] += 0.25 * q * q;
+    }
   }
 #pragma unroll
   for (int k = 0; k < kNormAcc; ++k) red[k][threadIdx.x] = acc[k];

@@ -109,6 +109,42 @@ def test_periodic_norms_match_oracle(N):
     assert abs(l2 - rl2) <= 1e-12 * rl2 and abs(h1 - rh1) <= 1e-12 * rh1 and mx == rmx
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", [[48, 36], [6, 12, 8]])
+def test_flory_huggins_energy_matches_oracle(N, dtype):
+    eife = _eife()
+    h = [1.0 / n for n in N]
+    u = np.random.default_rng(13).uniform(-0.95, 0.95, tuple(reversed(N)))
+    g = eife.Grid(N, h, 1e-4, dtype, bc=eife.BC_PERIODIC)
+    g.set_forcing(THETA, THETA_C)
+    ut = torch.tensor(u, dtype=g.torch_dtype, device="cuda")
+    got = g.energy(ut, eife.F_FLORY_HUGGINS)
+    ref = norms.flory_huggins_energy(N, h, 1e-4, ut.double().cpu().numpy(), THETA, THETA_C)
+    assert abs(got - ref) <= 1e-12 * abs(ref)
+    # the double-well energy agrees with the fourth output of the norms
+    assert g.energy(ut, eife.F_ALLEN_CAHN) == pytest.approx(g.norms(ut)[3], rel=1e-14)
+    with pytest.raises(eife.EIFEError) as e:
+        g.energy(ut, eife.F_CONST)
+    assert e.value.code == -1
+    with pytest.raises(eife.EIFEError) as e:  # outside (-1, 1) the logarithms are not finite
+        g.energy(torch.ones_like(ut), eife.F_FLORY_HUGGINS)
+    assert e.value.code == -6
+    g.close()
+
+
+def test_flory_huggins_energy_dirichlet_grid():
+    eife = _eife()
+    N = [16, 12]
+    h = [1.0 / n for n in N]
+    u = np.random.default_rng(17).uniform(-0.9, 0.9, (11, 15))
+    g = eife.Grid(N, h, 2e-3, "f64")
+    g.set_forcing(THETA, THETA_C)
+    got = g.energy(torch.tensor(u, device="cuda"), eife.F_FLORY_HUGGINS)
+    ref = norms.flory_huggins_energy(N, h, 2e-3, u, THETA, THETA_C, bc="dirichlet")
+    g.close()
+    assert abs(got - ref) <= 1e-12 * abs(ref)
+
+
 def test_periodic_unsupported_combinations():
     eife = _eife()
     g = eife.Grid([32, 32], [1 / 32, 1 / 32], 1e-3, "f32", bc=eife.BC_PERIODIC)
@@ -142,9 +178,11 @@ def test_example_53_maximum_bound_and_energy_decay_3d():
     for k in range(steps // every):
         g.step(u, every, eife.F_FLORY_HUGGINS, k * every * 5 / 512)
         torch.cuda.synchronize()
-        U = u.cpu().numpy()
-        maxima.append(float(np.abs(U).max()))
-        energies.append(norms.flory_huggins_energy(N, h, 1e-4, U, THETA, THETA_C))
+        maxima.append(g.norms(u)[2])
+        energies.append(g.energy(u, eife.F_FLORY_HUGGINS))
+    U = u.cpu().numpy()
+    assert maxima[-1] == float(np.abs(U).max())
+    assert abs(energies[-1] - norms.flory_huggins_energy(N, h, 1e-4, U, THETA, THETA_C)) <= 1e-12 * abs(energies[-1])
     g.close()
     print("max|u|", maxima[-1], "energies", energies[0], energies[-1])
     assert max(maxima) <= gamma
