@@ -61,6 +61,70 @@ def assemble_1d(N, h, bc="dirichlet"):
     return full_m[1:N, 1:N].copy(), full_k[1:N, 1:N].copy()
 
 
+def assemble_1d_all_nodes(N, h):
+    """1D mass and stiffness matrices over all N + 1 nodes of the uniform
+    partition (no node removed), summed from the element matrices."""
+    me, ke = p1_element_matrices(h)
+    m = np.zeros((N + 1, N + 1))
+    k = np.zeros((N + 1, N + 1))
+    for e in range(N):
+        idx = [e, e + 1]
+        for a in range(2):
+            for b in range(2):
+                m[idx[a], idx[b]] += me[a, b]
+                k[idx[a], idx[b]] += ke[a, b]
+    return m, k
+
+
+def boundary_nodes(N):
+    """Boolean mask over all nodes (shape (N_{d-1}+1, ..., N_0+1), x fastest) that
+    marks the Dirichlet boundary nodes (some index equal to 0 or N_a)."""
+    d = len(N)
+    mask = np.zeros(tuple(N[a] + 1 for a in reversed(range(d))), dtype=bool)
+    for a in range(d):
+        sl = [slice(None)] * d
+        sl[d - 1 - a] = 0
+        mask[tuple(sl)] = True
+        sl[d - 1 - a] = N[a]
+        mask[tuple(sl)] = True
+    return mask
+
+
+def boundary_coupling(N, h, D, origin=None):
+    """Interior-row, boundary-column blocks Mb, Kb of the all-node Q1 mass and
+    stiffness matrices, and the coordinates of the boundary nodes.
+
+    Nonhomogeneous Dirichlet data g(t) (the extension noted at the start of
+    Section 4): writing u_h = sum_interior u_i phi_i + sum_boundary g_j(t) phi_j
+    and testing eq. (2.3) with the interior hat functions gives
+        M u' + K u = F - Mb g'(t) - Kb g(t),
+    so the boundary values enter as one more forcing term.  The all-node
+    matrices are Kronecker products of assemble_1d_all_nodes (x fastest);
+    rows are the interior nodes in the package layout, columns the boundary
+    nodes in the flat order of boundary_nodes(N).  Returns (Mb, Kb, Xb) with
+    Xb a list of 1-D coordinate arrays, one per axis, of the boundary nodes.
+    """
+    d = len(N)
+    origin = [0.0] * d if origin is None else list(origin)
+    ones = [assemble_1d_all_nodes(N[a], h[a]) for a in range(d)]
+    A = [ones[a][0] for a in range(d)]
+    B = [ones[a][1] for a in range(d)]
+    Mf = _kron_list([A[a] for a in reversed(range(d))])
+    Kf = None
+    for ax in range(d):
+        term = _kron_list([B[a] if a == ax else A[a] for a in reversed(range(d))])
+        Kf = term if Kf is None else Kf + term
+    Kf = D * Kf
+    bmask = boundary_nodes(N).reshape(-1)
+    rows = np.flatnonzero(~bmask)
+    cols = np.flatnonzero(bmask)
+    Mb = Mf.tocsr()[rows][:, cols].tocsr()
+    Kb = Kf.tocsr()[rows][:, cols].tocsr()
+    full = np.meshgrid(*[origin[a] + h[a] * np.arange(N[a] + 1) for a in reversed(range(d))], indexing="ij")
+    Xb = [full[d - 1 - a].reshape(-1)[cols] for a in range(d)]
+    return Mb, Kb, Xb
+
+
 def n_unknowns(N, bc="dirichlet"):
     """Unknowns per axis: N - 1 (Dirichlet) or N (periodic)."""
     return N if bc == "periodic" else N - 1
@@ -94,7 +158,7 @@ def mass_stiffness(N, h, D, bc="dirichlet"):
     return M, (D * K).tocsr()
 
 
-def q1_quadrature_assembly(N, h, D, origin=None, bc="dirichlet"):
+def q1_quadrature_assembly(N, h, D, origin=None, bc="dirichlet", all_nodes=False):
     """Mass and stiffness by Gauss quadrature over each Q1 element (dense).
 
     Independent of the Kronecker formula: for every box element, the 2^d
@@ -102,11 +166,12 @@ def q1_quadrature_assembly(N, h, D, origin=None, bc="dirichlet"):
     2-point-per-axis Gauss points (exact for these polynomial integrands),
     giving (phi_i, phi_j) and a(phi_i, phi_j) = int D grad phi_i . grad phi_j
     (eq. (2.3)), which are summed into the interior-node numbering.
-    Only meant for tiny grids.
+    With all_nodes=True no node is dropped: the numbering runs over all
+    prod(N_a + 1) nodes (x fastest).  Only meant for tiny grids.
     """
     d = len(N)
     periodic = bc == "periodic"
-    n = [n_unknowns(N[a], bc) for a in range(d)]
+    n = [N[a] + 1 if all_nodes else n_unknowns(N[a], bc) for a in range(d)]
     ndof = int(np.prod(n))
     strides = [int(np.prod(n[:a])) for a in range(d)]
     gp = np.array([-1.0, 1.0]) / np.sqrt(3.0)  # on [-1, 1]
@@ -121,7 +186,9 @@ def q1_quadrature_assembly(N, h, D, origin=None, bc="dirichlet"):
         gidx = []
         for c in corners:
             node = [elem[a] + c[a] for a in range(d)]
-            if periodic:
+            if all_nodes:
+                gidx.append(sum(node[a] * strides[a] for a in range(d)))
+            elif periodic:
                 gidx.append(sum((node[a] % N[a]) * strides[a] for a in range(d)))
             elif any(node[a] == 0 or node[a] == N[a] for a in range(d)):
                 gidx.append(-1)

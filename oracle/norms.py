@@ -87,3 +87,58 @@ def quadrature_errors_2d(N, h, origin, U, exact, exact_grad, t, chunk_rows=64):
                 l2 += wt * float(np.sum((ue - uh) ** 2))
                 semi += wt * float(np.sum((gx - dux) ** 2 + (gy - duy) ** 2))
     return np.sqrt(l2), np.sqrt(l2 + semi)
+
+
+def quadrature_errors(N, h, origin, U, exact, exact_grad, t, npts=4):
+    """Continuous L2 and H1 errors between exact(t, .) and the Q1 function whose
+    interior nodal values are U and whose boundary nodal values are the exact
+    solution's (nonhomogeneous Dirichlet data), any d.
+
+    npts Gauss points per axis and element.  exact(t, X) and exact_grad(t, X)
+    (a list with one array per axis) take coordinate arrays broadcast to the
+    quadrature points.  Returns (L2, H1) with H1^2 = L2^2 + |grad error|^2.
+    """
+    d = len(N)
+    origin = [0.0] * d if origin is None else list(origin)
+    shape_all = tuple(N[a] + 1 for a in reversed(range(d)))
+    coords = np.meshgrid(*[origin[a] + h[a] * np.arange(N[a] + 1) for a in reversed(range(d))], indexing="ij")
+    Xall = [coords[d - 1 - a] for a in range(d)]
+    full = np.array(exact(t, Xall), dtype=np.float64) * np.ones(shape_all)
+    inner = tuple(slice(1, N[a]) for a in reversed(range(d)))
+    full[inner] = np.asarray(U, dtype=np.float64).reshape(tuple(N[a] - 1 for a in reversed(range(d))))
+    gq, wq = np.polynomial.legendre.leggauss(npts)
+    gq = (gq + 1.0) / 2.0
+    wq = wq / 2.0
+
+    def at_points(deriv_axis):
+        # value (or derivative along deriv_axis) of the Q1 function at every
+        # quadrature point: shape = cells in array order (N_{d-1}, ..., N_0),
+        # then one quadrature axis per mesh axis (0, 1, ..., d-1)
+        arr = full
+        for ax in range(d):
+            k = d - 1 - ax
+            lo = np.take(arr, np.arange(0, N[ax]), axis=k)
+            hi = np.take(arr, np.arange(1, N[ax] + 1), axis=k)
+            if ax == deriv_axis:
+                arr = np.stack([(hi - lo) / h[ax]] * npts, axis=-1)
+            else:
+                arr = np.stack([lo * (1.0 - g) + hi * g for g in gq], axis=-1)
+        return arr
+
+    uh = at_points(-1)
+    pts, w = [], 1.0
+    for ax in range(d):
+        xq = origin[ax] + h[ax] * (np.arange(N[ax])[:, None] + gq[None, :])  # (cells, q)
+        shp = [1] * (2 * d)
+        shp[d - 1 - ax] = N[ax]
+        shp[d + ax] = npts
+        pts.append(xq.reshape(shp))
+        wshp = [1] * (2 * d)
+        wshp[d + ax] = npts
+        w = w * (wq * h[ax]).reshape(wshp)
+    l2 = float(np.sum(w * (uh - exact(t, pts)) ** 2))
+    grads = exact_grad(t, pts)
+    semi = 0.0
+    for ax in range(d):
+        semi += float(np.sum(w * (at_points(ax) - grads[ax]) ** 2))
+    return np.sqrt(l2), np.sqrt(l2 + semi)

@@ -95,3 +95,47 @@ def ex51_exact_grad(t, X):
 
 EX51_ORIGIN = (0.5, 0.0)
 EX51_D = 0.5
+
+
+def traveling_wave(eps):
+    """Example 5.2 reaction (u - u^3) / eps^2 (the equation u_t = Lap u + f, D = 1)."""
+    return lambda t, X, U: (U - U ** 3) / (eps * eps)
+
+
+def traveling_wave_solution(eps):
+    """Example 5.2 exact solution and its derivatives, functions of (t, x):
+    u = (1 - tanh(xi)) / 2 with xi = (x - s t) / (2 sqrt(2) eps), s = 3 / (sqrt(2) eps);
+    u_t = s / (4 sqrt(2) eps) sech^2(xi), u_x = -1 / (4 sqrt(2) eps) sech^2(xi).
+    It depends on x only; the Dirichlet data are its values on the boundary."""
+    w = 2.0 * np.sqrt(2.0) * eps
+    s = 3.0 / (np.sqrt(2.0) * eps)
+
+    def u(t, x):
+        return 0.5 * (1.0 - np.tanh((x - s * t) / w))
+
+    def sech2(t, x):
+        return 1.0 / np.cosh((x - s * t) / w) ** 2
+
+    def u_t(t, x):
+        return 0.5 * s / w * sech2(t, x)
+
+    def u_x(t, x):
+        return -0.5 / w * sech2(t, x)
+
+    return u, u_t, u_x
+
+
+def linear_in_time_data(coef):
+    """Closed-form check of the boundary lifting: with l(x) = c_0 + sum_a c_{a+1} x_a,
+    f = l(x) (independent of u and t) and Dirichlet data g = t l(x), the solution
+    of u_t = D Lap u + f is u = t l(x) for every D (Lap l = 0)."""
+    def l(X):
+        v = coef[0]
+        for a, x in enumerate(X):
+            v = v + coef[a + 1] * x
+        return v
+
+    f = lambda t, X, U: np.broadcast_to(l(X), np.shape(U)).astype(np.float64)
+    g = lambda t, Xb: t * l(Xb)
+    g_t = lambda t, Xb: l(Xb) + 0.0 * Xb[0]
+    return f, g, g_t, l

@@ -34,17 +34,34 @@ def load_spectral(basis, f, t, U, X, load):
 
 
 def run(basis, u0, f, tau, n_steps, stages, c2=0.5, t0=0.0, load="lumped",
-        origin=None, callback=None):
+        origin=None, callback=None, boundary=None):
     """Advance nodal values u0 by n_steps EIFE steps; returns nodal u^n.
 
     f(t, X, U) is the reaction, X the coordinate arrays of the interior nodes.
     callback(n, t_n, U) is called after every step when given.
+    boundary: None (homogeneous data) or a pair (g, g_t) of callables of
+    (t, Xb) giving the Dirichlet values and their time derivative at the
+    boundary nodes (coordinates Xb of fem.boundary_coupling).  Then the load
+    gains -Mb g_t(t) - Kb g(t) (Dirichlet grids only): the boundary values
+    enter as part of f, evaluated at the same times as f.
     """
     if stages not in (1, 2):
         raise ValueError("stages must be 1 or 2")
     if not (0.0 < c2 <= 1.0):
         raise ValueError("c2 must lie in (0, 1]")
     X = fem.mesh(basis.N, basis.h, origin, getattr(basis, "bc", "dirichlet"))
+    if boundary is not None:
+        if getattr(basis, "bc", "dirichlet") != "dirichlet":
+            raise ValueError("boundary data need a Dirichlet grid")
+        Mb, Kb, Xb = fem.boundary_coupling(basis.N, basis.h, basis.D, origin)
+        g_b, g_bt = boundary
+
+        def load_at(t, U):
+            extra = -(Mb @ g_bt(t, Xb) + Kb @ g_b(t, Xb))
+            return load_spectral(basis, f, t, U, X, load) + basis.load_to_spectral(extra.reshape(basis.shape))
+    else:
+        def load_at(t, U):
+            return load_spectral(basis, f, t, U, X, load)
     z = -tau * basis.lam
     E = phi(0, z)
     P1 = phi(1, z)
@@ -58,13 +75,13 @@ def run(basis, u0, f, tau, n_steps, stages, c2=0.5, t0=0.0, load="lumped",
     c = basis.to_spectral(U)
     for n in range(n_steps):
         tn = t0 + n * tau
-        G1 = load_spectral(basis, f, tn, U, X, load)
+        G1 = load_at(tn, U)
         if stages == 1:
             c = E * c + tau * P1 * G1
         else:
             c_stage = Ec * c + c2 * tau * P1c * G1
             U2 = basis.from_spectral(c_stage)
-            G2 = load_spectral(basis, f, tn + c2 * tau, U2, X, load)
+            G2 = load_at(tn + c2 * tau, U2)
             c = E * c + tau * ((P1 - P2 / c2) * G1 + (P2 / c2) * G2)
         U = basis.from_spectral(c)
         if callback is not None:
