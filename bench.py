@@ -320,16 +320,112 @@ def cpu_baseline_ex53(u0, N, h, D, tau, theta, theta_c, budget_s=12.0, max_steps
                       f"periodic tier C (numpy real FFTs, one thread), {dt:.2f} s"}
 
 
+def q1_errors_wave(U, N, h, t, eps, npts=4, zchunk=4):
+    """Continuous L2 and H1 errors of the 3D Q1 function with interior nodal values U
+    (boundary nodes: the exact traveling wave) against Example 5.2's exact solution,
+    npts Gauss points per axis and element, summed over slabs of zchunk element layers."""
+    w2 = 2.0 * np.sqrt(2.0) * eps
+    s = 3.0 / (np.sqrt(2.0) * eps)
+    u_ex = lambda x: 0.5 * (1.0 - np.tanh((x - s * t) / w2))
+    ux_ex = lambda x: -0.5 / w2 / np.cosh((x - s * t) / w2) ** 2
+    nx, ny, nz = N
+    x = h[0] * np.arange(nx + 1)
+    full = np.broadcast_to(u_ex(x), (nz + 1, ny + 1, nx + 1)).copy()
+    full[1:nz, 1:ny, 1:nx] = U.reshape(nz - 1, ny - 1, nx - 1)
+    gq, wq = np.polynomial.legendre.leggauss(npts)
+    gq, wq = (gq + 1.0) / 2.0, wq / 2.0
+    xq = (x[:-1, None] + h[0] * gq[None, :]).reshape(-1)  # (cell, q) flattened
+    ue, uxe = u_ex(xq), ux_ex(xq)
+    wxyz = np.einsum("i,j,k->ijk", wq, wq, wq) * h[0] * h[1] * h[2]
+    l2 = semi = 0.0
+    for z0 in range(0, nz, zchunk):
+        z1 = min(nz, z0 + zchunk)
+        Fz = full[z0:z1 + 1]
+        for qz, gz in enumerate(gq):
+            Fzq = Fz[:-1] * (1 - gz) + Fz[1:] * gz            # value at z point
+            Dz = (Fz[1:] - Fz[:-1]) / h[2]                      # z derivative
+            for qy, gy in enumerate(gq):
+                V = Fzq[:, :-1] * (1 - gy) + Fzq[:, 1:] * gy    # (cz, ny, nx + 1)
+                Dy = (Fzq[:, 1:] - Fzq[:, :-1]) / h[1]
+                Vz = Dz[:, :-1] * (1 - gy) + Dz[:, 1:] * gy
+                for qx, gx in enumerate(gq):
+                    w = wxyz[qx, qy, qz]
+                    uh = V[..., :-1] * (1 - gx) + V[..., 1:] * gx
+                    dx = (V[..., 1:] - V[..., :-1]) / h[0]
+                    dy = Dy[..., :-1] * (1 - gx) + Dy[..., 1:] * gx
+                    dz = Vz[..., :-1] * (1 - gx) + Vz[..., 1:] * gx
+                    l2 += w * float(np.sum((uh - ue[qx::npts]) ** 2))
+                    semi += w * float(np.sum((dx - uxe[qx::npts]) ** 2 + dy ** 2 + dz ** 2))
+    return float(np.sqrt(l2)), float(np.sqrt(l2 + semi))
+
+
+def bench_ex52(args, torch, eife):
+    """Example 5.2 (Section 5.1), the traveling wave of Table 4: u_t = Lap u + (u - u^3)/eps^2 on
+    (0, sqrt 2) x (0, 1/8)^2, eps = 0.05, nonhomogeneous Dirichlet data from the exact wave, entering
+    as part of f, T = 3 sqrt(2) eps / 5.  FP64.  Spatial rows: EIFE2, N_T = 1024 on 64x4x4 ... 512x32x32;
+    temporal rows: EIFE1 and EIFE2, N_T = 16 ... 128 on 1024x64x64.  Per run: continuous L2 and H1 errors
+    (4^3 Gauss points per element) and DoF-steps/s; rates between consecutive rows."""
+    eps = 0.05
+    T = 3.0 * np.sqrt(2.0) * eps / 5.0
+    w2 = 2.0 * np.sqrt(2.0) * eps
+
+    def run(nx, ny, nt, stages):
+        N = [nx, ny, ny]
+        h = [np.sqrt(2.0) / nx, 0.125 / ny, 0.125 / ny]
+        x = h[0] * np.arange(1, nx)
+        u0 = np.broadcast_to(0.5 * (1.0 - np.tanh(x / w2)), (ny - 1, ny - 1, nx - 1))
+        g = eife.Grid(N, h, 1.0, "f64")
+        g.set_forcing(eps, 0.0)
+        g.set_phi(T / nt, stages)
+        u = torch.tensor(np.ascontiguousarray(u0), device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(u, nt, eife.F_TRAVELING_WAVE, 0.0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        g.close()
+        l2, h1 = q1_errors_wave(u.cpu().numpy(), N, h, T, eps)
+        ndof = (nx - 1) * (ny - 1) ** 2
+        log(f"  EIFE{stages} N_T={nt} {nx}x{ny}x{ny}: L2 {l2:.4e} H1 {h1:.4e}, {ndof * nt / dt:.3e} DoF-steps/s")
+        return {"N_T": nt, "grid": f"{nx}x{ny}x{ny}", "L2": l2, "H1": h1, "dof_steps_per_s": ndof * nt / dt}
+
+    def with_rates(rows):
+        for a, b in zip(rows, rows[1:]):
+            b["L2_rate"] = round(float(np.log2(a["L2"] / b["L2"])), 2)
+            b["H1_rate"] = round(float(np.log2(a["H1"] / b["H1"])), 2)
+        return rows
+
+    log("bench: Example 5.2 traveling wave (Table 4), FP64")
+    res = {"spatial_eife2": with_rates([run(nx, nx // 16, 1024, 2) for nx in (64, 128, 256, 512)])}
+    for stages in (1, 2):
+        res[f"temporal_eife{stages}"] = with_rates([run(1024, 64, nt, stages) for nt in (16, 32, 64, 128)])
+    for key, rows in res.items():
+        for r in rows:
+            log(f"  {key:15s} N_T={r['N_T']:5d} {r['grid']:>11s} L2 {r['L2']:.4e} ({r.get('L2_rate', '-')}) "
+                f"H1 {r['H1']:.4e} ({r.get('H1_rate', '-')}) {r['dof_steps_per_s']:.3e} DoF-steps/s")
+    best = res["temporal_eife2"][-1]
+    ndof = 1023 * 63 * 63
+    out = {"metric": "Example 5.2 (Table 4) EIFE errors, observed rates and DoF-steps/s", "value": best["dof_steps_per_s"],
+           "unit": "DoF-steps/s", "n_gpus": 1, "steps": best["N_T"], "warmup": 0,
+           "ms_per_step": 1e3 * ndof / best["dof_steps_per_s"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "Example 5.2 traveling wave, eps=0.05, nonhomogeneous Dirichlet data as part of f, "
+                                  "T=3 sqrt(2) eps/5; value: EIFE2 N_T=128 on 1024x64x64", "dofs": ndof},
+           "ex52": res}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", choices=["cube", "batched", "manufactured", "ex53"], default="cube",
+    ap.add_argument("--workload", choices=["cube", "batched", "manufactured", "ex53", "ex52"], default="cube",
                     help="cube: 3D Allen-Cahn 255^3 (default line); batched: 512 independent 2D instances; "
                          "manufactured: 4095^2 orders, errors and rates; ex53: periodic 128^3 Flory-Huggins "
-                         "grain coarsening to T = 20")
+                         "grain coarsening to T = 20; ex52: traveling wave with Dirichlet data (Table 4)")
     ap.add_argument("--transform", choices=["fft", "gemm"], default="fft",
                     help="cube workload: FFT sine transforms (default) or split-BF16 matrix-core products")
     ap.add_argument("--no-corrector", action="store_true",
@@ -352,6 +448,8 @@ def main():
         return bench_manufactured(args, torch, eife)
     if args.workload == "ex53":
         return bench_ex53(args, torch, eife)
+    if args.workload == "ex52":
+        return bench_ex52(args, torch, eife)
 
     N = [N_INT] * 3
     h = [1.0 / N_INT] * 3

@@ -63,8 +63,15 @@ enum eife_fkind {
                             f = -(pi^2/2) u + (pi^2/2) e^{-pi^2 t} sin(pi x) sin(pi y) */
   EIFE_F_CONST = 4,      /* f = c0, independent of u, x and t (c0 from eife_set_forcing) */
   EIFE_F_AFFINE_T = 5,   /* f = c0 + c1 t, independent of u and x */
-  EIFE_F_FLORY_HUGGINS = 6 /* Section 5.2, Example 5.3: f = (theta/2) ln((1 - u)/(1 + u)) + theta_c u,
-                              theta = c0, theta_c = c1 from eife_set_forcing; needs |u| < 1 */
+  EIFE_F_FLORY_HUGGINS = 6, /* Section 5.2, Example 5.3: f = (theta/2) ln((1 - u)/(1 + u)) + theta_c u,
+                               theta = c0, theta_c = c1 from eife_set_forcing; needs |u| < 1 */
+  EIFE_F_TRAVELING_WAVE = 7 /* Section 5.1, Example 5.2: f = (u - u^3) / eps^2 (eps = c0 > 0, the equation
+                               has D = 1) on a Dirichlet grid whose boundary nodes carry the exact wave
+                               g = (1 - tanh((x - s t) / (2 sqrt(2) eps))) / 2, s = 3 / (sqrt(2) eps),
+                               x = origin_x + i h_x.  The data enter as part of f (start of Section 4):
+                               the load of interior node i gains -sum_j (M_ij g_j' + D K1_ij g_j) over
+                               its boundary neighbours j (Q1 mass M, stiffness K1 for D = 1).  Lumped
+                               load only (EIFE_LOAD_NODAL: EIFE_EUNSUPPORTED); no periodic grids. */
 };
 
 /* How P_h f(t, u_h) is formed from the nodal values of f (the paper's load
@@ -131,7 +138,8 @@ enum eife_transform {
  * selection.  Unknown kind: EIFE_EINVAL.  Batches ignore this setting. */
 int eife_set_transform(eife_grid g, int kind);
 
-/* Parameters c0, c1 of EIFE_F_CONST / EIFE_F_AFFINE_T / EIFE_F_FLORY_HUGGINS. */
+/* Parameters c0, c1 of EIFE_F_CONST / EIFE_F_AFFINE_T / EIFE_F_FLORY_HUGGINS, c0 of
+ * EIFE_F_TRAVELING_WAVE. */
 int eife_set_forcing(eife_grid g, double c0, double c1);
 
 /* Advance the nodal values u (device pointer, in place) by n_steps >= 0

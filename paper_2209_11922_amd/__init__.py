@@ -19,6 +19,7 @@ from .binding import (  # noqa: F401
     F_CONST,
     F_EX51,
     F_FLORY_HUGGINS,
+    F_TRAVELING_WAVE,
     F_MMS_U2,
     F_ZERO,
     library_path,

@@ -12,7 +12,7 @@ OK, EINVAL, ENOMEM, EUNSUPPORTED, ESTATE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, 
 # enums
 BC_DIRICHLET, BC_PERIODIC = 0, 1
 F32, F64 = 0, 1
-F_ZERO, F_ALLEN_CAHN, F_MMS_U2, F_EX51, F_CONST, F_AFFINE_T, F_FLORY_HUGGINS = range(7)
+F_ZERO, F_ALLEN_CAHN, F_MMS_U2, F_EX51, F_CONST, F_AFFINE_T, F_FLORY_HUGGINS, F_TRAVELING_WAVE = range(8)
 LOAD_LUMPED, LOAD_NODAL = 0, 1
 TX_FFT, TX_FFT_GENERIC, TX_GEMM_SPLITBF16 = 0, 1, 2
 PASS_NAMES = ["row_phys", "row_fwd", "row_inv", "mid", "last_plain", "last_a", "last_b", "last_etd1"]

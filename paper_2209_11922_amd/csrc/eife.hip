@@ -239,6 +239,7 @@ Forcing make_forcing(const eife_grid_s* g, int kind, double t) {
   for (int a = 0; a < 3; ++a) {
     F.a[a] = g->a[a];
     F.h[a] = g->h[a];
+    F.n[a] = g->n[a];
   }
   return F;
 }
@@ -1149,10 +1150,15 @@ int eife_step(eife_grid g, void* u, int64_t n_steps, int f_kind, double t0, void
   RET_IF(check_grid(g));
   if (!u) return fail(EIFE_EINVAL, "u is null");
   if (n_steps < 0) return fail(EIFE_EINVAL, "n_steps must be >= 0");
-  if (f_kind < EIFE_F_ZERO || f_kind > EIFE_F_FLORY_HUGGINS) return fail(EIFE_EINVAL, "unknown f_kind %d", f_kind);
+  if (f_kind < EIFE_F_ZERO || f_kind > EIFE_F_TRAVELING_WAVE) return fail(EIFE_EINVAL, "unknown f_kind %d", f_kind);
   if (f_kind == EIFE_F_EX51 && g->d != 2) return fail(EIFE_EINVAL, "EIFE_F_EX51 is a 2D problem");
-  if ((f_kind == EIFE_F_MMS_U2 || f_kind == EIFE_F_EX51) && g->per[0])
+  if ((f_kind == EIFE_F_MMS_U2 || f_kind == EIFE_F_EX51 || f_kind == EIFE_F_TRAVELING_WAVE) && g->per[0])
     return fail(EIFE_EUNSUPPORTED, "f_kind %d is a Dirichlet problem", f_kind);
+  if (f_kind == EIFE_F_TRAVELING_WAVE) {
+    if (g->load != EIFE_LOAD_LUMPED)
+      return fail(EIFE_EUNSUPPORTED, "boundary data enter the lumped load only (EIFE_LOAD_LUMPED)");
+    if (!(g->c0 > 0.0)) return fail(EIFE_EINVAL, "EIFE_F_TRAVELING_WAVE needs eps = c0 > 0 (eife_set_forcing)");
+  }
   if (!std::isfinite(t0)) return fail(EIFE_EINVAL, "t0 must be finite");
   if (!g->phi_ready) return fail(EIFE_ESTATE, "eife_set_phi must be called before eife_step");
   if (n_steps == 0) return EIFE_OK;

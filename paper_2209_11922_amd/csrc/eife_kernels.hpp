@@ -225,9 +225,62 @@ struct Forcing {
   double D;
   double a[3];
   double h[3];
+  int n[3];  // interior nodes per axis (unused axes 1)
 };
 
-enum FKind { FK_ZERO = 0, FK_AC = 1, FK_MMS = 2, FK_EX51 = 3, FK_CONST = 4, FK_AFFINE = 5, FK_FH = 6 };
+enum FKind { FK_ZERO = 0, FK_AC = 1, FK_MMS = 2, FK_EX51 = 3, FK_CONST = 4, FK_AFFINE = 5, FK_FH = 6, FK_EX52 = 7 };
+
+// Example 5.2's traveling wave g = (1 - tanh(xi)) / 2, xi = (x - s t) / (2 sqrt(2) eps),
+// s = 3 / (sqrt(2) eps); returns g and stores dg/dt.
+__device__ __forceinline__ double ex52_wave(double x, double t, double eps, double* g_t) {
+  const double w = 2.0 * 1.4142135623730951 * eps;
+  const double s = 3.0 / (1.4142135623730951 * eps);
+  const double th = tanh((x - s * t) / w);
+  *g_t = 0.5 * s / w * (1.0 - th * th);
+  return 0.5 * (1.0 - th);
+}
+
+// Nonhomogeneous Dirichlet data as part of f (start of Section 4): with the
+// boundary nodes carrying g(t), the Galerkin load of interior node i gains
+// b_i = -sum over boundary neighbours j of (M_ij g_j' + D K1_ij g_j).  Returned
+// divided by prod(h), the scale of the lumped load f(u_i) prod(h), so it adds
+// to the reaction value.  Per axis the 1D entries over h are 2/3 (same node) and
+// 1/6 (neighbour) for the mass, 2/h^2 and -1/h^2 for the stiffness.  Nonzero
+// only on the shell of nodes next to the boundary.
+__device__ __forceinline__ double ex52_boundary_load(const Forcing& F, int ix, int iy, int iz) {
+  const int idx[3] = {ix + 1, iy + 1, iz + 1};  // all-node indices
+  const bool shell = idx[0] == 1 || idx[0] == F.n[0] || (F.d > 1 && (idx[1] == 1 || idx[1] == F.n[1])) ||
+                     (F.d > 2 && (idx[2] == 1 || idx[2] == F.n[2]));
+  if (!shell) return 0.0;
+  double acc = 0.0;
+  const int oz0 = F.d > 2 ? -1 : 0, oz1 = F.d > 2 ? 1 : 0;
+  const int oy0 = F.d > 1 ? -1 : 0, oy1 = F.d > 1 ? 1 : 0;
+  for (int oz = oz0; oz <= oz1; ++oz)
+    for (int oy = oy0; oy <= oy1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int o[3] = {ox, oy, oz};
+        bool bnd = false;
+        double al[3], be[3];
+        for (int a = 0; a < 3; ++a) {
+          if (a < F.d) {
+            const int j = idx[a] + o[a];
+            bnd = bnd || j == 0 || j == F.n[a] + 1;
+            al[a] = o[a] ? 1.0 / 6.0 : 2.0 / 3.0;
+            be[a] = (o[a] ? -1.0 : 2.0) / (F.h[a] * F.h[a]);
+          } else {
+            al[a] = 1.0;
+            be[a] = 0.0;
+          }
+        }
+        if (!bnd) continue;
+        const double mass = al[0] * al[1] * al[2];
+        const double stiff = be[0] * al[1] * al[2] + al[0] * be[1] * al[2] + al[0] * al[1] * be[2];
+        double g_t;
+        const double g = ex52_wave(F.a[0] + (idx[0] + ox) * F.h[0], F.t, F.c0, &g_t);
+        acc -= mass * g_t + F.D * stiff * g;
+      }
+  return acc;
+}
 
 // Per-instance data of a batched launch (instances of one size class share
 // geometry and launch shape; blockIdx.y (row passes) or blockIdx.z (column
@@ -261,6 +314,10 @@ __device__ __forceinline__ T reaction(const Forcing& F, T u, int ix, int iy, int
       return T(F.c0 + F.c1 * F.t);
     case FK_FH:  // Example 5.3: (theta/2) ln((1 - u)/(1 + u)) + theta_c u, theta = c0, theta_c = c1
       return T(0.5) * T(F.c0) * log((T(1) - u) / (T(1) + u)) + T(F.c1) * u;
+    case FK_EX52: {  // Example 5.2: (u - u^3) / eps^2, eps = c0, plus the traveling-wave boundary data
+      const double ud = double(u);
+      return T((ud - ud * ud * ud) / (F.c0 * F.c0) + ex52_boundary_load(F, ix, iy, iz));
+    }
     case FK_MMS: {
       double s = sinpi(F.a[0] + (ix + 1) * F.h[0]);
       if (F.d > 1) s *= sinpi(F.a[1] + (iy + 1) * F.h[1]);

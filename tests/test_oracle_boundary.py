@@ -131,3 +131,17 @@ def test_table4_spatial_rates():
     # same order of magnitude as the printed errors
     for (l2, h1), r in zip(errs, rows):
         assert 0.1 < l2 / r[5] < 10 and 0.5 < h1 / r[6] < 2
+
+
+def test_bench_wave_quadrature_equals_oracle_quadrature():
+    """The chunked error quadrature of the Example 5.2 bench equals the oracle's on random data."""
+    import bench
+    u, _, u_x = problems.traveling_wave_solution(EPS)
+    N = [16, 4, 3]
+    h = [np.sqrt(2.0) / 16, 0.125 / 4, 0.125 / 3]
+    U = np.random.default_rng(0).uniform(0.0, 1.0, (2, 3, 15))
+    ex = lambda t, Y: u(t, Y[0]) + 0.0 * sum(Y[1:])
+    gr = lambda t, Y: [u_x(t, Y[0]) + 0.0 * sum(Y[1:])] + [0.0 * Y[0] + 0.0 * y for y in Y[1:]]
+    got = bench.q1_errors_wave(U, N, h, 0.02, EPS, zchunk=2)
+    ref = norms.quadrature_errors(N, h, None, U, ex, gr, 0.02)
+    np.testing.assert_allclose(got, ref, rtol=1e-13)
