@@ -1,7 +1,7 @@
 """EIFE1 and EIFE2 time stepping (oracle; test infrastructure only).
 
-Section 2.2.  With uniform steps tau and t_n = t0 + n tau, the EIFE1 scheme
-(eq. (2.13)) is
+Section 2.2.  With steps tau_n and t_{n+1} = t_n + tau_n (uniform: tau_n = tau),
+the EIFE1 scheme (eq. (2.13)) is
     u^{n+1} = e^{-tau L} u^n + tau phi_1(-tau L) P_h f(t_n, u^n)
 and the EIFE2 scheme (eq. (2.14)), with node c2 in (0, 1], is
     U2      = e^{-c2 tau L} u^n + c2 tau phi_1(-c2 tau L) P_h f(t_n, u^n)
@@ -37,6 +37,10 @@ def run(basis, u0, f, tau, n_steps, stages, c2=0.5, t0=0.0, load="lumped",
         origin=None, callback=None, boundary=None):
     """Advance nodal values u0 by n_steps EIFE steps; returns nodal u^n.
 
+    tau: one step size, or a sequence of per-step sizes tau_n (Section 2.2
+    lets the step vary; every operator function is then formed with tau_n)
+    whose length must equal n_steps.
+
     f(t, X, U) is the reaction, X the coordinate arrays of the interior nodes.
     callback(n, t_n, U) is called after every step when given.
     boundary: None (homogeneous data) or a pair (g, g_t) of callables of
@@ -62,19 +66,27 @@ def run(basis, u0, f, tau, n_steps, stages, c2=0.5, t0=0.0, load="lumped",
     else:
         def load_at(t, U):
             return load_spectral(basis, f, t, U, X, load)
-    z = -tau * basis.lam
-    E = phi(0, z)
-    P1 = phi(1, z)
-    if stages == 1:
-        pass
-    else:
-        P2 = phi(2, z)
-        Ec = phi(0, c2 * z)
-        P1c = phi(1, c2 * z)
+    uniform = np.ndim(tau) == 0
+    taus = np.full(n_steps, float(tau)) if uniform else np.asarray(tau, dtype=np.float64)
+    if len(taus) != n_steps or np.any(taus <= 0.0):
+        raise ValueError("need n_steps positive step sizes")
+    cached = [None]
+
+    def factors(tau_n):
+        if cached[0] is None or cached[0][0] != tau_n:
+            z = -tau_n * basis.lam
+            f2 = (phi(2, z), phi(0, c2 * z), phi(1, c2 * z)) if stages == 2 else (None, None, None)
+            cached[0] = (tau_n, phi(0, z), phi(1, z)) + f2
+        return cached[0][1:]
+
     U = np.array(u0, dtype=np.float64).reshape(basis.shape)
     c = basis.to_spectral(U)
+    tn = t0
     for n in range(n_steps):
-        tn = t0 + n * tau
+        tau = float(taus[n])
+        # t_n = t0 + n tau (uniform) or the running sum t0 + tau_0 + ... + tau_{n-1}
+        tn = t0 + n * tau if uniform else (tn + float(taus[n - 1]) if n > 0 else t0)
+        E, P1, P2, Ec, P1c = factors(tau)
         G1 = load_at(tn, U)
         if stages == 1:
             c = E * c + tau * P1 * G1
@@ -85,5 +97,5 @@ def run(basis, u0, f, tau, n_steps, stages, c2=0.5, t0=0.0, load="lumped",
             c = E * c + tau * ((P1 - P2 / c2) * G1 + (P2 / c2) * G2)
         U = basis.from_spectral(c)
         if callback is not None:
-            callback(n + 1, t0 + (n + 1) * tau, U)
+            callback(n + 1, tn + tau, U)
     return U
