@@ -416,16 +416,62 @@ def bench_ex52(args, torch, eife):
     return 0
 
 
+def bench_variable(args, torch, eife):
+    """Variable step sizes on the benchmark problem (3D Allen-Cahn 255^3 FP32 EIFE2): the same
+    K steps through eife_step (uniform tau) and through eife_step_variable with equal steps
+    (same bits) and with varying steps tau_n = tau (1 + 0.5 sin n); DoF-steps/s of each, so the
+    cost of the per-step factors (built on the host, staged in chunks) shows."""
+    N = [N_INT] * 3
+    h = [1.0 / N_INT] * 3
+    ndof = (N_INT - 1) ** 3
+    u0 = seeded_inputs.uniform_field(SEED, N)
+    K = args.steps
+    g = eife.Grid(N, h, EPS * EPS, "f32")
+    g.set_phi(TAU, 2)
+    u = torch.tensor(u0, dtype=torch.float32, device="cuda")
+    g.step(u, args.warmup, eife.F_ALLEN_CAHN, 0.0)
+    g.step_variable(u, [TAU] * max(args.warmup, 1), eife.F_ALLEN_CAHN, 0.0)
+    res = {}
+    runs = (("uniform_eife_step", None), ("equal_taus_step_variable", [TAU] * K),
+            ("varying_taus_step_variable", list(TAU * (1.0 + 0.5 * np.sin(np.arange(K))))))
+    outs = {}
+    for name, taus in runs:
+        u.copy_(torch.tensor(u0, dtype=torch.float32))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if taus is None:
+            g.step(u, K, eife.F_ALLEN_CAHN, 0.0)
+        else:
+            g.step_variable(u, taus, eife.F_ALLEN_CAHN, 0.0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        outs[name] = u.clone()
+        res[name] = {"dof_steps_per_s": ndof * K / dt, "ms_per_step": dt * 1e3 / K}
+        log(f"  {name:28s} {dt * 1e3 / K:.4f} ms/step, {ndof * K / dt:.4e} DoF-steps/s")
+    g.close()
+    res["equal_taus_bitwise_equal"] = bool(torch.equal(outs["uniform_eife_step"], outs["equal_taus_step_variable"]))
+    v = res["varying_taus_step_variable"]
+    out = {"metric": "variable-step EIFE2 DoF-steps/s", "value": v["dof_steps_per_s"], "unit": "DoF-steps/s",
+           "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": v["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "3D Allen-Cahn eps=0.02, 255^3 DoFs, FP32, EIFE2 c2=1/2, tau_n = 0.005 (1 + 0.5 sin n)",
+                      "dofs": ndof},
+           "variable": res}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", choices=["cube", "batched", "manufactured", "ex53", "ex52"], default="cube",
+    ap.add_argument("--workload", choices=["cube", "batched", "manufactured", "ex53", "ex52", "variable"], default="cube",
                     help="cube: 3D Allen-Cahn 255^3 (default line); batched: 512 independent 2D instances; "
                          "manufactured: 4095^2 orders, errors and rates; ex53: periodic 128^3 Flory-Huggins "
-                         "grain coarsening to T = 20; ex52: traveling wave with Dirichlet data (Table 4)")
+                         "grain coarsening to T = 20; ex52: traveling wave with Dirichlet data (Table 4); "
+                         "variable: the cube problem with varying step sizes")
     ap.add_argument("--transform", choices=["fft", "gemm"], default="fft",
                     help="cube workload: FFT sine transforms (default) or split-BF16 matrix-core products")
     ap.add_argument("--no-corrector", action="store_true",
@@ -450,6 +496,8 @@ def main():
         return bench_ex53(args, torch, eife)
     if args.workload == "ex52":
         return bench_ex52(args, torch, eife)
+    if args.workload == "variable":
+        return bench_variable(args, torch, eife)
 
     N = [N_INT] * 3
     h = [1.0 / N_INT] * 3

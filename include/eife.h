@@ -24,7 +24,9 @@
  *     library keeps no pointer to them after a call returns.
  *   - The grid owns its device workspaces (spectral state, work array,
  *     tables), allocated by eife_create_grid and released by
- *     eife_destroy_grid.  A grid may be used from one host thread at a time.
+ *     eife_destroy_grid.  A grid may be used from one host thread at a time,
+ *     and calls on one grid that use different streams must be ordered by
+ *     the caller (they share the grid's workspaces).
  *   - Work is enqueued on the HIP stream passed in (NULL = the default
  *     stream) and is asynchronous unless stated otherwise.  Argument errors
  *     are reported synchronously; a failed kernel launch returns EIFE_EHIP.
@@ -150,6 +152,24 @@ int eife_set_forcing(eife_grid g, double c0, double c1);
  * after enqueueing.  Errors: EIFE_EINVAL (null u, negative n_steps, unknown
  * f_kind, EX51 with d != 2), EIFE_ESTATE (no eife_set_phi), EIFE_EHIP. */
 int eife_step(eife_grid g, void* u, int64_t n_steps, int f_kind, double t0, void* stream);
+
+/* Variable step sizes (Section 2.2 lets the step vary): advance u (device,
+ * in place) by n_steps steps of sizes taus[0 .. n_steps-1] (host array, each
+ * > 0 and finite), t_{n+1} = t_n + tau_n from t_0 = t0 (a running sum in
+ * double), every factor of eqs. (2.13)/(2.14) formed with tau_n.  Scheme
+ * (stages, c2), load reading and transform as set on the grid; the step size
+ * of eife_set_phi is neither used nor changed.  The factors of up to 512
+ * steps (at most 16 MB) at a time are built on the host, staged in pinned
+ * memory and copied on `stream` ahead of the steps that read them, in two
+ * alternating buffers that the grid allocates on its first variable-step
+ * call and keeps; the host waits only before it refills a buffer whose
+ * previous copy has not completed (it returns after enqueueing the last
+ * step).
+ * All taus equal to the grid's tau give the same bits as eife_step.
+ * Errors: as eife_step, plus EIFE_EINVAL for a null or non-positive taus
+ * entry and EIFE_ENOMEM. */
+int eife_step_variable(eife_grid g, void* u, const double* taus, int64_t n_steps, int f_kind, double t0,
+                       void* stream);
 
 /* Double-precision norms of the finite element function with nodal values
  * e = u - uref (uref may be NULL, then e = u), both device arrays in the

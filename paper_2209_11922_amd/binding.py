@@ -52,6 +52,8 @@ def load_library():
     lib.eife_set_transform.argtypes = [c_void_p, c_int]
     lib.eife_step.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_int, c_double, c_void_p]
     lib.eife_norms.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]
+    lib.eife_step_variable.argtypes = [c_void_p, c_void_p, ctypes.POINTER(c_double), ctypes.c_int64, c_int,
+                                       c_double, c_void_p]
     lib.eife_energy.argtypes = [c_void_p, c_void_p, c_int, ctypes.POINTER(c_double), c_void_p]
     lib.eife_grid_size.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_int64)]
     lib.eife_profile.argtypes = [c_void_p, c_int]
@@ -90,7 +92,7 @@ def load_library():
     lib.eife_last_error.argtypes = []
     lib.eife_version.argtypes = []
     for name in ("eife_create_grid", "eife_destroy_grid", "eife_set_phi", "eife_set_c2", "eife_set_origin",
-                 "eife_set_load", "eife_set_forcing", "eife_step", "eife_norms", "eife_energy", "eife_grid_size",
+                 "eife_set_load", "eife_set_forcing", "eife_step", "eife_step_variable", "eife_norms", "eife_energy", "eife_grid_size",
                  "eife_version", "eife_profile", "eife_profile_read", "eife_set_transform", "eife_create_batch",
                  "eife_destroy_batch", "eife_batch_offsets", "eife_batch_set_phi", "eife_batch_step",
                  "eife_batch_autotune", "eife_batch_class_info"):
@@ -180,6 +182,14 @@ class Grid:
         self._check_array(u, "u")
         _check(self._lib, self._lib.eife_step(self._g, ctypes.c_void_p(u.data_ptr()), int(n_steps), int(f_kind),
                                               float(t0), _stream_ptr(stream)))
+        return u
+
+    def step_variable(self, u, taus, f_kind, t0=0.0, stream=None):
+        """Advance u in place by len(taus) steps of sizes taus[n] (eife_step_variable)."""
+        self._check_array(u, "u")
+        arr = (ctypes.c_double * len(taus))(*[float(t) for t in taus])
+        _check(self._lib, self._lib.eife_step_variable(self._g, ctypes.c_void_p(u.data_ptr()), arr, len(taus),
+                                                       int(f_kind), float(t0), _stream_ptr(stream)))
         return u
 
     def profile(self, on):

@@ -109,6 +109,14 @@ struct eife_grid_s {
   double* partials = nullptr;
   double* out5 = nullptr;
   double* host5 = nullptr;  // pinned
+  // per-step phi tables of variable-step runs (eife_step_variable): a chunk of
+  // steps at a time, each step 3 arrays (M, Q, Mc) per axis
+  // (two chunk buffers, filled alternately)
+  double* vtab = nullptr;
+  double* vhost = nullptr;  // pinned staging copies
+  hipEvent_t vev[2] = {nullptr, nullptr};  // copy of the buffer's last chunk done
+  int64_t vchunk = 0;       // steps per chunk (0: not allocated)
+  std::vector<double> hlam[3];  // host copy of the lambda table of each axis
   // launch shapes
   FftPlan plan[3];
   int transform = EIFE_TX_FFT;
@@ -176,6 +184,24 @@ double expm1_minus_z(double z) {
   return std::expm1(z) - z;
 }
 
+// The step-dependent tables of one axis for step size tau (zeros on virtual
+// axes and padding columns, which the stage never reads as nonzero).
+void fill_phi(const eife_grid_s* g, int ax, double tau, double* M, double* Q, double* Mc) {
+  const int len = g->tablen[ax];
+  for (int k = 0; k < len; ++k) {
+    M[k] = Q[k] = Mc[k] = 0.0;
+    if (ax >= g->d || k >= g->n[ax]) continue;
+    const double z = -tau * g->D * g->hlam[ax][k];
+    M[k] = std::expm1(z);
+    Q[k] = expm1_minus_z(z);
+    Mc[k] = std::expm1(g->c2 * z);
+  }
+}
+
+int64_t step_table_stride(const eife_grid_s* g) {
+  return 3 * (int64_t(g->tablen[0]) + g->tablen[1] + g->tablen[2]);
+}
+
 int upload_tables(eife_grid_s* g) {
   for (int ax = 0; ax < 3; ++ax) {
     const int len = g->tablen[ax];
@@ -200,13 +226,9 @@ int upload_tables(eife_grid_s* g) {
       const int kk = g->per[ax] ? 2 * k : k + 1;
       lam[k] = lam1d(g->N[ax], g->h[ax], kk);
       w[k] = (g->load == EIFE_LOAD_LUMPED) ? g->h[ax] / lamA1d(g->N[ax], g->h[ax], kk) : 1.0;
-      if (g->phi_ready) {
-        const double z = -g->tau * g->D * lam[k];
-        M[k] = std::expm1(z);
-        Q[k] = expm1_minus_z(z);
-        Mc[k] = std::expm1(g->c2 * z);
-      }
     }
+    g->hlam[ax].assign(lam, lam + len);
+    if (g->phi_ready) fill_phi(g, ax, g->tau, M, Q, Mc);
     HIP_TRY(hipMemcpy(g->tab[ax], buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   return EIFE_OK;
@@ -225,6 +247,21 @@ Diag make_diag(const eife_grid_s* g) {
   dg.D = g->D;
   dg.tau = g->tau;
   dg.c2 = g->c2;
+  return dg;
+}
+
+// The stage tables of one step of a variable-step run: lam and w as always,
+// M, Q, Mc from the step's block of the chunk table.
+Diag make_diag_at(const eife_grid_s* g, const double* block, double tau) {
+  Diag dg = make_diag(g);
+  for (int ax = 0; ax < 3; ++ax) {
+    const int len = g->tablen[ax];
+    dg.ax[ax].M = block;
+    dg.ax[ax].Q = block + len;
+    dg.ax[ax].Mc = block + 2 * len;
+    block += 3 * len;
+  }
+  dg.tau = tau;
   return dg;
 }
 
@@ -817,11 +854,41 @@ int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, h
     if (_r != EIFE_OK) return _r; \
   } while (0)
 
+// Steps per chunk of a variable-step run: the chunk's tables take at most
+// 16 MB (at least one step).
+constexpr int64_t kVarChunkMax = 512;
+constexpr int64_t kVarChunkBytes = int64_t(16) << 20;
+
+int ensure_step_tables(eife_grid_s* g) {
+  if (g->vchunk) return EIFE_OK;
+  const int64_t stride = step_table_stride(g);
+  const int64_t chunk = std::max<int64_t>(1, std::min(kVarChunkMax, kVarChunkBytes / (stride * 8)));
+  const size_t bytes = 2 * size_t(chunk * stride) * sizeof(double);
+  if (hipMalloc(reinterpret_cast<void**>(&g->vtab), bytes) != hipSuccess) {
+    g->vtab = nullptr;
+    return fail(EIFE_ENOMEM, "variable-step table allocation failed");
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&g->vhost), bytes, hipHostMallocDefault) != hipSuccess) {
+    hipFree(g->vtab);
+    g->vtab = nullptr;
+    g->vhost = nullptr;
+    return fail(EIFE_ENOMEM, "variable-step staging allocation failed");
+  }
+  for (int b = 0; b < 2; ++b) HIP_TRY(hipEventCreateWithFlags(&g->vev[b], hipEventDisableTiming));
+  g->vchunk = chunk;
+  return EIFE_OK;
+}
+
+// taus (host, n_steps entries) selects variable steps: t_{n+1} = t_n + tau_n
+// (running sum in double), every factor formed with tau_n; null: uniform
+// steps of the grid's tau, t_n = t0 + n tau.
 template <typename T>
-int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipStream_t s) {
+int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipStream_t s,
+              const double* taus = nullptr) {
   T* W = static_cast<T*>(g->W);
   T* H = static_cast<T*>(g->H);
-  const Diag dg = make_diag(g);
+  const Diag dg_fixed = make_diag(g);
+  const Diag& dg0 = dg_fixed;
   const bool three = g->d == 3;
   const int last = three ? 2 : 1;
   // the y pass after the last-axis pass goes back to nodal y (the sine
@@ -832,10 +899,44 @@ int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipS
   // reaction is fused in
   const bool fused = n_steps > 0 && fused_first_row<T>(g);
   RET_IF(launch_row<T>(g, fused ? ROW_FWD_PHYS : ROW_FWD_USER, u, g->n[0], W, g->pitch, H, F0, s));
-  if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, H, H, dg, s));
-  RET_IF(launch_col<T>(g, last, COL_PLAIN, H, H, dg, s));
+  if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, H, H, dg0, s));
+  RET_IF(launch_col<T>(g, last, COL_PLAIN, H, H, dg0, s));
+  const int64_t stride = taus ? step_table_stride(g) : 0;
+  double tv = t0;  // running time of a variable-step run
   for (int64_t st = 0; st < n_steps; ++st) {
-    const double tn = t0 + double(st) * g->tau;
+    double tau = g->tau;
+    Diag dg_var;
+    if (taus) {
+      const int64_t j = st % g->vchunk;
+      const int64_t c = st / g->vchunk;
+      double* dev = g->vtab + (c & 1) * g->vchunk * stride;
+      if (j == 0) {
+        // chunk c goes to buffer c & 1 while the device may still run chunk
+        // c - 1 from the other one.  The staging half is rewritten once the
+        // last copy out of it (chunk c - 2, or a previous call's) has
+        // completed (its event; an event never recorded does not wait); the
+        // device half is rewritten in stream order, after the kernels that
+        // read it (calls on one grid are ordered by the caller, as for W, H).
+        double* host = g->vhost + (c & 1) * g->vchunk * stride;
+        HIP_TRY(hipEventSynchronize(g->vev[c & 1]));
+        const int64_t cnt = std::min(g->vchunk, n_steps - st);
+        for (int64_t q = 0; q < cnt; ++q) {
+          double* blk = host + q * stride;
+          for (int ax = 0; ax < 3; ++ax) {
+            const int len = g->tablen[ax];
+            fill_phi(g, ax, taus[st + q], blk, blk + len, blk + 2 * len);
+            blk += 3 * len;
+          }
+        }
+        HIP_TRY(hipMemcpyAsync(dev, host, size_t(cnt * stride) * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(g->vev[c & 1], s));
+      }
+      tau = taus[st];
+      if (st > 0) tv += taus[st - 1];
+      dg_var = make_diag_at(g, dev + j * stride, tau);
+    }
+    const Diag& dg = taus ? dg_var : dg_fixed;
+    const double tn = taus ? tv : t0 + double(st) * g->tau;
     if (!(fused && st == 0))
       RET_IF(launch_row<T>(g, ROW_PHYS, W, g->pitch, W, g->pitch, nullptr, make_forcing(g, f_kind, tn), s));
     if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, W, H, dg, s));
@@ -843,7 +944,7 @@ int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipS
     if (three) RET_IF(launch_col<T>(g, 1, inv_plain, W, H, dg, s));
     if (g->stages == 2) {
       RET_IF(launch_row<T>(g, ROW_PHYS, W, g->pitch, W, g->pitch, nullptr,
-                           make_forcing(g, f_kind, tn + g->c2 * g->tau), s));
+                           make_forcing(g, f_kind, tn + g->c2 * tau), s));
       if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, W, H, dg, s));
       RET_IF(launch_col<T>(g, last, COL_STAGE_B, W, H, dg, s));
       if (three) RET_IF(launch_col<T>(g, 1, inv_plain, W, H, dg, s));
@@ -917,6 +1018,10 @@ void free_grid(eife_grid_s* g) {
   hipFree(g->partials);
   hipFree(g->out5);
   if (g->host5) hipHostFree(g->host5);
+  hipFree(g->vtab);
+  if (g->vhost) hipHostFree(g->vhost);
+  for (int b = 0; b < 2; ++b)
+    if (g->vev[b]) hipEventDestroy(g->vev[b]);
   delete g;
 }
 
@@ -1165,6 +1270,24 @@ int eife_step(eife_grid g, void* u, int64_t n_steps, int f_kind, double t0, void
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (g->dtype == EIFE_F32) return run_steps<float>(g, static_cast<float*>(u), n_steps, f_kind, t0, s);
   return run_steps<double>(g, static_cast<double*>(u), n_steps, f_kind, t0, s);
+}
+
+int eife_step_variable(eife_grid g, void* u, const double* taus, int64_t n_steps, int f_kind, double t0,
+                       void* stream) {
+  RET_IF(check_grid(g));
+  if (n_steps < 0) return fail(EIFE_EINVAL, "n_steps must be >= 0");
+  if (n_steps > 0 && !taus) return fail(EIFE_EINVAL, "taus is null");
+  for (int64_t i = 0; i < n_steps; ++i)
+    if (!(taus[i] > 0.0) || !std::isfinite(taus[i]))
+      return fail(EIFE_EINVAL, "taus[%lld] must be a positive finite number", static_cast<long long>(i));
+  if (!g->phi_ready) return fail(EIFE_ESTATE, "eife_set_phi must be called before eife_step_variable");
+  if (n_steps == 0) return eife_step(g, u, 0, f_kind, t0, stream);
+  // the checks of eife_step on u, f_kind and t0, without running anything
+  RET_IF(eife_step(g, u, 0, f_kind, t0, stream));
+  RET_IF(ensure_step_tables(g));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (g->dtype == EIFE_F32) return run_steps<float>(g, static_cast<float*>(u), n_steps, f_kind, t0, s, taus);
+  return run_steps<double>(g, static_cast<double*>(u), n_steps, f_kind, t0, s, taus);
 }
 
 int eife_norms(eife_grid g, const void* u, const void* uref, double* out, void* stream) {
