@@ -105,11 +105,27 @@ int eife_create_grid(int d, const int32_t* N, const double* h, double D, int bc,
 int eife_destroy_grid(eife_grid g);
 
 /* Fix the step tau > 0 and the number of exponential Runge-Kutta stages:
- * 1 = EIFE1 (eq. (2.13)), 2 = EIFE2 (eq. (2.14)) with node c2.  Builds the
- * per-axis double tables of e^{-tau D lambda} and e^{-c2 tau D lambda}.
- * Must precede eife_step; repeat after eife_set_c2 or to change tau.
- * Synchronous with respect to the host (tables are uploaded before return). */
+ * 1 = EIFE1 (eq. (2.13)), 2 = EIFE2 (eq. (2.14)) with node c2, 3 = the
+ * three-stage scheme of eq. (2.2) with nodes (0, c2, c3) of eife_set_nodes3.
+ * Builds the per-axis double tables of e^{-tau D lambda} and e^{-c2 tau D
+ * lambda} (and, for 3 stages, of the c3-scaled and third-order terms).  The
+ * first 3-stage call allocates one more state array of the grid's size
+ * (kept until eife_destroy_grid).  Must precede eife_step; repeat after
+ * eife_set_c2 / eife_set_nodes3 or to change tau.  Synchronous with respect
+ * to the host (tables are uploaded before return).  Errors: EIFE_EINVAL,
+ * EIFE_ENOMEM. */
 int eife_set_phi(eife_grid g, double tau, int stages);
+
+/* Nodes 0 < c2 < c3 <= 1 of the three-stage scheme (default 1/3, 2/3; the
+ * EIFE2 node of eife_set_c2 is separate).  Its weights follow eq. (2.2): b_i
+ * from the Lagrange polynomials of (0, c2, c3), a_3j from those of (0, c2)
+ * (the reading that satisfies the consistency conditions, eq. (2.3)).  The
+ * three-stage column passes are the generic kernels (no specialised or
+ * split-BF16 variant: eife_step returns EIFE_EUNSUPPORTED with
+ * EIFE_TX_GEMM_SPLITBF16); the scheme keeps a third array X = e^{c3 z} u^ +
+ * tau a31 G_1 between its first and second stage.  If the grid is set to
+ * 3 stages, eife_set_phi must be called again.  Errors: EIFE_EINVAL. */
+int eife_set_nodes3(eife_grid g, double c2, double c3);
 
 /* EIFE2 node c2 in (0, 1] (Section 2.2, default 1/2).  Invalidates the phi
  * tables: call eife_set_phi again before stepping. */

@@ -57,17 +57,28 @@ def weights(nodes, z):
 
 
 def run(basis, u0, f, tau, n_steps, nodes, t0=0.0, load="lumped", origin=None):
-    """n_steps uniform steps of the s-stage scheme with the given nodes (nodes[0] = 0)."""
+    """n_steps steps of the s-stage scheme with the given nodes (nodes[0] = 0).
+
+    tau: one step size (t_n = t0 + n tau) or a sequence of n_steps sizes tau_n
+    (t_{n+1} = t_n + tau_n, every weight formed with tau_n)."""
     nodes = [float(c) for c in nodes]
     if nodes[0] != 0.0 or len(set(nodes)) != len(nodes) or not all(0.0 <= c <= 1.0 for c in nodes):
         raise ValueError("nodes must be distinct, in [0, 1], the first one 0")
     X = fem.mesh(basis.N, basis.h, origin, getattr(basis, "bc", "dirichlet"))
-    chi_i, a, b, chi = weights(nodes, -tau * basis.lam)
+    uniform = np.ndim(tau) == 0
+    taus = np.full(n_steps, float(tau)) if uniform else np.asarray(tau, dtype=np.float64)
+    if len(taus) != n_steps or np.any(taus <= 0.0):
+        raise ValueError("need n_steps positive step sizes")
     s = len(nodes)
     U = np.array(u0, dtype=np.float64).reshape(basis.shape)
     c = basis.to_spectral(U)
+    tn, cached = t0, (None, None)
     for n in range(n_steps):
-        tn = t0 + n * tau
+        tau = float(taus[n])
+        tn = t0 + n * tau if uniform else (tn + float(taus[n - 1]) if n > 0 else t0)
+        if cached[0] != tau:
+            cached = (tau, weights(nodes, -tau * basis.lam))
+        chi_i, a, b, chi = cached[1]
         G = []
         for i in range(s):
             ci = chi_i[i] * c + tau * sum(a[i, j] * G[j] for j in range(i)) if i else c

@@ -52,6 +52,7 @@ def load_library():
     lib.eife_set_transform.argtypes = [c_void_p, c_int]
     lib.eife_step.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_int, c_double, c_void_p]
     lib.eife_norms.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]
+    lib.eife_set_nodes3.argtypes = [c_void_p, c_double, c_double]
     lib.eife_step_variable.argtypes = [c_void_p, c_void_p, ctypes.POINTER(c_double), ctypes.c_int64, c_int,
                                        c_double, c_void_p]
     lib.eife_energy.argtypes = [c_void_p, c_void_p, c_int, ctypes.POINTER(c_double), c_void_p]
@@ -92,7 +93,7 @@ def load_library():
     lib.eife_last_error.argtypes = []
     lib.eife_version.argtypes = []
     for name in ("eife_create_grid", "eife_destroy_grid", "eife_set_phi", "eife_set_c2", "eife_set_origin",
-                 "eife_set_load", "eife_set_forcing", "eife_step", "eife_step_variable", "eife_norms", "eife_energy", "eife_grid_size",
+                 "eife_set_load", "eife_set_forcing", "eife_step", "eife_step_variable", "eife_set_nodes3", "eife_norms", "eife_energy", "eife_grid_size",
                  "eife_version", "eife_profile", "eife_profile_read", "eife_set_transform", "eife_create_batch",
                  "eife_destroy_batch", "eife_batch_offsets", "eife_batch_set_phi", "eife_batch_step",
                  "eife_batch_autotune", "eife_batch_class_info"):
@@ -155,6 +156,10 @@ class Grid:
 
     def set_c2(self, c2):
         _check(self._lib, self._lib.eife_set_c2(self._g, float(c2)))
+
+    def set_nodes3(self, c2, c3):
+        """Nodes (0, c2, c3) of the three-stage scheme (eife_set_nodes3)."""
+        _check(self._lib, self._lib.eife_set_nodes3(self._g, float(c2), float(c3)))
 
     def set_origin(self, a):
         arr = (ctypes.c_double * self.d)(*[float(x) for x in a])

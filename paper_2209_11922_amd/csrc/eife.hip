@@ -54,7 +54,7 @@ int fail(int code, const char* fmt, ...) {
 constexpr int kThreads = 256;
 constexpr size_t kLdsBudget = 80 * 1024;  // per block, two blocks per CU fit in 160 KB
 constexpr int kNormBlocksMax = 1024;
-constexpr int kTabArrays = 5;  // lam, w, M, Q, Mc per axis
+constexpr int kTabArrays = 8;  // lam, w, M, Q, Mc, R, Mc3, Qc3 per axis
 constexpr int kPipeBlocksPerCu = 4;  // resident blocks of the pipelined column pass (LDS permitting)
 constexpr int kStagePipeMinTiles = 2;  // tiles per resident block from which the stage pass is pipelined
 int g_cus = 256;                     // compute units of the device (set at grid creation)
@@ -95,6 +95,8 @@ struct eife_grid_s {
   double tau = 0;
   int stages = 0;
   double c2 = 0.5;
+  double c2_3 = 1.0 / 3.0, c3_3 = 2.0 / 3.0;  // nodes of the three-stage scheme
+  void* X = nullptr;  // extra spectral state of the three-stage scheme (allocated on first use)
   int load = EIFE_LOAD_LUMPED;
   double c0 = 0, c1 = 0;
   bool phi_ready = false;
@@ -184,22 +186,50 @@ double expm1_minus_z(double z) {
   return std::expm1(z) - z;
 }
 
+// expm1(z) - z - z^2/2 for z <= 0: power series below |z| = 1, else direct.
+double expm1_minus_z2(double z) {
+  if (std::fabs(z) < 1.0) {
+    double term = z * z * z / 6.0, sum = 0.0;
+    for (int m = 3; m < 60 && term != 0.0; ++m) {
+      sum += term;
+      term *= z / double(m + 1);
+    }
+    return sum;
+  }
+  return std::expm1(z) - z - 0.5 * z * z;
+}
+
+// Second node of the scheme in use (the three-stage scheme has its own pair).
+double node_c2(const eife_grid_s* g) { return g->stages == 3 ? g->c2_3 : g->c2; }
+
+constexpr int kStepArrays = 6;  // M, Q, Mc, R, Mc3, Qc3
+
 // The step-dependent tables of one axis for step size tau (zeros on virtual
-// axes and padding columns, which the stage never reads as nonzero).
-void fill_phi(const eife_grid_s* g, int ax, double tau, double* M, double* Q, double* Mc) {
+// axes and padding columns, which the stage never reads as nonzero; R, Mc3,
+// Qc3 only for the three-stage scheme).  t points at kStepArrays arrays of
+// the axis length.
+void fill_phi(const eife_grid_s* g, int ax, double tau, double* t) {
   const int len = g->tablen[ax];
+  double *M = t, *Q = t + len, *Mc = t + 2 * len, *R = t + 3 * len, *Mc3 = t + 4 * len, *Qc3 = t + 5 * len;
+  const double c2 = node_c2(g), c3 = g->c3_3;
+  const bool three = g->stages == 3;
   for (int k = 0; k < len; ++k) {
-    M[k] = Q[k] = Mc[k] = 0.0;
+    M[k] = Q[k] = Mc[k] = R[k] = Mc3[k] = Qc3[k] = 0.0;
     if (ax >= g->d || k >= g->n[ax]) continue;
     const double z = -tau * g->D * g->hlam[ax][k];
     M[k] = std::expm1(z);
     Q[k] = expm1_minus_z(z);
-    Mc[k] = std::expm1(g->c2 * z);
+    Mc[k] = std::expm1(c2 * z);
+    if (three) {
+      R[k] = expm1_minus_z2(z);
+      Mc3[k] = std::expm1(c3 * z);
+      Qc3[k] = expm1_minus_z(c3 * z);
+    }
   }
 }
 
 int64_t step_table_stride(const eife_grid_s* g) {
-  return 3 * (int64_t(g->tablen[0]) + g->tablen[1] + g->tablen[2]);
+  return kStepArrays * (int64_t(g->tablen[0]) + g->tablen[1] + g->tablen[2]);
 }
 
 int upload_tables(eife_grid_s* g) {
@@ -209,8 +239,6 @@ int upload_tables(eife_grid_s* g) {
     double* lam = buf.data();
     double* w = lam + len;
     double* M = w + len;
-    double* Q = M + len;
-    double* Mc = Q + len;
     const bool real_axis = ax < g->d;
     for (int k = 0; k < len; ++k) {
       if (!real_axis) {  // virtual axis of a 1D/2D grid: the identity
@@ -228,7 +256,7 @@ int upload_tables(eife_grid_s* g) {
       w[k] = (g->load == EIFE_LOAD_LUMPED) ? g->h[ax] / lamA1d(g->N[ax], g->h[ax], kk) : 1.0;
     }
     g->hlam[ax].assign(lam, lam + len);
-    if (g->phi_ready) fill_phi(g, ax, g->tau, M, Q, Mc);
+    if (g->phi_ready) fill_phi(g, ax, g->tau, M);
     HIP_TRY(hipMemcpy(g->tab[ax], buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   return EIFE_OK;
@@ -243,10 +271,15 @@ Diag make_diag(const eife_grid_s* g) {
     dg.ax[ax].M = g->tab[ax] + 2 * len;
     dg.ax[ax].Q = g->tab[ax] + 3 * len;
     dg.ax[ax].Mc = g->tab[ax] + 4 * len;
+    dg.ax[ax].R = g->tab[ax] + 5 * len;
+    dg.ax[ax].Mc3 = g->tab[ax] + 6 * len;
+    dg.ax[ax].Qc3 = g->tab[ax] + 7 * len;
   }
   dg.D = g->D;
   dg.tau = g->tau;
-  dg.c2 = g->c2;
+  dg.c2 = node_c2(g);
+  dg.c3 = g->c3_3;
+  dg.X = g->X;
   return dg;
 }
 
@@ -259,7 +292,10 @@ Diag make_diag_at(const eife_grid_s* g, const double* block, double tau) {
     dg.ax[ax].M = block;
     dg.ax[ax].Q = block + len;
     dg.ax[ax].Mc = block + 2 * len;
-    block += 3 * len;
+    dg.ax[ax].R = block + 3 * len;
+    dg.ax[ax].Mc3 = block + 4 * len;
+    dg.ax[ax].Qc3 = block + 5 * len;
+    block += kStepArrays * len;
   }
   dg.tau = tau;
   return dg;
@@ -554,6 +590,20 @@ void row_generic_go(int mode, dim3 grid, size_t shm, hipStream_t s, const T* src
 template <typename T, bool BATC>
 void col_generic_go(int mode, dim3 grid, size_t shm, hipStream_t s, T* W, T* H, const ColGeom& cg, const Cx<T>* tw,
                     const Diag& dg, const ColInst<T>* ci) {
+  if constexpr (!BATC) {
+    if (mode == COL_S3_1) {
+      hipLaunchKernelGGL((col_pass<T, COL_S3_1, false>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+      return;
+    }
+    if (mode == COL_S3_2) {
+      hipLaunchKernelGGL((col_pass<T, COL_S3_2, false>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+      return;
+    }
+    if (mode == COL_S3_3) {
+      hipLaunchKernelGGL((col_pass<T, COL_S3_3, false>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+      return;
+    }
+  }
   if (mode == COL_PLAIN)
     hipLaunchKernelGGL((col_pass<T, COL_PLAIN, BATC>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
   else if (mode == COL_STAGE_A)
@@ -587,6 +637,12 @@ void col_periodic_go(int mode, dim3 grid, size_t shm, hipStream_t s, T* W, T* H,
     hipLaunchKernelGGL((col_pass_per<T, COL_STAGE_A>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
   else if (mode == COL_STAGE_B)
     hipLaunchKernelGGL((col_pass_per<T, COL_STAGE_B>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+  else if (mode == COL_S3_1)
+    hipLaunchKernelGGL((col_pass_per<T, COL_S3_1>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+  else if (mode == COL_S3_2)
+    hipLaunchKernelGGL((col_pass_per<T, COL_S3_2>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+  else if (mode == COL_S3_3)
+    hipLaunchKernelGGL((col_pass_per<T, COL_S3_3>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
   else
     hipLaunchKernelGGL((col_pass_per<T, COL_ETD1>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
 }
@@ -827,12 +883,14 @@ int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, h
   int kind = EIFE_PASS_MID;
   if (!(axis == 1 && g->d == 3)) {
     kind = mode == COL_PLAIN ? EIFE_PASS_LAST_PLAIN
-           : mode == COL_STAGE_A ? EIFE_PASS_LAST_A
-           : mode == COL_STAGE_B ? EIFE_PASS_LAST_B : EIFE_PASS_LAST_ETD1;
+           : (mode == COL_STAGE_A || mode == COL_S3_1) ? EIFE_PASS_LAST_A
+           : (mode == COL_STAGE_B || mode == COL_S3_2 || mode == COL_S3_3) ? EIFE_PASS_LAST_B : EIFE_PASS_LAST_ETD1;
   }
   const int pidx = prof_begin(g, kind, s);
-  if (!(B.count == 1 && !ci && try_col_gemm<T>(g, axis, mode, outer, s, W, H, cg, dg)) &&
-      !try_col_fast<T>(g, B.var_col, axis, mode, outer, B.count, s, W, H, cg, tw, dg, ci)) {
+  // the three-stage column passes exist as generic kernels only
+  const bool s3 = mode >= COL_S3_1;
+  if (s3 || (!(B.count == 1 && !ci && try_col_gemm<T>(g, axis, mode, outer, s, W, H, cg, dg)) &&
+             !try_col_fast<T>(g, B.var_col, axis, mode, outer, B.count, s, W, H, cg, tw, dg, ci))) {
     const size_t shm = lds_bytes(g, cg.P, cg.pl.L);
     dim3 grid(g->pitch / (2 * cg.P), outer, B.count);
     if (g->per[axis]) {
@@ -923,9 +981,8 @@ int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipS
         for (int64_t q = 0; q < cnt; ++q) {
           double* blk = host + q * stride;
           for (int ax = 0; ax < 3; ++ax) {
-            const int len = g->tablen[ax];
-            fill_phi(g, ax, taus[st + q], blk, blk + len, blk + 2 * len);
-            blk += 3 * len;
+            fill_phi(g, ax, taus[st + q], blk);
+            blk += kStepArrays * g->tablen[ax];
           }
         }
         HIP_TRY(hipMemcpyAsync(dev, host, size_t(cnt * stride) * sizeof(double), hipMemcpyHostToDevice, s));
@@ -937,16 +994,16 @@ int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipS
     }
     const Diag& dg = taus ? dg_var : dg_fixed;
     const double tn = taus ? tv : t0 + double(st) * g->tau;
-    if (!(fused && st == 0))
-      RET_IF(launch_row<T>(g, ROW_PHYS, W, g->pitch, W, g->pitch, nullptr, make_forcing(g, f_kind, tn), s));
-    if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, W, H, dg, s));
-    RET_IF(launch_col<T>(g, last, g->stages == 1 ? COL_ETD1 : COL_STAGE_A, W, H, dg, s));
-    if (three) RET_IF(launch_col<T>(g, 1, inv_plain, W, H, dg, s));
-    if (g->stages == 2) {
-      RET_IF(launch_row<T>(g, ROW_PHYS, W, g->pitch, W, g->pitch, nullptr,
-                           make_forcing(g, f_kind, tn + g->c2 * tau), s));
+    // stage i: reaction at t_n + c_i tau, transforms, the stage's diagonal update
+    static const int kModes[4][3] = {{0, 0, 0}, {COL_ETD1, 0, 0}, {COL_STAGE_A, COL_STAGE_B, 0},
+                                     {COL_S3_1, COL_S3_2, COL_S3_3}};
+    const double nodes[3] = {0.0, node_c2(g), g->c3_3};
+    for (int i = 0; i < g->stages; ++i) {
+      if (!(fused && st == 0 && i == 0))
+        RET_IF(launch_row<T>(g, ROW_PHYS, W, g->pitch, W, g->pitch, nullptr,
+                             make_forcing(g, f_kind, i ? tn + nodes[i] * tau : tn), s));
       if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, W, H, dg, s));
-      RET_IF(launch_col<T>(g, last, COL_STAGE_B, W, H, dg, s));
+      RET_IF(launch_col<T>(g, last, kModes[g->stages][i], W, H, dg, s));
       if (three) RET_IF(launch_col<T>(g, 1, inv_plain, W, H, dg, s));
     }
   }
@@ -1005,6 +1062,7 @@ void free_grid(eife_grid_s* g) {
   if (!g) return;
   hipFree(g->W);
   hipFree(g->H);
+  hipFree(g->X);
   for (int a = 0; a < 3; ++a) {
     hipFree(g->tw[a]);
     hipFree(g->tab[a]);
@@ -1168,6 +1226,15 @@ int eife_set_c2(eife_grid g, double c2) {
   return EIFE_OK;
 }
 
+int eife_set_nodes3(eife_grid g, double c2, double c3) {
+  RET_IF(check_grid(g));
+  if (!(c2 > 0.0 && c2 < c3 && c3 <= 1.0)) return fail(EIFE_EINVAL, "nodes must satisfy 0 < c2 < c3 <= 1");
+  g->c2_3 = c2;
+  g->c3_3 = c3;
+  if (g->stages == 3) g->phi_ready = false;
+  return EIFE_OK;
+}
+
 int eife_set_origin(eife_grid g, const double* a) {
   RET_IF(check_grid(g));
   if (!a) return fail(EIFE_EINVAL, "origin is null");
@@ -1213,7 +1280,15 @@ int eife_set_forcing(eife_grid g, double c0, double c1) {
 int eife_set_phi(eife_grid g, double tau, int stages) {
   RET_IF(check_grid(g));
   if (!(tau > 0.0) || !std::isfinite(tau)) return fail(EIFE_EINVAL, "tau must be a positive finite number");
-  if (stages != 1 && stages != 2) return fail(EIFE_EINVAL, "stages must be 1 or 2 (got %d)", stages);
+  if (stages < 1 || stages > 3) return fail(EIFE_EINVAL, "stages must be 1, 2 or 3 (got %d)", stages);
+  if (stages == 3 && !g->X) {
+    const size_t bytes = size_t(g->pitch) * g->n[1] * g->n[2] * g->esz;
+    if (hipMalloc(&g->X, bytes) != hipSuccess) {
+      g->X = nullptr;
+      return fail(EIFE_ENOMEM, "cannot allocate the three-stage state (%zu bytes)", bytes);
+    }
+    HIP_TRY(hipMemset(g->X, 0, bytes));
+  }
   g->tau = tau;
   g->stages = stages;
   g->phi_ready = true;
@@ -1266,6 +1341,8 @@ int eife_step(eife_grid g, void* u, int64_t n_steps, int f_kind, double t0, void
   }
   if (!std::isfinite(t0)) return fail(EIFE_EINVAL, "t0 must be finite");
   if (!g->phi_ready) return fail(EIFE_ESTATE, "eife_set_phi must be called before eife_step");
+  if (g->stages == 3 && g->transform == EIFE_TX_GEMM_SPLITBF16)
+    return fail(EIFE_EUNSUPPORTED, "the three-stage scheme runs on the FFT transforms only");
   if (n_steps == 0) return EIFE_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (g->dtype == EIFE_F32) return run_steps<float>(g, static_cast<float*>(u), n_steps, f_kind, t0, s);

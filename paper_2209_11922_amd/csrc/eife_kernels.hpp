@@ -158,6 +158,10 @@ struct AxisTab {
   const double* M;    // expm1(-tau D lambda_k)
   const double* Q;    // expm1(-tau D lambda_k) + tau D lambda_k
   const double* Mc;   // expm1(-c2 tau D lambda_k)
+  // three-stage scheme only (zero otherwise)
+  const double* R;    // expm1(z) - z - z^2/2, z = -tau D lambda_k
+  const double* Mc3;  // expm1(c3 z)
+  const double* Qc3;  // expm1(c3 z) - c3 z
 };
 
 struct Sep {
@@ -214,7 +218,78 @@ __device__ __forceinline__ void diag_apply(const Sep& s, double D, double tau, d
 struct Diag {
   AxisTab ax[3];
   double D, tau, c2;
+  double c3;  // third node of the three-stage scheme
+  void* X;    // its extra spectral state e^{c3 z} u^ + tau a31 G_1 (layout of H)
 };
+
+// The separable tables of the three-stage scheme (eq. (2.2), s = 3): besides
+// e^z - 1 and e^z - 1 - z it needs R = e^z - 1 - z - z^2/2 (phi_3 = R / z^3) and
+// the c3-scaled pair.  With e^a = 1 + a + Q_a, the product e^a e^b gives
+//   R_{a+b} = R_a + R_b + a Q_b + b Q_a + Q_a Q_b.
+struct Sep3 {
+  double lam, w, M, Q, Mc, R, Mc3, Qc3;
+};
+
+__device__ __forceinline__ Sep3 sep3_load(const AxisTab& t, int k) {
+  return Sep3{t.lam[k], t.w[k], t.M[k], t.Q[k], t.Mc[k], t.R[k], t.Mc3[k], t.Qc3[k]};
+}
+
+// tD = tau D, so that z = -tD lam
+__device__ __forceinline__ Sep3 sep3_combine(const Sep3& a, const Sep3& b, double tD) {
+  const double za = -tD * a.lam, zb = -tD * b.lam;
+  return Sep3{a.lam + b.lam,
+              a.w * b.w,
+              a.M + b.M + a.M * b.M,
+              a.Q + b.Q + a.M * b.M,
+              a.Mc + b.Mc + a.Mc * b.Mc,
+              a.R + b.R + za * b.Q + zb * a.Q + a.Q * b.Q,
+              a.Mc3 + b.Mc3 + a.Mc3 * b.Mc3,
+              a.Qc3 + b.Qc3 + a.Mc3 * b.Mc3};
+}
+
+// Column modes of the three-stage scheme (nodes 0, c2, c3; weights of eq. (2.2)
+// from the Lagrange polynomials: b_i of all three nodes, a_3j of nodes 0, c2):
+//   COL_S3_1: out = e^{c2 z} u^ + tau a21 G1,  X = e^{c3 z} u^ + tau a31 G1,
+//             H = e^z u^ + tau b1 G1
+//   COL_S3_2: out = X + tau a32 G2,  H += tau b2 G2
+//   COL_S3_3: out = H + tau b3 G3 (the new u^), H = out
+enum { COL_S3_1 = 5, COL_S3_2 = 6, COL_S3_3 = 7 };
+
+template <int MODE>
+__device__ __forceinline__ void diag3_apply(const Sep3& s, const Diag& dg, double g, double h, double x, double* out,
+                                            double* nh, double* nx) {
+  const double tau = dg.tau, c2 = dg.c2, c3 = dg.c3;
+  const double G = g * s.w;
+  // t_k = tau phi_k(z); p1c2 = tau phi_1(c2 z), p1c3 = tau phi_1(c3 z), p2c3 = tau phi_2(c3 z)
+  double t1, t2, t3, p1c2, p1c3, p2c3;
+  if (s.lam == 0.0) {  // zero mode of a periodic grid: phi_k(0) = 1/k!
+    t1 = tau;
+    t2 = 0.5 * tau;
+    t3 = tau / 6.0;
+    p1c2 = p1c3 = tau;
+    p2c3 = 0.5 * tau;
+  } else {
+    const double rL = 1.0 / (dg.D * s.lam);
+    t1 = -s.M * rL;
+    t2 = s.Q * rL * rL / tau;
+    t3 = -s.R * rL * rL * rL / (tau * tau);
+    p1c2 = -s.Mc * rL / c2;
+    p1c3 = -s.Mc3 * rL / c3;
+    p2c3 = s.Qc3 * rL * rL / (c3 * c3 * tau);
+  }
+  if (MODE == COL_S3_1) {
+    *out = h + s.Mc * h + c2 * p1c2 * G;
+    *nx = h + s.Mc3 * h + (c3 * p1c3 - c3 * c3 / c2 * p2c3) * G;
+    *nh = h + s.M * h + (2.0 * t3 - (c2 + c3) * t2 + c2 * c3 * t1) / (c2 * c3) * G;
+  } else if (MODE == COL_S3_2) {
+    *out = x + c3 * c3 / c2 * p2c3 * G;
+    *nh = h + (2.0 * t3 - c3 * t2) / (c2 * (c2 - c3)) * G;
+  } else {
+    *out = *nh = h + (2.0 * t3 - c2 * t2) / (c3 * (c3 - c2)) * G;
+  }
+}
+
+
 
 // Reaction parameters
 struct Forcing {
@@ -500,6 +575,33 @@ __device__ __forceinline__ Cx<T> mask_pad(Cx<T> v, int c, int ncols) {
   return v;
 }
 
+// One spectral point pair (columns col, col + 1 at the line position of ky,
+// kz) of a three-stage column pass: reads H (and X), writes H (and X), returns
+// the two values to inverse transform.
+template <typename T, int MODE>
+__device__ __forceinline__ void stage3_pair(const Diag& dg, int col, int ky, int kz, int64_t off, T* H, T ga, T gb,
+                                            int ncols, T* outv) {
+  T* X = static_cast<T*>(dg.X);
+  const double tD = dg.tau * dg.D;
+  const Sep3 syz = sep3_combine(sep3_load(dg.ax[1], ky), sep3_load(dg.ax[2], kz), tD);
+  const Cx<T> hv = *reinterpret_cast<const Cx<T>*>(H + off);
+  Cx<T> xv{T(0), T(0)};
+  if (MODE == COL_S3_2) xv = *reinterpret_cast<const Cx<T>*>(X + off);
+  const T gin[2] = {ga, gb}, hin[2] = {hv.re, hv.im}, xin[2] = {xv.re, xv.im};
+  T newh[2], newx[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const Sep3 sp = sep3_combine(sep3_load(dg.ax[0], col + q), syz, tD);
+    double o, nh, nx = 0.0;
+    diag3_apply<MODE>(sp, dg, double(gin[q]), double(hin[q]), double(xin[q]), &o, &nh, &nx);
+    outv[q] = T(o);
+    newh[q] = T(nh);
+    newx[q] = T(nx);
+  }
+  *reinterpret_cast<Cx<T>*>(H + off) = mask_pad(Cx<T>{newh[0], newh[1]}, col, ncols);
+  if (MODE == COL_S3_1) *reinterpret_cast<Cx<T>*>(X + off) = mask_pad(Cx<T>{newx[0], newx[1]}, col, ncols);
+}
+
 template <typename T>
 __device__ __forceinline__ void col_inst_ptrs(const ColInst<T>* insts, T*& W, T*& H, Diag& dg) {
   if (!insts) return;
@@ -551,6 +653,22 @@ __global__ void __launch_bounds__(256) col_pass(T* W, T* H, ColGeom g, const Cx<
 
   // diagonal stage in spectral space, then the inverse transform
   const double tau = dg.tau, c2 = dg.c2, D = dg.D;
+  if constexpr (MODE >= COL_S3_1) {
+    for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+      const int m = i / P;
+      const int p = i - m * P;
+      Cx<T>* line = lds + p * g.ls;
+      const Cx<T> Z = line[m + 1];
+      T outv[2];
+      stage3_pair<T, MODE>(dg, c0 + 2 * p, g.last_is_z ? outer : m, g.last_is_z ? m : 0,
+                           base + int64_t(m) * g.ld_line + 2 * p, H, -Z.im * scale, Z.re * scale, g.ncols, outv);
+      put_odd(line, L, m + 1, outv[0], outv[1]);
+      if (m == 0) {
+        line[0] = Cx<T>{T(0), T(0)};
+        line[N] = Cx<T>{T(0), T(0)};
+      }
+    }
+  } else
   for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
     const int m = i / P;
     const int p = i - m * P;
@@ -771,6 +889,18 @@ __global__ void __launch_bounds__(256) col_pass_per(T* W, T* H, ColGeom g, const
   }
   // diagonal stage at position m of this axis, then the inverse transform
   const double tau = dg.tau, c2 = dg.c2, D = dg.D;
+  if constexpr (MODE >= COL_S3_1) {
+    for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
+      const int m = i / P;
+      const int p = i - m * P;
+      Cx<T>* line = lds + p * g.ls;
+      const Cx<T> gv = line[m];
+      T outv[2];
+      stage3_pair<T, MODE>(dg, c0 + 2 * p, g.last_is_z ? outer : m, g.last_is_z ? m : 0,
+                           base + int64_t(m) * g.ld_line + 2 * p, H, gv.re, gv.im, g.ncols, outv);
+      line[m] = Cx<T>{outv[0], outv[1]};
+    }
+  } else
   for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
     const int m = i / P;
     const int p = i - m * P;

@@ -238,7 +238,7 @@ def test_abi_errors():
     with pytest.raises(eife.EIFEError):
         g.set_phi(-1.0, 2)
     with pytest.raises(eife.EIFEError):
-        g.set_phi(0.1, 3)
+        g.set_phi(0.1, 4)
     with pytest.raises(eife.EIFEError):
         g.set_c2(0.0)
     g.set_phi(0.1, 2)

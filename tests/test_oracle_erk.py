@@ -95,3 +95,13 @@ def test_three_stage_order(nodes, order):
     errs = [norms.discrete_norms(N, h, erk.run(b, u0, f, 1.0 / 2 ** k, 2 ** k, nodes) - ref)[0] for k in (4, 5, 6)]
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(np.abs(rates - order) < 0.2), rates
+
+
+def test_variable_steps_match_the_two_stage_stepper():
+    N, h = [9, 7], [1 / 9, 1 / 7]
+    u0 = np.random.default_rng(6).uniform(-0.9, 0.9, (6, 8))
+    b = spectral.make_basis("C", N, h, 0.02)
+    taus = np.random.default_rng(7).uniform(0.01, 0.1, 7)
+    got = erk.run(b, u0, problems.affine_t(0.2, 0.7), taus, 7, [0.0, 0.4], t0=0.3)
+    ref = stepper.run(b, u0, problems.affine_t(0.2, 0.7), taus, 7, 2, c2=0.4, t0=0.3)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14)
