@@ -461,17 +461,96 @@ def bench_variable(args, torch, eife):
     return 0
 
 
+def bench_three(args, torch, eife):
+    """The three-stage scheme (eq. (2.2), nodes 0, 1/3, 2/3): (1) throughput on the benchmark problem
+    (3D Allen-Cahn 255^3 FP32) next to EIFE2 with per-pass event timings; (2) temporal errors on the
+    manufactured problem (2D 1023^2 FP64, T = 1) against a same-grid three-stage run at tau = 2^-10,
+    for EIFE2 and the three-stage scheme, with the observed orders."""
+    N = [N_INT] * 3
+    h = [1.0 / N_INT] * 3
+    ndof = (N_INT - 1) ** 3
+    u0 = seeded_inputs.uniform_field(SEED, N)
+    K = args.steps
+    res = {"cube": {}}
+    # FP32 bytes per DoF per launch: the first three-stage pass reads W, H and writes W, H, X; the
+    # second reads W, H, X and writes W, H; the third reads and writes W, H
+    s3_bytes = {"last_a": 20, "last_b": 18}
+    for stages in (2, 3):
+        g = eife.Grid(N, h, EPS * EPS, "f32")
+        g.set_phi(TAU, stages)
+        u = torch.tensor(u0, dtype=torch.float32, device="cuda")
+        g.step(u, args.warmup, eife.F_ALLEN_CAHN, 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(u, K, eife.F_ALLEN_CAHN, 0.0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        g.profile(True)
+        g.step(u, min(K, 20), eife.F_ALLEN_CAHN, 0.0)
+        prof = g.profile_read()
+        g.profile(False)
+        g.close()
+        passes = {}
+        for name, (ms, cnt) in prof.items():
+            if cnt:
+                b = s3_bytes.get(name, BYTES_PER_DOF[name]) if stages == 3 else BYTES_PER_DOF[name]
+                passes[name] = {"launches": cnt, "avg_us": round(ms / cnt * 1e3, 2),
+                                "alg_GBs": round(b * ndof / (ms / cnt * 1e-3) / 1e9, 1)}
+        res["cube"][f"stages{stages}"] = {"ms_per_step": dt * 1e3 / K, "dof_steps_per_s": ndof * K / dt,
+                                          "passes": passes}
+        log(f"  {stages} stages, 255^3 FP32: {dt * 1e3 / K:.3f} ms/step, {ndof * K / dt:.4e} DoF-steps/s; "
+            + ", ".join(f"{k} {v['avg_us']} us ({v['alg_GBs']} GB/s)" for k, v in passes.items()))
+        del u
+    # temporal orders on the manufactured problem
+    n_int = 1024
+    Nm, hm = [n_int, n_int], [1.0 / n_int] * 2
+    sx = np.sin(np.pi * np.arange(1, n_int) / n_int)
+    base = np.outer(sx, sx)
+
+    def run(stages, k):
+        g = eife.Grid(Nm, hm, 1.0, "f64")
+        g.set_phi(2.0 ** -k, stages)
+        u = torch.tensor(base, device="cuda")
+        g.step(u, 2 ** k, eife.F_MMS_U2, 0.0)
+        torch.cuda.synchronize()
+        return g, u
+
+    g_ref, u_ref = run(3, 10)
+    rows = {}
+    for stages in (2, 3):
+        errs = []
+        for k in (3, 4, 5, 6):
+            g, u = run(stages, k)
+            errs.append(g.norms(u, u_ref)[0])
+            g.close()
+        rates = [round(float(np.log2(a / b)), 2) for a, b in zip(errs, errs[1:])]
+        rows[f"stages{stages}"] = {"tau": [2.0 ** -k for k in (3, 4, 5, 6)], "L2_vs_ref": errs, "rates": rates}
+        log(f"  manufactured 1023^2 FP64, {stages} stages: L2 vs tau=2^-10 three-stage run "
+            + " ".join(f"{e:.3e}" for e in errs) + f", rates {rates}")
+    g_ref.close()
+    res["manufactured_orders"] = rows
+    v = res["cube"]["stages3"]
+    out = {"metric": "three-stage EIFE DoF-steps/s and observed temporal order", "value": v["dof_steps_per_s"],
+           "unit": "DoF-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": v["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "3D Allen-Cahn eps=0.02, 255^3 DoFs, FP32, three stages (nodes 0, 1/3, 2/3), "
+                                  "tau=0.005", "dofs": ndof},
+           "three_stage": res}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", choices=["cube", "batched", "manufactured", "ex53", "ex52", "variable"], default="cube",
+    ap.add_argument("--workload", choices=["cube", "batched", "manufactured", "ex53", "ex52", "variable", "three"], default="cube",
                     help="cube: 3D Allen-Cahn 255^3 (default line); batched: 512 independent 2D instances; "
                          "manufactured: 4095^2 orders, errors and rates; ex53: periodic 128^3 Flory-Huggins "
                          "grain coarsening to T = 20; ex52: traveling wave with Dirichlet data (Table 4); "
-                         "variable: the cube problem with varying step sizes")
+                         "variable: the cube problem with varying step sizes; three: the three-stage scheme")
     ap.add_argument("--transform", choices=["fft", "gemm"], default="fft",
                     help="cube workload: FFT sine transforms (default) or split-BF16 matrix-core products")
     ap.add_argument("--no-corrector", action="store_true",
@@ -498,6 +577,8 @@ def main():
         return bench_ex52(args, torch, eife)
     if args.workload == "variable":
         return bench_variable(args, torch, eife)
+    if args.workload == "three":
+        return bench_three(args, torch, eife)
 
     N = [N_INT] * 3
     h = [1.0 / N_INT] * 3

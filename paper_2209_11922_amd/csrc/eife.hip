@@ -495,7 +495,7 @@ void col_fast_go(int mode, int pitch, int outer, int count, bool pipe, hipStream
     constexpr int lds = PB * fast::Line<T, L>::BUF * int(sizeof(Cx<T>));
     constexpr int per_cu = std::max(1, std::min(kPipeBlocksPerCu, 160 * 1024 / lds));
     const int nblk = g_cus * per_cu;
-    if (pipe && ntiles >= kStagePipeMinTiles * nblk) {
+    if (pipe && ntiles >= kStagePipeMinTiles * nblk && mode < COL_S3_1) {
       if (mode == COL_STAGE_A)
         hipLaunchKernelGGL((fast::col_stage_pipe<T, L, PB, PPW, COL_STAGE_A>), dim3(nblk), dim3(NT), 0, s, W, H, cg,
                            tw, dg, ntx, ntiles);
@@ -505,6 +505,17 @@ void col_fast_go(int mode, int pitch, int outer, int count, bool pipe, hipStream
       else
         hipLaunchKernelGGL((fast::col_stage_pipe<T, L, PB, PPW, COL_ETD1>), dim3(nblk), dim3(NT), 0, s, W, H, cg,
                            tw, dg, ntx, ntiles);
+      return;
+    }
+  }
+  if constexpr (!BAT) {
+    if (mode == COL_S3_1 || mode == COL_S3_2 || mode == COL_S3_3) {
+      if (mode == COL_S3_1)
+        hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_S3_1, false>), grid, dim3(NT), 0, s, W, H, cg, tw, dg, ci);
+      else if (mode == COL_S3_2)
+        hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_S3_2, false>), grid, dim3(NT), 0, s, W, H, cg, tw, dg, ci);
+      else
+        hipLaunchKernelGGL((fast::col_fast<T, L, PB, PPW, COL_S3_3, false>), grid, dim3(NT), 0, s, W, H, cg, tw, dg, ci);
       return;
     }
   }
@@ -539,7 +550,8 @@ void col_fast_launch(int var, int mode, int pitch, int outer, int count, hipStre
 template <typename T>
 bool try_row_fast(const eife_grid_s* g, int var, int mode, int count, hipStream_t s, const T* src, T* dst, T* dst2,
                   const RowGeom& rg, const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
-  if (g->transform != EIFE_TX_FFT || g->per[0] || !fast_len<T>(g->N[0])) return false;
+  // the traveling wave's boundary code runs in the generic row pass only
+  if (g->transform != EIFE_TX_FFT || g->per[0] || !fast_len<T>(g->N[0]) || F.kind == FK_EX52) return false;
   switch (g->N[0]) {
     case 64: row_fast_launch<T, 128>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
     case 128: row_fast_launch<T, 256>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
@@ -769,7 +781,8 @@ bool try_row_gemm(const eife_grid_s* g, int mode, hipStream_t s, const T* src, T
   if constexpr (sizeof(T) != 4) {
     return false;
   } else {
-    if (g->transform != EIFE_TX_GEMM_SPLITBF16) return false;
+    // the traveling wave's boundary code runs in the generic row pass only
+    if (g->transform != EIFE_TX_GEMM_SPLITBF16 || F.kind == FK_EX52) return false;
     const gemm::SMat S = smat_of(g, 0);
     const bool ac = F.kind == FK_AC;
     switch (g->kp[0]) {
@@ -805,8 +818,8 @@ bool try_col_gemm(const eife_grid_s* g, int axis, int mode, int outer, hipStream
 // The first reaction of a run is fused into the forward row pass of the
 // prologue (ROW_FWD_PHYS) wherever the specialised row kernels run.
 template <typename T>
-bool fused_first_row(const eife_grid_s* g) {
-  return g->transform == EIFE_TX_FFT && !g->per[0] && fast_len<T>(g->N[0]);
+bool fused_first_row(const eife_grid_s* g, int f_kind) {
+  return g->transform == EIFE_TX_FFT && !g->per[0] && fast_len<T>(g->N[0]) && f_kind != EIFE_F_TRAVELING_WAVE;
 }
 
 // A launch of one pass over `count` instances shaped like grid `g`.
@@ -835,7 +848,7 @@ int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, i
   const int pidx = prof_begin(g, mode == ROW_PHYS ? EIFE_PASS_ROW_PHYS
                                  : (mode == ROW_FWD_USER || mode == ROW_FWD_PHYS) ? EIFE_PASS_ROW_FWD
                                                                                    : EIFE_PASS_ROW_INV, s);
-  if (mode == ROW_FWD_PHYS && !fused_first_row<T>(g)) return fail(EIFE_EUNSUPPORTED, "fused first row pass");
+  if (mode == ROW_FWD_PHYS && !fused_first_row<T>(g, F.kind)) return fail(EIFE_EUNSUPPORTED, "fused first row pass");
   if (!(B.count == 1 && !ri && try_row_gemm<T>(g, mode, s, src, dst, dst2, rg, F)) &&
       !try_row_fast<T>(g, B.var_row, mode, B.count, s, src, dst, dst2, rg, tw, F, ri)) {
     const size_t shm = lds_bytes(g, rg.P, rg.pl.L);
@@ -887,10 +900,10 @@ int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, h
            : (mode == COL_STAGE_B || mode == COL_S3_2 || mode == COL_S3_3) ? EIFE_PASS_LAST_B : EIFE_PASS_LAST_ETD1;
   }
   const int pidx = prof_begin(g, kind, s);
-  // the three-stage column passes exist as generic kernels only
+  // the three-stage column passes: specialised (one tile per block) or generic kernels, no matrix-core variant
   const bool s3 = mode >= COL_S3_1;
-  if (s3 || (!(B.count == 1 && !ci && try_col_gemm<T>(g, axis, mode, outer, s, W, H, cg, dg)) &&
-             !try_col_fast<T>(g, B.var_col, axis, mode, outer, B.count, s, W, H, cg, tw, dg, ci))) {
+  if ((s3 || !(B.count == 1 && !ci && try_col_gemm<T>(g, axis, mode, outer, s, W, H, cg, dg))) &&
+      !try_col_fast<T>(g, B.var_col, axis, mode, outer, B.count, s, W, H, cg, tw, dg, ci)) {
     const size_t shm = lds_bytes(g, cg.P, cg.pl.L);
     dim3 grid(g->pitch / (2 * cg.P), outer, B.count);
     if (g->per[axis]) {
@@ -955,7 +968,7 @@ int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipS
   const Forcing F0 = make_forcing(g, f_kind, t0);
   // prologue: H = S u and W = S_x u, or W = S_x f(t0, u) when the first
   // reaction is fused in
-  const bool fused = n_steps > 0 && fused_first_row<T>(g);
+  const bool fused = n_steps > 0 && fused_first_row<T>(g, f_kind);
   RET_IF(launch_row<T>(g, fused ? ROW_FWD_PHYS : ROW_FWD_USER, u, g->n[0], W, g->pitch, H, F0, s));
   if (three) RET_IF(launch_col<T>(g, 1, COL_PLAIN, H, H, dg0, s));
   RET_IF(launch_col<T>(g, last, COL_PLAIN, H, H, dg0, s));
@@ -1506,14 +1519,14 @@ int batch_enqueue(eife_batch_s* b, T* u, int64_t n_steps, int f_kind, double t0,
   for (auto& c : b->classes) {
     eife_grid_s* g = b->inst[c.members[0]];
     const Batchlet B = class_batchlet(c, false);
-    const int mode = (n_steps > 0 && fused_first_row<T>(g)) ? ROW_FWD_PHYS : ROW_FWD_USER;
+    const int mode = (n_steps > 0 && fused_first_row<T>(g, f_kind)) ? ROW_FWD_PHYS : ROW_FWD_USER;
     RET_IF(launch_row<T>(g, mode, u, g->n[0], nullptr, g->pitch, nullptr, make_forcing(g, f_kind, t0), s, B));
     RET_IF(launch_col<T>(g, 1, COL_PLAIN, nullptr, nullptr, make_diag(g), s, class_batchlet(c, true)));
   }
   for (int64_t st = 0; st < n_steps; ++st) {
     const double tn = t0 + double(st) * b->inst[0]->tau;
     for (auto& c : b->classes)
-      RET_IF(class_step<T>(b, c, f_kind, tn, s, st == 0 && fused_first_row<T>(b->inst[c.members[0]])));
+      RET_IF(class_step<T>(b, c, f_kind, tn, s, st == 0 && fused_first_row<T>(b->inst[c.members[0]], f_kind)));
   }
   for (auto& c : b->classes) {
     eife_grid_s* g = b->inst[c.members[0]];

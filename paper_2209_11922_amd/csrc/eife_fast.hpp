@@ -376,7 +376,7 @@ enum { RK_GENERIC = 0, RK_AC = 1 };
 template <typename T, int RK>
 __device__ __forceinline__ T reaction_k(const Forcing& F, T u, int ix, int iy, int iz) {
   if (RK == RK_AC) return u - u * u * u;
-  return reaction<T>(F, u, ix, iy, iz);
+  return reaction<T, false>(F, u, ix, iy, iz);
 }
 
 // ---------------------------------------------------------------------------
@@ -489,14 +489,6 @@ __global__ void __launch_bounds__((PB * Line<T, L>::LP), (MinWaves<T, L>::value)
   }
 }
 
-// 1 / x in double from the hardware estimate and two Newton steps (x > 0 normal).
-__device__ __forceinline__ double rcp64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
 
 template <int MODE>
 __device__ __forceinline__ void diag_fast(const Sep& s, double D, double tau, double rtc2, double g, double h,
@@ -522,8 +514,15 @@ __device__ __forceinline__ void diag_fast(const Sep& s, double D, double tau, do
 // Column passes (strided axis).  Block = PB pairs = C = 2 PB adjacent x-columns
 // (C * sizeof(T) >= 128 bytes per row segment); each wavefront slice of LP
 // lanes transforms PPW of the pairs one after the other.
+// The three-stage modes carry more tables through the stage: 2 waves per SIMD
+// (up to 256 registers per lane) keep them out of scratch.
+template <typename T, int L, int MODE>
+struct ColMinWaves {
+  static constexpr int value = MODE >= COL_S3_1 ? 2 : MinWaves<T, L>::value;
+};
+
 template <typename T, int L, int PB, int PPW, int MODE, bool BAT>
-__global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::value)) col_fast(T* W, T* H, ColGeom g, const Cx<T>* tw,
+__global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (ColMinWaves<T, L, MODE>::value)) col_fast(T* W, T* H, ColGeom g, const Cx<T>* tw,
                                                                         Diag dg, const ColInst<T>* __restrict__ insts) {
   // per-instance tables of a batched launch are held in separate locals (a
   // modified copy of the Diag argument would live in private memory)
@@ -597,7 +596,37 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
     }
   }
 
-  if (MODE != COL_PLAIN) {
+  if constexpr (MODE >= COL_S3_1) {
+    // three-stage scheme (single grids only): the generic per-point stage on
+    // the tile, reading H (and X) at the point
+    static_assert(!BAT, "the three-stage passes take single grids");
+    __syncthreads();
+    // the column pair and the outer index are fixed per thread
+    const S3K k3 = s3k_make(dg);
+    Sep3 sxy[2];
+    sep3_pair(dg, c0 + 2 * tq, g.last_is_z, outer, sxy);
+#pragma unroll
+    for (int it = 0; it < CIT; ++it) {
+      const int m = m0 + MS * it;
+      if (m < n) {
+        const Cx<T> gv = ltile[MS * it];
+        T outv[2];
+        stage3_pair<T, MODE>(dg, k3, sxy, g.last_is_z, m, c0 + 2 * tq, base + int64_t(m) * g.ld_line + 2 * tq, H,
+                             gv.re, gv.im, g.ncols, outv);
+        ltile[MS * it] = Cx<T>{outv[0], outv[1]};
+      }
+    }
+    __syncthreads();
+    __asm__ volatile("" ::: "memory");
+    typename Ln::Tw twl;
+    twl.load(tw, lane);
+#pragma unroll 1
+    for (int r = 0; r < PPW; ++r) {
+      Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
+      Ln::transform(v, my, my, lane, twl, tw);
+      Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+    }
+  } else if (MODE != COL_PLAIN) {
     __syncthreads();
     // diagonal stage over the tile: thread -> (row m, pair q), pair fixed per thread
     const double tau = dg.tau, D = Dv;

@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(Shape<KP>::THREADS) gemm_row(const float* src,
   if (MODE == ROW_PHYS) {
     for_acc<KP>(acc, wave, lane, [&](int m, int l, float& v) {
       const int r = r0 + l;
-      if (m < n && r < g.nrows) v = AC ? v - v * v * v : reaction<float>(F, v, m, r % g.ny, r / g.ny);
+      if (m < n && r < g.nrows) v = AC ? v - v * v * v : reaction<float, false>(F, v, m, r % g.ny, r / g.ny);
     });
     __syncthreads();
     acc_to_b<KP>(acc, bhi, blo, n, wave, lane);

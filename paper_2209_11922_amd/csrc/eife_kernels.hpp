@@ -255,37 +255,72 @@ __device__ __forceinline__ Sep3 sep3_combine(const Sep3& a, const Sep3& b, doubl
 //   COL_S3_3: out = H + tau b3 G3 (the new u^), H = out
 enum { COL_S3_1 = 5, COL_S3_2 = 6, COL_S3_3 = 7 };
 
+// 1 / x in double from the hardware estimate and two Newton steps (x > 0 normal).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Step constants of the three-stage weights, formed once per thread.
+struct S3K {
+  double tau, c2, c3, D;
+  double itau, itau2;        // 1 / tau, 1 / tau^2
+  double kb1, kb2, kb3;      // 1 / (c2 c3), 1 / (c2 (c2 - c3)), 1 / (c3 (c3 - c2))
+  double ka, ic3sq_tau;      // c3^2 / c2, 1 / (c3^2 tau)
+};
+
+__device__ __forceinline__ S3K s3k_make(const Diag& dg) {
+  S3K k;
+  k.tau = dg.tau;
+  k.c2 = dg.c2;
+  k.c3 = dg.c3;
+  k.D = dg.D;
+  k.itau = 1.0 / dg.tau;
+  k.itau2 = k.itau * k.itau;
+  k.kb1 = 1.0 / (dg.c2 * dg.c3);
+  k.kb2 = 1.0 / (dg.c2 * (dg.c2 - dg.c3));
+  k.kb3 = 1.0 / (dg.c3 * (dg.c3 - dg.c2));
+  k.ka = dg.c3 * dg.c3 / dg.c2;
+  k.ic3sq_tau = 1.0 / (dg.c3 * dg.c3 * dg.tau);
+  return k;
+}
+
 template <int MODE>
-__device__ __forceinline__ void diag3_apply(const Sep3& s, const Diag& dg, double g, double h, double x, double* out,
+__device__ __forceinline__ void diag3_apply(const Sep3& s, const S3K& k, double g, double h, double x, double* out,
                                             double* nh, double* nx) {
-  const double tau = dg.tau, c2 = dg.c2, c3 = dg.c3;
   const double G = g * s.w;
-  // t_k = tau phi_k(z); p1c2 = tau phi_1(c2 z), p1c3 = tau phi_1(c3 z), p2c3 = tau phi_2(c3 z)
-  double t1, t2, t3, p1c2, p1c3, p2c3;
+  // t_k = tau phi_k(z); a21 = tau a_21, a31 = tau a_31, a32 = tau a_32
+  double t1, t2, t3, a21, a31, a32;
   if (s.lam == 0.0) {  // zero mode of a periodic grid: phi_k(0) = 1/k!
-    t1 = tau;
-    t2 = 0.5 * tau;
-    t3 = tau / 6.0;
-    p1c2 = p1c3 = tau;
-    p2c3 = 0.5 * tau;
+    t1 = k.tau;
+    t2 = 0.5 * k.tau;
+    t3 = k.tau / 6.0;
+    a21 = k.c2 * k.tau;
+    a32 = k.ka * 0.5 * k.tau;
+    a31 = k.c3 * k.tau - a32;
   } else {
-    const double rL = 1.0 / (dg.D * s.lam);
+    const double rL = rcp64(k.D * s.lam);
+    const double rL2 = rL * rL;
     t1 = -s.M * rL;
-    t2 = s.Q * rL * rL / tau;
-    t3 = -s.R * rL * rL * rL / (tau * tau);
-    p1c2 = -s.Mc * rL / c2;
-    p1c3 = -s.Mc3 * rL / c3;
-    p2c3 = s.Qc3 * rL * rL / (c3 * c3 * tau);
+    t2 = s.Q * rL2 * k.itau;
+    t3 = -s.R * rL2 * rL * k.itau2;
+    // c2 tau phi_1(c2 z) = -Mc rL;  c3 tau phi_1(c3 z) = -Mc3 rL;  tau phi_2(c3 z) = Qc3 rL^2 / (c3^2 tau)
+    a21 = -s.Mc * rL;
+    a32 = k.ka * s.Qc3 * rL2 * k.ic3sq_tau;
+    a31 = -s.Mc3 * rL - a32;
   }
   if (MODE == COL_S3_1) {
-    *out = h + s.Mc * h + c2 * p1c2 * G;
-    *nx = h + s.Mc3 * h + (c3 * p1c3 - c3 * c3 / c2 * p2c3) * G;
-    *nh = h + s.M * h + (2.0 * t3 - (c2 + c3) * t2 + c2 * c3 * t1) / (c2 * c3) * G;
+    *out = h + s.Mc * h + a21 * G;
+    *nx = h + s.Mc3 * h + a31 * G;
+    *nh = h + s.M * h + (2.0 * t3 - (k.c2 + k.c3) * t2 + k.c2 * k.c3 * t1) * k.kb1 * G;
   } else if (MODE == COL_S3_2) {
-    *out = x + c3 * c3 / c2 * p2c3 * G;
-    *nh = h + (2.0 * t3 - c3 * t2) / (c2 * (c2 - c3)) * G;
+    *out = x + a32 * G;
+    *nh = h + (2.0 * t3 - k.c3 * t2) * k.kb2 * G;
   } else {
-    *out = *nh = h + (2.0 * t3 - c2 * t2) / (c3 * (c3 - c2)) * G;
+    *out = *nh = h + (2.0 * t3 - k.c2 * t2) * k.kb3 * G;
   }
 }
 
@@ -322,11 +357,8 @@ __device__ __forceinline__ double ex52_wave(double x, double t, double eps, doub
 // to the reaction value.  Per axis the 1D entries over h are 2/3 (same node) and
 // 1/6 (neighbour) for the mass, 2/h^2 and -1/h^2 for the stiffness.  Nonzero
 // only on the shell of nodes next to the boundary.
-__device__ __forceinline__ double ex52_boundary_load(const Forcing& F, int ix, int iy, int iz) {
+__device__ __forceinline__ double ex52_shell_load(const Forcing& F, int ix, int iy, int iz) {
   const int idx[3] = {ix + 1, iy + 1, iz + 1};  // all-node indices
-  const bool shell = idx[0] == 1 || idx[0] == F.n[0] || (F.d > 1 && (idx[1] == 1 || idx[1] == F.n[1])) ||
-                     (F.d > 2 && (idx[2] == 1 || idx[2] == F.n[2]));
-  if (!shell) return 0.0;
   double acc = 0.0;
   const int oz0 = F.d > 2 ? -1 : 0, oz1 = F.d > 2 ? 1 : 0;
   const int oy0 = F.d > 1 ? -1 : 0, oy1 = F.d > 1 ? 1 : 0;
@@ -357,6 +389,12 @@ __device__ __forceinline__ double ex52_boundary_load(const Forcing& F, int ix, i
   return acc;
 }
 
+__device__ __forceinline__ double ex52_boundary_load(const Forcing& F, int ix, int iy, int iz) {
+  const bool shell = ix == 0 || ix == F.n[0] - 1 || (F.d > 1 && (iy == 0 || iy == F.n[1] - 1)) ||
+                     (F.d > 2 && (iz == 0 || iz == F.n[2] - 1));
+  return shell ? ex52_shell_load(F, ix, iy, iz) : 0.0;
+}
+
 // Per-instance data of a batched launch (instances of one size class share
 // geometry and launch shape; blockIdx.y (row passes) or blockIdx.z (column
 // passes) selects the instance).  A single grid launches with a null table.
@@ -376,7 +414,10 @@ struct ColInst {
   double D;
 };
 
-template <typename T>
+// EX52 = false leaves out the traveling wave's boundary code (its neighbour
+// loop raises the register demand of the specialised passes, which therefore
+// do not take that kind).
+template <typename T, bool EX52 = true>
 __device__ __forceinline__ T reaction(const Forcing& F, T u, int ix, int iy, int iz) {
   switch (F.kind) {
     case FK_AC:
@@ -390,8 +431,12 @@ __device__ __forceinline__ T reaction(const Forcing& F, T u, int ix, int iy, int
     case FK_FH:  // Example 5.3: (theta/2) ln((1 - u)/(1 + u)) + theta_c u, theta = c0, theta_c = c1
       return T(0.5) * T(F.c0) * log((T(1) - u) / (T(1) + u)) + T(F.c1) * u;
     case FK_EX52: {  // Example 5.2: (u - u^3) / eps^2, eps = c0, plus the traveling-wave boundary data
-      const double ud = double(u);
-      return T((ud - ud * ud * ud) / (F.c0 * F.c0) + ex52_boundary_load(F, ix, iy, iz));
+      if constexpr (EX52) {
+        const double ud = double(u);
+        return T((ud - ud * ud * ud) / (F.c0 * F.c0) + ex52_boundary_load(F, ix, iy, iz));
+      } else {
+        return T(0);
+      }
     }
     case FK_MMS: {
       double s = sinpi(F.a[0] + (ix + 1) * F.h[0]);
@@ -575,15 +620,23 @@ __device__ __forceinline__ Cx<T> mask_pad(Cx<T> v, int c, int ncols) {
   return v;
 }
 
-// One spectral point pair (columns col, col + 1 at the line position of ky,
-// kz) of a three-stage column pass: reads H (and X), writes H (and X), returns
-// the two values to inverse transform.
-template <typename T, int MODE>
-__device__ __forceinline__ void stage3_pair(const Diag& dg, int col, int ky, int kz, int64_t off, T* H, T ga, T gb,
-                                            int ncols, T* outv) {
-  T* X = static_cast<T*>(dg.X);
+// The separable tables of columns col, col + 1 combined with the non-line
+// axis (z for y lines, y for z lines) at index ko.
+__device__ __forceinline__ void sep3_pair(const Diag& dg, int col, bool last_is_z, int ko, Sep3* sxy) {
   const double tD = dg.tau * dg.D;
-  const Sep3 syz = sep3_combine(sep3_load(dg.ax[1], ky), sep3_load(dg.ax[2], kz), tD);
+  const Sep3 so = last_is_z ? sep3_load(dg.ax[1], ko) : sep3_load(dg.ax[2], 0);
+  sxy[0] = sep3_combine(sep3_load(dg.ax[0], col), so, tD);
+  sxy[1] = sep3_combine(sep3_load(dg.ax[0], col + 1), so, tD);
+}
+
+// One spectral point pair (columns col, col + 1; sxy from sep3_pair) at line
+// position m of a three-stage column pass: reads H (and X), writes H (and X),
+// returns the two values to inverse transform.
+template <typename T, int MODE>
+__device__ __forceinline__ void stage3_pair(const Diag& dg, const S3K& k, const Sep3* sxy, bool last_is_z, int m,
+                                            int col, int64_t off, T* H, T ga, T gb, int ncols, T* outv) {
+  T* X = static_cast<T*>(dg.X);
+  const Sep3 sl = sep3_load(last_is_z ? dg.ax[2] : dg.ax[1], m);
   const Cx<T> hv = *reinterpret_cast<const Cx<T>*>(H + off);
   Cx<T> xv{T(0), T(0)};
   if (MODE == COL_S3_2) xv = *reinterpret_cast<const Cx<T>*>(X + off);
@@ -591,9 +644,9 @@ __device__ __forceinline__ void stage3_pair(const Diag& dg, int col, int ky, int
   T newh[2], newx[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const Sep3 sp = sep3_combine(sep3_load(dg.ax[0], col + q), syz, tD);
+    const Sep3 sp = sep3_combine(sxy[q], sl, k.tau * k.D);
     double o, nh, nx = 0.0;
-    diag3_apply<MODE>(sp, dg, double(gin[q]), double(hin[q]), double(xin[q]), &o, &nh, &nx);
+    diag3_apply<MODE>(sp, k, double(gin[q]), double(hin[q]), double(xin[q]), &o, &nh, &nx);
     outv[q] = T(o);
     newh[q] = T(nh);
     newx[q] = T(nx);
@@ -660,8 +713,10 @@ __global__ void __launch_bounds__(256) col_pass(T* W, T* H, ColGeom g, const Cx<
       Cx<T>* line = lds + p * g.ls;
       const Cx<T> Z = line[m + 1];
       T outv[2];
-      stage3_pair<T, MODE>(dg, c0 + 2 * p, g.last_is_z ? outer : m, g.last_is_z ? m : 0,
-                           base + int64_t(m) * g.ld_line + 2 * p, H, -Z.im * scale, Z.re * scale, g.ncols, outv);
+      Sep3 sxy[2];
+      sep3_pair(dg, c0 + 2 * p, g.last_is_z, outer, sxy);
+      stage3_pair<T, MODE>(dg, s3k_make(dg), sxy, g.last_is_z, m, c0 + 2 * p, base + int64_t(m) * g.ld_line + 2 * p, H,
+                           -Z.im * scale, Z.re * scale, g.ncols, outv);
       put_odd(line, L, m + 1, outv[0], outv[1]);
       if (m == 0) {
         line[0] = Cx<T>{T(0), T(0)};
@@ -896,8 +951,10 @@ __global__ void __launch_bounds__(256) col_pass_per(T* W, T* H, ColGeom g, const
       Cx<T>* line = lds + p * g.ls;
       const Cx<T> gv = line[m];
       T outv[2];
-      stage3_pair<T, MODE>(dg, c0 + 2 * p, g.last_is_z ? outer : m, g.last_is_z ? m : 0,
-                           base + int64_t(m) * g.ld_line + 2 * p, H, gv.re, gv.im, g.ncols, outv);
+      Sep3 sxy[2];
+      sep3_pair(dg, c0 + 2 * p, g.last_is_z, outer, sxy);
+      stage3_pair<T, MODE>(dg, s3k_make(dg), sxy, g.last_is_z, m, c0 + 2 * p, base + int64_t(m) * g.ld_line + 2 * p, H,
+                           gv.re, gv.im, g.ncols, outv);
       line[m] = Cx<T>{outv[0], outv[1]};
     }
   } else
