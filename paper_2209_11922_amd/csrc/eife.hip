@@ -22,6 +22,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/eife.h"
@@ -547,11 +548,91 @@ void col_fast_launch(int var, int mode, int pitch, int outer, int count, hipStre
   }
 }
 
+// Periodic lines with wave-local kernels: N = L = 128, 256, 512 (single grids).
+inline bool per_fast_len(int N) { return N == 128 || N == 256 || N == 512; }
+
+template <typename T, int L>
+void row_per_launch(int mode, int nrows, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
+                    const Cx<T>* tw, const Forcing& F) {
+  constexpr int pb0 = row_pb<T, L>(0);
+  constexpr int pbs = std::max(1, pb0 / 4);
+  const bool few = (nrows + 2 * pb0 - 1) / (2 * pb0) < g_cus;
+  auto go = [&](auto pbc) {
+    constexpr int PB = decltype(pbc)::value;
+    constexpr int NT = PB * fast::FftShape<L>::LP;
+    dim3 grid((nrows + 2 * PB - 1) / (2 * PB));
+    if (mode == ROW_PHYS)
+      hipLaunchKernelGGL((fast::row_fast_per<T, L, PB, ROW_PHYS>), grid, dim3(NT), 0, s, src, dst, dst2, rg, tw, F);
+    else if (mode == ROW_FWD_USER)
+      hipLaunchKernelGGL((fast::row_fast_per<T, L, PB, ROW_FWD_USER>), grid, dim3(NT), 0, s, src, dst, dst2, rg, tw, F);
+    else
+      hipLaunchKernelGGL((fast::row_fast_per<T, L, PB, ROW_INV_USER>), grid, dim3(NT), 0, s, src, dst, dst2, rg, tw, F);
+  };
+  if (few)
+    go(std::integral_constant<int, pbs>());
+  else
+    go(std::integral_constant<int, pb0>());
+}
+
+template <typename T>
+bool try_row_fast_per(const eife_grid_s* g, int mode, int count, hipStream_t s, const T* src, T* dst, T* dst2,
+                      const RowGeom& rg, const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
+  if (g->transform != EIFE_TX_FFT || ri || count != 1 || !per_fast_len(g->N[0])) return false;
+  if (mode != ROW_PHYS && mode != ROW_FWD_USER && mode != ROW_INV_USER) return false;
+  switch (g->N[0]) {
+    case 128: row_per_launch<T, 128>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F); return true;
+    case 256: row_per_launch<T, 256>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F); return true;
+    case 512: row_per_launch<T, 512>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F); return true;
+  }
+  return false;
+}
+
+template <typename T, int L>
+void col_per_launch(int mode, int pitch, int outer, hipStream_t s, T* W, T* H, const ColGeom& cg, const Cx<T>* tw,
+                    const Diag& dg) {
+  constexpr int pb0 = col_pb<T, L>(0);
+  constexpr int pbs = std::max(1, pb0 / 8);
+  const bool few = (pitch / (2 * pb0)) * outer < g_cus;
+  auto go = [&](auto pbc) {
+    constexpr int PB = decltype(pbc)::value;
+    constexpr int PPW = col_ppw<T, L, PB>();
+    constexpr int NT = PB / PPW * fast::FftShape<L>::LP;
+    dim3 grid(pitch / (2 * PB), outer);
+    if (mode == COL_PLAIN)
+      hipLaunchKernelGGL((fast::col_fast_per<T, L, PB, PPW, COL_PLAIN>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+    else if (mode == COL_PLAIN_INV)
+      hipLaunchKernelGGL((fast::col_fast_per<T, L, PB, PPW, COL_PLAIN_INV>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+    else if (mode == COL_STAGE_A)
+      hipLaunchKernelGGL((fast::col_fast_per<T, L, PB, PPW, COL_STAGE_A>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+    else if (mode == COL_STAGE_B)
+      hipLaunchKernelGGL((fast::col_fast_per<T, L, PB, PPW, COL_STAGE_B>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+    else
+      hipLaunchKernelGGL((fast::col_fast_per<T, L, PB, PPW, COL_ETD1>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+  };
+  if (few)
+    go(std::integral_constant<int, pbs>());
+  else
+    go(std::integral_constant<int, pb0>());
+}
+
+template <typename T>
+bool try_col_fast_per(const eife_grid_s* g, int axis, int mode, int outer, int count, hipStream_t s, T* W, T* H,
+                      const ColGeom& cg, const Cx<T>* tw, const Diag& dg, const ColInst<T>* ci) {
+  if (g->transform != EIFE_TX_FFT || ci || count != 1 || !per_fast_len(g->N[axis]) || mode >= COL_S3_1) return false;
+  switch (g->N[axis]) {
+    case 128: col_per_launch<T, 128>(mode, g->pitch, outer, s, W, H, cg, tw, dg); return true;
+    case 256: col_per_launch<T, 256>(mode, g->pitch, outer, s, W, H, cg, tw, dg); return true;
+    case 512: col_per_launch<T, 512>(mode, g->pitch, outer, s, W, H, cg, tw, dg); return true;
+  }
+  return false;
+}
+
 template <typename T>
 bool try_row_fast(const eife_grid_s* g, int var, int mode, int count, hipStream_t s, const T* src, T* dst, T* dst2,
                   const RowGeom& rg, const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
+  if (g->per[0]) return try_row_fast_per<T>(g, mode, count, s, src, dst, dst2, rg, tw, F, ri);
   // the traveling wave's boundary code runs in the generic row pass only
-  if (g->transform != EIFE_TX_FFT || g->per[0] || !fast_len<T>(g->N[0]) || F.kind == FK_EX52) return false;
+  if (g->transform != EIFE_TX_FFT || !fast_len<T>(g->N[0]) || F.kind == FK_EX52) return false;
   switch (g->N[0]) {
     case 64: row_fast_launch<T, 128>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
     case 128: row_fast_launch<T, 256>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
@@ -571,7 +652,8 @@ bool try_row_fast(const eife_grid_s* g, int var, int mode, int count, hipStream_
 template <typename T>
 bool try_col_fast(const eife_grid_s* g, int var, int axis, int mode, int outer, int count, hipStream_t s, T* W, T* H,
                   const ColGeom& cg, const Cx<T>* tw, const Diag& dg, const ColInst<T>* ci) {
-  if (g->transform != EIFE_TX_FFT || g->per[axis] || !fast_len<T>(g->N[axis])) return false;
+  if (g->per[axis]) return try_col_fast_per<T>(g, axis, mode, outer, count, s, W, H, cg, tw, dg, ci);
+  if (g->transform != EIFE_TX_FFT || !fast_len<T>(g->N[axis])) return false;
   switch (g->N[axis]) {
     case 64: col_fast_launch<T, 128>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
     case 128: col_fast_launch<T, 256>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;

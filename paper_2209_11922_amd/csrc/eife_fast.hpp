@@ -871,5 +871,275 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Periodic lines of N = L points (L a power of two, 128 ... 1024): the real
+// orthonormal Fourier transform of two packed lines through one complex FFT
+// of length L, wave-local as above.  Forward: Z = FFT(a + ib), then position r
+// of the half-complex order combines Z_r and Z_{L-r} (per_pos below); inverse:
+// the FFT input at m is conj(Z^_m), built from the coefficients at m and L - m,
+// and the nodal values are (X.re, -X.im) / sqrt(L).  Both pair reads go
+// through the pair's LDS region.
+
+// Coefficient pair at position m from the FFT outputs Z (line[k] = Z_k).
+template <typename T, int L>
+__device__ __forceinline__ Cx<T> per_pos(const Cx<T>* line, int m) {
+  const T s1 = T(1.0 / sqrt(double(L)));
+  const T s2 = T(1.0 / sqrt(2.0 * double(L)));
+  if (m == 0 || 2 * m == L) {
+    const Cx<T> z = line[m];
+    return Cx<T>{z.re * s1, z.im * s1};
+  }
+  const Cx<T> zm = line[m], zo = line[L - m];
+  if (2 * m < L) return Cx<T>{(zm.re + zo.re) * s2, (zm.im + zo.im) * s2};
+  return Cx<T>{(zm.im - zo.im) * s2, (zo.re - zm.re) * s2};
+}
+
+// FFT input at m of the inverse transform: conj(Z^_m) from the coefficient
+// pairs c at positions m and L - m.
+template <typename T, int L>
+__device__ __forceinline__ Cx<T> per_inv_input(const Cx<T>* c, int m) {
+  const T r2 = T(0.70710678118654752440);
+  if (m == 0 || 2 * m == L) {
+    const Cx<T> v = c[m];
+    return Cx<T>{v.re, -v.im};
+  }
+  if (2 * m < L) {
+    const Cx<T> ck = c[m], cm = c[L - m];
+    return Cx<T>{(ck.re + cm.im) * r2, (cm.re - ck.im) * r2};
+  }
+  const Cx<T> ck = c[L - m], cm = c[m];
+  return Cx<T>{(ck.re - cm.im) * r2, -(ck.im + cm.re) * r2};
+}
+
+// Forward (INV = false: FFT of node[0 .. L-1]) or inverse (INV = true: FFT of
+// the conj(Z^) built from the coefficient line node) transform of one pair;
+// the region may overlay node (all inputs are read before it is written).
+template <typename T, int L, bool INV>
+__device__ __forceinline__ void per_fft(Cx<T> (&v)[FftShape<L>::E], const Cx<T>* node, Cx<T>* buf, int lane,
+                                        const LaneTw<T, L>& tw) {
+  constexpr int E = FftShape<L>::E;
+  constexpr int LP = FftShape<L>::LP;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int m = lane + LP * q;
+    v[q] = INV ? per_inv_input<T, L>(node, m) : node[m];
+  }
+  wave_sync();
+  fft_head<T, L>(v, buf, lane);
+  wave_sync();
+  fft_tail<T, L>(v, buf, lane, tw);
+  wave_sync();
+}
+
+// Visit every output k in [0, L) held by this lane: f(k, Z_k).
+template <typename T, int L, typename F>
+__device__ __forceinline__ void for_all_outputs(const Cx<T> (&v)[FftShape<L>::E], int lane, F f) {
+  constexpr int E = FftShape<L>::E;
+  constexpr int LP = FftShape<L>::LP;
+  constexpr int R2 = FftShape<L>::R2;
+  constexpr int NB = E / R2;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+#pragma unroll
+    for (int q = 0; q < R2; ++q) f(lane + LP * b + q * (L / R2), v[b * R2 + q]);
+  }
+}
+
+// Row pass of periodic x lines: ROW_FWD_USER, ROW_INV_USER or ROW_PHYS (as
+// row_fast; the reaction takes no position, periodic grids have none).
+template <typename T, int L, int PB, int MODE>
+__global__ void __launch_bounds__((PB * FftShape<L>::LP), (MinWaves<T, L>::value)) row_fast_per(
+    const T* src, T* dst, T* dst2, RowGeom g, const Cx<T>* __restrict__ tw, Forcing F) {
+  constexpr int LP = FftShape<L>::LP;
+  constexpr int BUF = FftShape<L>::BUF;
+  constexpr int RIT = L / LP;
+  __shared__ Cx<T> lds[PB * BUF];
+  const int tid = threadIdx.x;
+  const int p = tid / LP;
+  const int lane = tid - p * LP;
+  const int ra = blockIdx.x * 2 * PB + 2 * p, rb = ra + 1;
+  const bool hasa = ra < g.nrows, hasb = rb < g.nrows;
+  const T s1 = T(1.0 / sqrt(double(L)));
+  LaneTw<T, L> twl;
+  twl.load(tw, lane);
+  Cx<T>* my = lds + p * BUF;
+  {
+    const T* sa = src + int64_t(ra) * g.ld_src + lane;
+    const T* sb = src + int64_t(rb) * g.ld_src + lane;
+    T va[RIT], vb[RIT];
+#pragma unroll
+    for (int t = 0; t < RIT; ++t) {
+      va[t] = hasa ? sa[LP * t] : T(0);
+      vb[t] = hasb ? sb[LP * t] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < RIT; ++t) my[lane + LP * t] = Cx<T>{va[t], vb[t]};
+  }
+  wave_sync();
+  Cx<T> v[FftShape<L>::E];
+  if (MODE != ROW_FWD_USER) {
+    per_fft<T, L, true>(v, my, my, lane, twl);
+    for_all_outputs<T, L>(v, lane, [&](int k, Cx<T> X) {
+      const T ua = X.re * s1, ub = -X.im * s1;
+      if (MODE == ROW_INV_USER)
+        my[k] = Cx<T>{ua, ub};
+      else
+        my[k] = Cx<T>{reaction_k<T, RK_GENERIC>(F, ua, k, 0, 0), reaction_k<T, RK_GENERIC>(F, ub, k, 0, 0)};
+    });
+    wave_sync();
+  }
+  if (MODE != ROW_INV_USER) {
+    per_fft<T, L, false>(v, my, my, lane, twl);
+    for_all_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k] = Z; });
+    wave_sync();
+  }
+  Cx<T> outv[RIT];
+#pragma unroll
+  for (int t = 0; t < RIT; ++t) outv[t] = MODE == ROW_INV_USER ? my[lane + LP * t] : per_pos<T, L>(my, lane + LP * t);
+  T* da = dst + int64_t(ra) * g.ld_dst + lane;
+  T* db = dst + int64_t(rb) * g.ld_dst + lane;
+#pragma unroll
+  for (int t = 0; t < RIT; ++t) {
+    if (hasa) da[LP * t] = outv[t].re;
+    if (hasb) db[LP * t] = outv[t].im;
+  }
+  if (MODE == ROW_FWD_USER) {
+    T* ha = dst2 + int64_t(ra) * g.ld_dst + lane;
+    T* hb = dst2 + int64_t(rb) * g.ld_dst + lane;
+#pragma unroll
+    for (int t = 0; t < RIT; ++t) {
+      if (hasa) ha[LP * t] = outv[t].re;
+      if (hasb) hb[LP * t] = outv[t].im;
+    }
+  }
+}
+
+// Column pass of periodic lines (one tile of C = 2 PB columns per block, as
+// col_fast): COL_PLAIN (forward), COL_PLAIN_INV (inverse) or a stage
+// (forward, the diagonal stage at every position, inverse).
+// The stage variants keep a tile column of results in registers between the
+// two transforms: 2 waves per SIMD.
+template <typename T, int L, int MODE>
+struct PerMinWaves {
+  static constexpr int value = (MODE == COL_PLAIN || MODE == COL_PLAIN_INV) ? MinWaves<T, L>::value : 2;
+};
+
+template <typename T, int L, int PB, int PPW, int MODE>
+__global__ void __launch_bounds__((PB / PPW * FftShape<L>::LP), (PerMinWaves<T, L, MODE>::value)) col_fast_per(
+    T* W, T* H, ColGeom g, const Cx<T>* tw, Diag dg) {
+  constexpr int LP = FftShape<L>::LP;
+  constexpr int BUF = FftShape<L>::BUF;
+  constexpr int SLOTS = PB / PPW;
+  constexpr int NT = SLOTS * LP;
+  constexpr int MS = NT / PB;
+  constexpr int CIT = (L + MS - 1) / MS;
+  __shared__ Cx<T> lds[PB * BUF];
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * 2 * PB;
+  const int outer = blockIdx.y;
+  const int64_t base = int64_t(outer) * g.ld_outer + c0;
+  const T s1 = T(1.0 / sqrt(double(L)));
+  const int slot = tid / LP;
+  const int lane = tid - slot * LP;
+  const int tq = tid % PB;
+  const int m0 = tid / PB;
+  const int ldl = int(g.ld_line);
+  Cx<T>* ltile = lds + tq * BUF;  // this thread's column pair, row m at ltile[m]
+  {
+    const Cx<T>* gsrc = reinterpret_cast<const Cx<T>*>(W + base + m0 * ldl + 2 * tq);
+    Cx<T> tmp[CIT];
+#pragma unroll
+    for (int it = 0; it < CIT; ++it)
+      if (m0 + MS * it < L) tmp[it] = gsrc[(MS * it * ldl) / 2];
+#pragma unroll
+    for (int it = 0; it < CIT; ++it)
+      if (m0 + MS * it < L) ltile[m0 + MS * it] = mask_pad(tmp[it], c0 + 2 * tq, g.ncols);
+  }
+  __syncthreads();
+  LaneTw<T, L> twl;
+  twl.load(tw, lane);
+  Cx<T> v[FftShape<L>::E];
+  if (MODE == COL_PLAIN_INV) {
+#pragma unroll 1
+    for (int r = 0; r < PPW; ++r) {
+      Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
+      per_fft<T, L, true>(v, my, my, lane, twl);
+      for_all_outputs<T, L>(v, lane, [&](int k, Cx<T> X) { my[k] = Cx<T>{X.re * s1, -X.im * s1}; });
+    }
+  } else {
+#pragma unroll 1
+    for (int r = 0; r < PPW; ++r) {
+      Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
+      per_fft<T, L, false>(v, my, my, lane, twl);
+      for_all_outputs<T, L>(v, lane, [&](int k, Cx<T> Z) { my[k] = Z; });
+    }
+  }
+  __syncthreads();
+  if (MODE == COL_PLAIN || MODE == COL_PLAIN_INV) {
+    Cx<T>* gdst = reinterpret_cast<Cx<T>*>(W + base + m0 * ldl + 2 * tq);
+#pragma unroll
+    for (int it = 0; it < CIT; ++it) {
+      const int m = m0 + MS * it;
+      if (m < L) {
+        const Cx<T> c = MODE == COL_PLAIN ? per_pos<T, L>(ltile, m) : ltile[m];
+        gdst[(MS * it * ldl) / 2] = mask_pad(c, c0 + 2 * tq, g.ncols);
+      }
+    }
+    return;
+  }
+  // diagonal stage: thread -> (row m, pair tq); the coefficient pairs are read
+  // from the FFT outputs before any is overwritten
+  const double tau = dg.tau, c2 = dg.c2, D = dg.D;
+  const int kx0 = c0 + 2 * tq;
+  Sep sxy[2];
+  {
+    const Sep so = g.last_is_z ? sep_load(dg.ax[1], outer) : sep_load(dg.ax[2], 0);
+    sxy[0] = sep_combine(sep_load(dg.ax[0], kx0), so);
+    sxy[1] = sep_combine(sep_load(dg.ax[0], kx0 + 1), so);
+  }
+  const AxisTab line_tab = g.last_is_z ? dg.ax[2] : dg.ax[1];
+  Cx<T>* hrow = reinterpret_cast<Cx<T>*>(H + base + m0 * ldl + 2 * tq);
+  Cx<T> res[CIT];
+#pragma unroll
+  for (int it = 0; it < CIT; ++it) {
+    const int m = m0 + MS * it;
+    if (m < L) {
+      const Cx<T> gv = per_pos<T, L>(ltile, m);
+      const Cx<T> hv = hrow[(MS * it * ldl) / 2];
+      const Sep sl = sep_load(line_tab, m);
+      double o0, o1, n0, n1;
+      if (MODE == COL_ETD1) {
+        diag_apply<DIAG_ETD1>(sep_combine(sxy[0], sl), D, tau, c2, double(gv.re), double(hv.re), &o0, &n0);
+        diag_apply<DIAG_ETD1>(sep_combine(sxy[1], sl), D, tau, c2, double(gv.im), double(hv.im), &o1, &n1);
+      } else if (MODE == COL_STAGE_A) {
+        diag_apply<DIAG_A>(sep_combine(sxy[0], sl), D, tau, c2, double(gv.re), double(hv.re), &o0, &n0);
+        diag_apply<DIAG_A>(sep_combine(sxy[1], sl), D, tau, c2, double(gv.im), double(hv.im), &o1, &n1);
+      } else {
+        diag_apply<DIAG_B>(sep_combine(sxy[0], sl), D, tau, c2, double(gv.re), double(hv.re), &o0, &n0);
+        diag_apply<DIAG_B>(sep_combine(sxy[1], sl), D, tau, c2, double(gv.im), double(hv.im), &o1, &n1);
+      }
+      hrow[(MS * it * ldl) / 2] = mask_pad(Cx<T>{T(n0), T(n1)}, kx0, g.ncols);
+      res[it] = Cx<T>{T(o0), T(o1)};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < CIT; ++it)
+    if (m0 + MS * it < L) ltile[m0 + MS * it] = res[it];
+  __syncthreads();
+#pragma unroll 1
+  for (int r = 0; r < PPW; ++r) {
+    Cx<T>* my = lds + (slot + SLOTS * r) * BUF;
+    per_fft<T, L, true>(v, my, my, lane, twl);
+    for_all_outputs<T, L>(v, lane, [&](int k, Cx<T> X) { my[k] = Cx<T>{X.re * s1, -X.im * s1}; });
+  }
+  __syncthreads();
+  Cx<T>* gdst = reinterpret_cast<Cx<T>*>(W + base + m0 * ldl + 2 * tq);
+#pragma unroll
+  for (int it = 0; it < CIT; ++it)
+    if (m0 + MS * it < L) gdst[(MS * it * ldl) / 2] = mask_pad(ltile[m0 + MS * it], kx0, g.ncols);
+}
+
 }  // namespace fast
 }  // namespace eife

@@ -64,6 +64,32 @@ def test_periodic_allen_cahn_matches_oracle(N, stages, dtype):
     assert err <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("stages", [2, 1])
+@pytest.mark.parametrize("N", [[128, 256], [512, 128], [256, 12, 128]], ids=["2d", "2d-512", "3d-mixed"])
+def test_periodic_wave_local_passes_match_oracle(N, stages, dtype):
+    """Lines of 128, 256 and 512 points run on the wave-local periodic kernels (the others on
+    the generic ones); both launch widths of the row and column passes occur here."""
+    eife = _eife()
+    u0 = np.random.default_rng(sum(N)).uniform(-0.9, 0.9, tuple(reversed(N)))
+    got = _gpu(N, 2.5e-3, u0, 0.02, 6, stages, eife.F_ALLEN_CAHN, dtype)
+    ref = _oracle(N, 2.5e-3, u0, problems.allen_cahn(), 0.02, 6, stages)
+    err = _rel(got, ref)
+    print(f"periodic wave-local {N} EIFE{stages} {dtype}: {err:.2e}")
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_periodic_wave_local_cube_flory_huggins(dtype):
+    """Example 5.3's reaction and parameters on 128^3 (the bench's grid), 10 steps."""
+    eife = _eife()
+    N = [128, 128, 128]
+    u0 = np.random.default_rng(53).uniform(-0.9, 0.9, (128, 128, 128))
+    got = _gpu(N, 1e-4, u0, 5 / 512, 10, 2, eife.F_FLORY_HUGGINS, dtype, forcing=(THETA, THETA_C))
+    ref = _oracle(N, 1e-4, u0, problems.flory_huggins(THETA, THETA_C), 5 / 512, 10, 2)
+    assert _rel(got, ref) <= TOL[dtype]
+
+
 def test_periodic_nodal_load_matches_oracle():
     eife = _eife()
     N = [24, 16]
