@@ -75,11 +75,11 @@ def test_time_dependent_forcing_and_variable_steps():
     assert _rel(got, ref) <= 1e-12
 
 
-def test_periodic_three_stages():
+@pytest.mark.parametrize("N", [[32, 36], [128, 256]], ids=["generic", "wave-local-rows"])
+def test_periodic_three_stages(N):
     eife = _eife()
-    N = [32, 36]
     h = [1.0 / n for n in N]
-    u0 = np.random.default_rng(4).uniform(-0.9, 0.9, (36, 32))
+    u0 = np.random.default_rng(4).uniform(-0.9, 0.9, tuple(reversed(N)))
     got = _run(N, 1e-3, u0, 0.02, 6, (0.0, 1 / 3, 2 / 3), eife.F_ALLEN_CAHN, "f64", bc=eife.BC_PERIODIC)
     ref = erk.run(spectral.make_basis("C", N, h, 1e-3, bc="periodic"), u0, problems.allen_cahn(), 0.02, 6,
                   [0.0, 1 / 3, 2 / 3])
