@@ -89,8 +89,10 @@ enum eife_load {
  * interior nodes of each axis, the sine basis of Section 4) or
  * EIFE_BC_PERIODIC (the variant at the end of Section 4: unknowns at the
  * N[a] nodes j h[a], j = 0 .. N[a] - 1, of each axis, circulant matrices
- * diagonalised by the real orthonormal Fourier basis; generic passes only,
- * no split-BF16 transform, no batches, no EIFE_F_MMS_U2 / EIFE_F_EX51); dtype is
+ * diagonalised by the real orthonormal Fourier basis; wave-local passes for
+ * lines of 128, 256 and 512 points, generic passes otherwise; no split-BF16
+ * transform, no batches, no EIFE_F_MMS_U2 / EIFE_F_EX51 /
+ * EIFE_F_TRAVELING_WAVE); dtype is
  * EIFE_F32 or EIFE_F64, the precision of nodal arrays and transforms
  * (eigenvalue and phi factors are always formed in double).  The origin
  * defaults to 0, c2 to 1/2 and the load to EIFE_LOAD_LUMPED.  On success

@@ -1027,7 +1027,17 @@ int ensure_step_tables(eife_grid_s* g) {
     g->vhost = nullptr;
     return fail(EIFE_ENOMEM, "variable-step staging allocation failed");
   }
-  for (int b = 0; b < 2; ++b) HIP_TRY(hipEventCreateWithFlags(&g->vev[b], hipEventDisableTiming));
+  for (int b = 0; b < 2; ++b) {
+    if (hipEventCreateWithFlags(&g->vev[b], hipEventDisableTiming) != hipSuccess) {
+      for (int c = 0; c < b; ++c) hipEventDestroy(g->vev[c]);
+      g->vev[0] = g->vev[1] = nullptr;
+      hipFree(g->vtab);
+      hipHostFree(g->vhost);
+      g->vtab = nullptr;
+      g->vhost = nullptr;
+      return fail(EIFE_EHIP, "cannot create the variable-step events");
+    }
+  }
   g->vchunk = chunk;
   return EIFE_OK;
 }
