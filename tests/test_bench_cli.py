@@ -12,3 +12,11 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
     assert not r.stdout.strip().startswith("{")  # no JSON result line
+
+
+def test_every_workload_is_listed_in_the_help():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0
+    for w in ("cube", "batched", "manufactured", "ex53", "ex52", "variable", "three"):
+        assert w in r.stdout
