@@ -97,6 +97,25 @@ def cpu_baseline(u0, N, h, D, budget_s=15.0, max_steps=20):
                       f"(scipy.fft.dstn type-I, workers={cores}), {dt:.2f} s"}
 
 
+def reduction_rate(torch, g, u, ndof, calls=10):
+    """The FP64 norm and energy reduction (eife_norms) on the benchmark grid against a second
+    array: wall time per call (it returns the four values to the host) and the algorithmic
+    rate, two FP32 arrays read once."""
+    ref = torch.zeros_like(u)
+    g.norms(u, ref)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        vals = g.norms(u, ref)
+    dt = (time.perf_counter() - t0) / calls
+    gbs = 2 * 4 * ndof / dt / 1e9
+    log(f"bench: eife_norms {dt * 1e6:.1f} us per call (host round trip included), {gbs:.1f} GB/s algorithmic "
+        f"({gbs / HBM_PEAK_GBS * 100:.1f}% of HBM peak)")
+    del ref
+    return {"us_per_call": round(dt * 1e6, 1), "alg_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_per_call": 2 * 4 * ndof, "values": list(vals)}
+
+
 def accuracy_vs_f64(torch, eife, u0, N, h, D, steps):
     """Relative max-norm error of the benchmark problem after `steps` EIFE2 steps for the FP32
     sine-transform path and the split-BF16 matrix-core path, against the FP64 sine-transform
@@ -666,6 +685,7 @@ def main():
                         "frac": round(tfs / BF16_PEAK_TFS, 4), "flops_per_launch": flops}
         log(f"  dominant pass {dom[1]}: {tfs:.1f} TFLOP/s BF16 ({tfs / BF16_PEAK_TFS * 100:.1f}% of dense peak)")
 
+    red = reduction_rate(torch, g, u, ndof)
     g.close()
     del u
     acc = accuracy_vs_f64(torch, eife, u0, N, h, D, args.steps)
@@ -686,7 +706,7 @@ def main():
                                   "u0 uniform[-0.9,0.9] seed 0, EIFE2 c2=1/2 tau=0.005, "
                                   + ("split-BF16 matrix-core sine transforms" if gemm else "FP32 sine-transform path"),
                       "dofs": ndof, "tau": TAU, "scheme": "EIFE2", "transform": args.transform},
-           "roofline": roof, "cpu_baseline": cpu, "accuracy": acc, "corrector": corr}
+           "roofline": roof, "cpu_baseline": cpu, "accuracy": acc, "corrector": corr, "reductions": red}
     print(json.dumps(out), flush=True)
 
 

@@ -54,7 +54,7 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr int kThreads = 256;
 constexpr size_t kLdsBudget = 80 * 1024;  // per block, two blocks per CU fit in 160 KB
-constexpr int kNormBlocksMax = 1024;
+constexpr int kNormBlocksMax = 8192;
 constexpr int kTabArrays = 8;  // lam, w, M, Q, Mc, R, Mc3, Qc3 per axis
 constexpr int kPipeBlocksPerCu = 4;  // resident blocks of the pipelined column pass (LDS permitting)
 constexpr int kStagePipeMinTiles = 2;  // tiles per resident block from which the stage pass is pipelined
@@ -1148,10 +1148,28 @@ template <typename T>
 int run_norms(eife_grid_s* g, const void* u, const void* uref, hipStream_t s, int pot = NORM_POT_DOUBLE_WELL) {
   const NormGeom ng = make_norm_geom(g, pot);
   const int64_t total = int64_t(g->n[0]) * g->n[1] * g->n[2];
-  int nb = int(std::min<int64_t>(kNormBlocksMax, (total + kNormThreads - 1) / kNormThreads));
-  nb = std::max(nb, 1);
-  hipLaunchKernelGGL((norm_partial<T>), dim3(nb), dim3(kNormThreads), 0, s, static_cast<const T*>(u),
-                     static_cast<const T*>(uref), ng, g->partials);
+  const int64_t tiles = int64_t((g->n[0] + kNtX - 1) / kNtX) * ((g->n[1] + kNtY - 1) / kNtY);
+  int nb;
+  if (g->d == 3 && tiles <= kNormBlocksMax / 2) {
+    // 3D: tiles of (x, y) columns marching over chunks of z planes: about 2048
+    // blocks, at least 8 planes per chunk (each chunk also loads the plane
+    // before and after it)
+    const int nz = g->n[2];
+    int64_t want = std::min<int64_t>(kNormBlocksMax / tiles, std::max<int64_t>(1, 2048 / tiles));
+    want = std::min<int64_t>(want, std::max(1, nz / 8));
+    int nzc = int(std::max<int64_t>(1, std::min<int64_t>(nz, want)));
+    const int zc = (nz + nzc - 1) / nzc;
+    nzc = (nz + zc - 1) / zc;
+    nb = int(tiles) * nzc;
+    const dim3 grid(unsigned((g->n[0] + kNtX - 1) / kNtX), unsigned((g->n[1] + kNtY - 1) / kNtY), unsigned(nzc));
+    hipLaunchKernelGGL((norm_tile<T>), grid, dim3(kNormThreads), 0, s, static_cast<const T*>(u),
+                       static_cast<const T*>(uref), ng, zc, g->partials);
+  } else {
+    nb = int(std::min<int64_t>(kNormBlocksMax, (total + kNormThreads - 1) / kNormThreads));
+    nb = std::max(nb, 1);
+    hipLaunchKernelGGL((norm_partial<T>), dim3(nb), dim3(kNormThreads), 0, s, static_cast<const T*>(u),
+                       static_cast<const T*>(uref), ng, g->partials);
+  }
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(norm_final, dim3(1), dim3(kNormFinalThreads), 0, s, g->partials, nb, g->out5);
   HIP_TRY(hipGetLastError());

@@ -1100,6 +1100,132 @@ __global__ void __launch_bounds__(kNormThreads) norm_partial(const T* __restrict
   if (threadIdx.x < kNormAcc) partials[blockIdx.x * kNormAcc + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// The same five sums with the tensor structure used directly: M = A_z (x) A_y (x)
+// A_x and K_1 = B_z (x) A_y (x) A_x + A_z (x) (A_y (x) B_x + B_y (x) A_x).  A block
+// owns a tile of kNtX x kNtY (x, y) columns and marches over a chunk of z
+// planes.  Per plane the tile with a one-node halo is staged in LDS (e and u,
+// zero outside a Dirichlet boundary, wrapped on periodic axes) and every
+// thread forms the in-plane 9-point sums wA = (A_y (x) A_x) v and wB = (A_y (x)
+// B_x + B_y (x) A_x) v for v = e and v = u; the z coupling comes from the
+// previous and next planes' sums, kept in registers:
+//   (M e)_z = ad wA_z + ao (wA_{z-1} + wA_{z+1}),
+//   (K_1 e)_z = bd wA_z + bo (wA_{z-1} + wA_{z+1}) + ad wB_z + ao (wB_{z-1} + wB_{z+1}).
+// Global reads: one per node and array plus the halo.  Block partials as
+// norm_partial.
+constexpr int kNtX = 64, kNtY = 4;  // kNtX * kNtY = kNormThreads
+
+struct PlaneSums {
+  double eA, eB, uA, uB;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kNormThreads) norm_tile(const T* __restrict__ u, const T* __restrict__ ur,
+                                                          NormGeom g, int zc, double* __restrict__ partials) {
+  constexpr int HX = kNtX + 2, HY = kNtY + 2;
+  constexpr int G = 4;  // planes staged per barrier pair (their loads overlap)
+  __shared__ double te[G][HY][HX], tu[G][HY][HX];
+  __shared__ double red[kNormAcc][kNormThreads];
+  double acc[kNormAcc] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int tx = threadIdx.x % kNtX, ty = threadIdx.x / kNtX;
+  const int x0 = blockIdx.x * kNtX, y0 = blockIdx.y * kNtY;
+  const int ix = x0 + tx, iy = y0 + ty;
+  const bool own = ix < g.n[0] && iy < g.n[1];
+  const int nz = g.n[2];
+  const int z0 = blockIdx.z * zc;
+  const int z1 = min(nz, z0 + zc);
+  const int64_t sy = g.n[0], sz = int64_t(g.n[0]) * g.n[1];
+  // planes p = 0 .. np-1 are z = z0 - 1 .. z1; a z axis of one node couples to
+  // nothing, so there the planes before and after the chunk stay zero
+  const int np = z0 < nz ? z1 - z0 + 2 : 0;
+  PlaneSums prev{0.0, 0.0, 0.0, 0.0}, cur{0.0, 0.0, 0.0, 0.0};
+  for (int pg = 0; pg < np; pg += G) {
+    // stage planes pg .. pg+G-1 (wrapped on a periodic z axis; zero outside)
+    for (int k = threadIdx.x; k < G * HX * HY; k += kNormThreads) {
+      const int gp = k / (HX * HY), r = k - gp * (HX * HY);
+      const int hx = r % HX, hy = r / HX;
+      const int p = pg + gp;
+      int z = z0 - 1 + p;
+      if (g.per[2]) z = (z + nz) % nz;
+      const bool zin = p < np && z >= 0 && z < nz && (nz > 1 || (p >= 1 && p <= np - 2));
+      int jx = x0 + hx - 1, jy = y0 + hy - 1;
+      if (g.per[0]) jx = (jx + g.n[0]) % g.n[0];
+      if (g.per[1]) jy = (jy + g.n[1]) % g.n[1];
+      double vu = 0.0, ve = 0.0;
+      if (zin && jx >= 0 && jx < g.n[0] && jy >= 0 && jy < g.n[1]) {
+        const int64_t j = jx + jy * sy + z * sz;
+        vu = double(u[j]);
+        ve = ur ? vu - double(ur[j]) : vu;
+      }
+      tu[gp][hy][hx] = vu;
+      te[gp][hy][hx] = ve;
+    }
+    __syncthreads();
+    for (int gp = 0; gp < G && pg + gp < np; ++gp) {
+      const int p = pg + gp;
+      PlaneSums next{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int oy = -1; oy <= 1; ++oy) {
+        const double ay = oy ? g.ao[1] : g.ad[1];
+        const double by = oy ? g.bo[1] : g.bd[1];
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          const double axv = ox ? g.ao[0] : g.ad[0];
+          const double bxv = ox ? g.bo[0] : g.bd[0];
+          const double wa = axv * ay, wb = bxv * ay + axv * by;
+          const double ej = te[gp][ty + 1 + oy][tx + 1 + ox], uj = tu[gp][ty + 1 + oy][tx + 1 + ox];
+          next.eA += wa * ej;
+          next.eB += wb * ej;
+          next.uA += wa * uj;
+          next.uB += wb * uj;
+        }
+      }
+      // plane p closes the window of the node at z = z0 - 2 + p (planes p - 2, p - 1, p)
+      if (p >= 2 && own) {
+        const int z = z0 - 2 + p;
+        const int64_t i = ix + iy * sy + z * sz;
+        const double ui = double(u[i]);
+        const double ei = ur ? ui - double(ur[i]) : ui;
+        const double Me = g.ad[2] * cur.eA + g.ao[2] * (prev.eA + next.eA);
+        const double Ke =
+            g.bd[2] * cur.eA + g.bo[2] * (prev.eA + next.eA) + g.ad[2] * cur.eB + g.ao[2] * (prev.eB + next.eB);
+        const double Ku =
+            g.bd[2] * cur.uA + g.bo[2] * (prev.uA + next.uA) + g.ad[2] * cur.uB + g.ao[2] * (prev.uB + next.uB);
+        acc[0] += ei * Me;
+        acc[1] += ei * Ke;
+        acc[2] = fmax(acc[2], fabs(ei));
+        acc[3] += ui * Ku;
+        if (g.pot == NORM_POT_FH) {
+          acc[4] += 0.5 * g.th * ((1.0 + ui) * log1p(ui) + (1.0 - ui) * log1p(-ui)) - 0.5 * g.thc * ui * ui;
+        } else {
+          const double q = ui * ui - 1.0;
+          acc[4] += 0.25 * q * q;
+        }
+      }
+      prev = cur;
+      cur = next;
+    }
+    __syncthreads();  // the planes are restaged by the next group
+  }
+#pragma unroll
+  for (int k = 0; k < kNormAcc; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < kNormAcc; ++k) {
+        if (k == 2)
+          red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+        else
+          red[k][threadIdx.x] += red[k][threadIdx.x + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kNormAcc)
+    partials[((int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * kNormAcc + threadIdx.x] =
+        red[threadIdx.x][0];
+}
+
 // Second level: 256 threads stride over the block partials, then a fixed-order
 // tree in LDS (deterministic); accumulator 2 is a maximum, the others sums.
 constexpr int kNormFinalThreads = 256;

@@ -200,6 +200,27 @@ def test_norms_match_oracle():
     assert l2u == pytest.approx(norms.discrete_norms(N, h, a)[0], rel=1e-12)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_norms_match_oracle_across_z_chunks(dtype):
+    """A 3D grid whose norm reduction marches over chunks of two z planes per thread."""
+    eife = _lib()
+    N = [256, 64, 24]
+    h = [1 / 256, 1 / 64, 1 / 24]
+    g = eife.Grid(N, h, 0.01, dtype)
+    a = seeded_inputs.uniform_field(5, N)
+    b = seeded_inputs.uniform_field(6, N)
+    ta = torch.tensor(a, dtype=g.torch_dtype, device="cuda")
+    tb = torch.tensor(b, dtype=g.torch_dtype, device="cuda")
+    a64, b64 = ta.double().cpu().numpy(), tb.double().cpu().numpy()
+    l2, h1, mx, en = g.norms(ta, tb)
+    g.close()
+    rl2, rh1, rmx = norms.discrete_norms(N, h, a64 - b64)
+    assert l2 == pytest.approx(rl2, rel=1e-12)
+    assert h1 == pytest.approx(rh1, rel=1e-12)
+    assert mx == pytest.approx(rmx, rel=1e-15)
+    assert en == pytest.approx(norms.allen_cahn_energy(N, h, 0.01, a64), rel=1e-12)
+
+
 def test_runs_on_a_side_stream():
     eife = _lib()
     N = [64, 64]

@@ -121,7 +121,7 @@ def test_constant_forcing_raises_the_mean_exactly():
     assert _rel(got, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("N", [[48, 36], [6, 12, 8]])
+@pytest.mark.parametrize("N", [[48, 36], [6, 12, 8], [512, 128, 8]])
 def test_periodic_norms_match_oracle(N):
     eife = _eife()
     h = [1.0 / n for n in N]
