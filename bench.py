@@ -321,6 +321,26 @@ def bench_ex53(args, torch, eife):
     return 0
 
 
+def cpu_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count()
+
+
+def cpu_oracle_rate(one_step, run_steps, ndof, budget_s, max_steps, cores, sample):
+    """Time the oracle: one untimed step, then as many steps as fit the budget (at most max_steps)."""
+    t0 = time.perf_counter()
+    state = one_step()
+    one = time.perf_counter() - t0
+    steps = int(max(1, min(max_steps, budget_s // max(one, 1e-3))))
+    t0 = time.perf_counter()
+    run_steps(state, steps)
+    dt = time.perf_counter() - t0
+    return {"value": ndof * steps / dt, "unit": "DoF-steps/s", "cores": cores, "kind": "oracle",
+            "sample": sample.format(steps=steps, dt=dt)}
+
+
 def cpu_baseline_ex53(u0, N, h, D, tau, theta, theta_c, budget_s=12.0, max_steps=20):
     """Time the FP64 CPU oracle (periodic tier C) on the first steps of Example 5.3."""
     from oracle import problems, spectral, stepper
@@ -424,13 +444,34 @@ def bench_ex52(args, torch, eife):
                 f"H1 {r['H1']:.4e} ({r.get('H1_rate', '-')}) {r['dof_steps_per_s']:.3e} DoF-steps/s")
     best = res["temporal_eife2"][-1]
     ndof = 1023 * 63 * 63
+    cpu = None
+    if not args.no_cpu:
+        from oracle import problems, spectral, stepper
+        cores = cpu_cores()
+        nx, ny = 512, 32
+        Ns, hs = [nx, ny, ny], [np.sqrt(2.0) / nx, 0.125 / ny, 0.125 / ny]
+        basis = spectral.SineBasis(Ns, hs, 1.0, workers=cores)
+        uw, uwt, _ = problems.traveling_wave_solution(eps)
+        x = hs[0] * np.arange(1, nx)
+        u0s = np.broadcast_to(uw(0.0, x), (ny - 1, ny - 1, nx - 1))
+        bd = (lambda t, Xb: uw(t, Xb[0]), lambda t, Xb: uwt(t, Xb[0]))
+        tau = T / 1024
+        cpu = cpu_oracle_rate(
+            lambda: stepper.run(basis, u0s, problems.traveling_wave(eps), tau, 1, 2, boundary=bd),
+            lambda U, k: stepper.run(basis, U, problems.traveling_wave(eps), tau, k, 2, t0=tau, boundary=bd),
+            (nx - 1) * (ny - 1) ** 2, 15.0, 200, cores,
+            "{steps} EIFE2 steps of Table 4's 512x32x32 spatial row (N_T = 1024; after 1 untimed step; the "
+            "1024x64x64 grid's all-node boundary matrices are too large for the oracle; each oracle call builds "
+            "the boundary matrices once, inside the timing), FP64 oracle tier C "
+            f"(scipy.fft.dstn, workers={cores}), {{dt:.2f}} s")
+        log(f"bench: cpu oracle {cpu['value']:.4e} DoF-steps/s on {cpu['cores']} cores")
     out = {"metric": "Example 5.2 (Table 4) EIFE errors, observed rates and DoF-steps/s", "value": best["dof_steps_per_s"],
            "unit": "DoF-steps/s", "n_gpus": 1, "steps": best["N_T"], "warmup": 0,
            "ms_per_step": 1e3 * ndof / best["dof_steps_per_s"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "Example 5.2 traveling wave, eps=0.05, nonhomogeneous Dirichlet data as part of f, "
                                   "T=3 sqrt(2) eps/5; value: EIFE2 N_T=128 on 1024x64x64", "dofs": ndof},
-           "ex52": res}
+           "ex52": res, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -470,12 +511,25 @@ def bench_variable(args, torch, eife):
     g.close()
     res["equal_taus_bitwise_equal"] = bool(torch.equal(outs["uniform_eife_step"], outs["equal_taus_step_variable"]))
     v = res["varying_taus_step_variable"]
+    cpu = None
+    if not args.no_cpu:
+        from oracle import problems, spectral, stepper
+        cores = cpu_cores()
+        basis = spectral.SineBasis(N, h, EPS * EPS, workers=cores)
+        taus = list(TAU * (1.0 + 0.5 * np.sin(np.arange(K))))
+        cpu = cpu_oracle_rate(
+            lambda: stepper.run(basis, u0, problems.allen_cahn(), taus[:1], 1, 2),
+            lambda U, k: stepper.run(basis, U, problems.allen_cahn(), taus[1:1 + k], k, 2, t0=taus[0]), ndof, 15.0,
+            min(20, K - 1), cores,
+            "{steps} varying-step EIFE2 steps of the same 255^3 problem (after 1 untimed step), FP64 oracle tier C "
+            f"(scipy.fft.dstn, workers={cores}), {{dt:.2f}} s")
+        log(f"bench: cpu oracle {cpu['value']:.4e} DoF-steps/s on {cpu['cores']} cores")
     out = {"metric": "variable-step EIFE2 DoF-steps/s", "value": v["dof_steps_per_s"], "unit": "DoF-steps/s",
            "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": v["ms_per_step"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "3D Allen-Cahn eps=0.02, 255^3 DoFs, FP32, EIFE2 c2=1/2, tau_n = 0.005 (1 + 0.5 sin n)",
                       "dofs": ndof},
-           "variable": res}
+           "variable": res, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -548,13 +602,25 @@ def bench_three(args, torch, eife):
             + " ".join(f"{e:.3e}" for e in errs) + f", rates {rates}")
     g_ref.close()
     res["manufactured_orders"] = rows
+    cpu = None
+    if not args.no_cpu:
+        from oracle import erk, problems, spectral
+        cores = cpu_cores()
+        basis = spectral.SineBasis(N, h, EPS * EPS, workers=cores)
+        nodes = [0.0, 1.0 / 3.0, 2.0 / 3.0]
+        cpu = cpu_oracle_rate(
+            lambda: erk.run(basis, u0, problems.allen_cahn(), TAU, 1, nodes),
+            lambda U, k: erk.run(basis, U, problems.allen_cahn(), TAU, k, nodes, t0=TAU), ndof, 15.0, 10, cores,
+            "{steps} three-stage steps of the same 255^3 problem (after 1 untimed step), FP64 oracle (oracle/erk.py, "
+            f"tier C scipy.fft.dstn, workers={cores}), {{dt:.2f}} s")
+        log(f"bench: cpu oracle {cpu['value']:.4e} DoF-steps/s on {cpu['cores']} cores")
     v = res["cube"]["stages3"]
     out = {"metric": "three-stage EIFE DoF-steps/s and observed temporal order", "value": v["dof_steps_per_s"],
            "unit": "DoF-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": v["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "3D Allen-Cahn eps=0.02, 255^3 DoFs, FP32, three stages (nodes 0, 1/3, 2/3), "
                                   "tau=0.005", "dofs": ndof},
-           "three_stage": res}
+           "three_stage": res, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     return 0
 
