@@ -1116,6 +1116,7 @@ constexpr int kNtX = 64, kNtY = 4;  // kNtX * kNtY = kNormThreads
 
 struct PlaneSums {
   double eA, eB, uA, uB;
+  double e, u;  // the thread's own node of the plane
 };
 
 template <typename T>
@@ -1137,7 +1138,7 @@ __global__ void __launch_bounds__(kNormThreads) norm_tile(const T* __restrict__ 
   // planes p = 0 .. np-1 are z = z0 - 1 .. z1; a z axis of one node couples to
   // nothing, so there the planes before and after the chunk stay zero
   const int np = z0 < nz ? z1 - z0 + 2 : 0;
-  PlaneSums prev{0.0, 0.0, 0.0, 0.0}, cur{0.0, 0.0, 0.0, 0.0};
+  PlaneSums prev{0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, cur{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int pg = 0; pg < np; pg += G) {
     // stage planes pg .. pg+G-1 (wrapped on a periodic z axis; zero outside)
     for (int k = threadIdx.x; k < G * HX * HY; k += kNormThreads) {
@@ -1162,7 +1163,7 @@ __global__ void __launch_bounds__(kNormThreads) norm_tile(const T* __restrict__ 
     __syncthreads();
     for (int gp = 0; gp < G && pg + gp < np; ++gp) {
       const int p = pg + gp;
-      PlaneSums next{0.0, 0.0, 0.0, 0.0};
+      PlaneSums next{0.0, 0.0, 0.0, 0.0, te[gp][ty + 1][tx + 1], tu[gp][ty + 1][tx + 1]};
 #pragma unroll
       for (int oy = -1; oy <= 1; ++oy) {
         const double ay = oy ? g.ao[1] : g.ad[1];
@@ -1181,10 +1182,7 @@ __global__ void __launch_bounds__(kNormThreads) norm_tile(const T* __restrict__ 
       }
       // plane p closes the window of the node at z = z0 - 2 + p (planes p - 2, p - 1, p)
       if (p >= 2 && own) {
-        const int z = z0 - 2 + p;
-        const int64_t i = ix + iy * sy + z * sz;
-        const double ui = double(u[i]);
-        const double ei = ur ? ui - double(ur[i]) : ui;
+        const double ui = cur.u, ei = cur.e;
         const double Me = g.ad[2] * cur.eA + g.ao[2] * (prev.eA + next.eA);
         const double Ke =
             g.bd[2] * cur.eA + g.bo[2] * (prev.eA + next.eA) + g.ad[2] * cur.eB + g.ao[2] * (prev.eB + next.eB);
