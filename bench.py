@@ -625,17 +625,87 @@ def bench_three(args, torch, eife):
     return 0
 
 
+# Table 3 of the paper (Example 5.1, EIFE2 with c2 = 1/2, N_T = 50): average seconds per step of the
+# authors' Matlab FP64 solver on an Intel i5-8250U (1.8 GHz, 8 GB), per grid of intervals.
+PAPER_TABLE3 = {(512, 256): 1.121, (1024, 512): 4.444, (2048, 1024): 17.516, (4096, 2048): 75.944}
+
+
+def bench_table3(args, torch, eife):
+    """The paper's timing table (Table 3): Example 5.1, u_t = (1/2) Lap u - (pi^2/2) u + (pi^2/2) e^{-pi^2 t}
+    sin(pi x) sin(pi y) on (1/2, 5/2) x (0, 1), exact u = e^{-pi^2 t} (sin(pi x) - 1) sin(pi y), EIFE2 with
+    c2 = 1/2 and N_T = 50 (tau = 1/50, T = 1), FP64, grids 512x256 ... 4096x2048 intervals.  Per grid: the
+    50 steps timed in one call (after one untimed call), DoF-steps/s next to the paper's Matlab figure on
+    its laptop CPU, and the discrete L2 error against the exact nodal values at T as a check."""
+    rows = []
+    log("bench: Table 3 (Example 5.1, EIFE2, N_T = 50, FP64)")
+    for (nx, ny), paper_s in PAPER_TABLE3.items():
+        N, h = [nx, ny], [2.0 / nx, 1.0 / ny]
+        x = 0.5 + h[0] * np.arange(1, nx)
+        y = h[1] * np.arange(1, ny)
+        base = np.outer(np.sin(np.pi * y), np.sin(np.pi * x) - 1.0)  # [y][x]
+        g = eife.Grid(N, h, 0.5, "f64")
+        g.set_origin([0.5, 0.0])
+        g.set_phi(1.0 / 50.0, 2)
+        u = torch.tensor(base, device="cuda")
+        g.step(u, 50, eife.F_EX51, 0.0)  # untimed
+        u.copy_(torch.tensor(base))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(u, 50, eife.F_EX51, 0.0)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 50
+        exact = torch.tensor(np.exp(-np.pi ** 2) * base, device="cuda")
+        l2 = g.norms(u, exact)[0]
+        g.close()
+        ndof = (nx - 1) * (ny - 1)
+        row = {"grid": f"{nx}x{ny}", "dofs": ndof, "s_per_step": dt, "dof_steps_per_s": ndof / dt,
+               "paper_s_per_step": paper_s, "paper_dof_steps_per_s": ndof / paper_s, "speedup_vs_paper": paper_s / dt,
+               "L2_vs_exact_nodal": l2}
+        rows.append(row)
+        log(f"  {nx}x{ny}: {dt * 1e3:.4f} ms/step, {ndof / dt:.4e} DoF-steps/s; paper {paper_s:.3f} s/step "
+            f"({ndof / paper_s:.3e} DoF-steps/s, i5-8250U Matlab) -> x{paper_s / dt:.0f}; L2 vs exact {l2:.3e}")
+    cpu = None
+    if not args.no_cpu:
+        from oracle import problems, spectral, stepper
+        cores = cpu_cores()
+        nx, ny = 2048, 1024
+        N, h = [nx, ny], [2.0 / nx, 1.0 / ny]
+        x = 0.5 + h[0] * np.arange(1, nx)
+        y = h[1] * np.arange(1, ny)
+        base = np.outer(np.sin(np.pi * y), np.sin(np.pi * x) - 1.0)
+        basis = spectral.SineBasis(N, h, 0.5, workers=cores)
+        cpu = cpu_oracle_rate(
+            lambda: stepper.run(basis, base, problems.ex51(), 1.0 / 50, 1, 2, origin=(0.5, 0.0)),
+            lambda U, k: stepper.run(basis, U, problems.ex51(), 1.0 / 50, k, 2, t0=1.0 / 50, origin=(0.5, 0.0)),
+            (nx - 1) * (ny - 1), 12.0, 49, cores,
+            "{steps} EIFE2 steps of Table 3's 2048x1024 grid (after 1 untimed step), FP64 oracle tier C "
+            f"(scipy.fft.dstn, workers={cores}), {{dt:.2f}} s")
+        log(f"bench: cpu oracle {cpu['value']:.4e} DoF-steps/s on {cpu['cores']} cores")
+    big = rows[-1]
+    out = {"metric": "Table 3 (Example 5.1) EIFE2 DoF-steps/s per grid, with the paper's Matlab timings",
+           "value": big["dof_steps_per_s"], "unit": "DoF-steps/s", "n_gpus": 1, "steps": 50, "warmup": 50,
+           "ms_per_step": big["s_per_step"] * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": big["speedup_vs_paper"], "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "Example 5.1 (Table 3), EIFE2 c2=1/2, N_T=50, FP64; value: 4096x2048 intervals; "
+                                  "vs_baseline: against the paper's 75.944 s/step (Matlab FP64, Intel i5-8250U "
+                                  "1.8 GHz laptop)", "dofs": big["dofs"]},
+           "table3": rows, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", choices=["cube", "batched", "manufactured", "ex53", "ex52", "variable", "three"], default="cube",
+    ap.add_argument("--workload", choices=["cube", "batched", "manufactured", "ex53", "ex52", "variable", "three", "table3"], default="cube",
                     help="cube: 3D Allen-Cahn 255^3 (default line); batched: 512 independent 2D instances; "
                          "manufactured: 4095^2 orders, errors and rates; ex53: periodic 128^3 Flory-Huggins "
                          "grain coarsening to T = 20; ex52: traveling wave with Dirichlet data (Table 4); "
-                         "variable: the cube problem with varying step sizes; three: the three-stage scheme")
+                         "variable: the cube problem with varying step sizes; three: the three-stage scheme; "
+                         "table3: the paper's timing table (Example 5.1)")
     ap.add_argument("--transform", choices=["fft", "gemm"], default="fft",
                     help="cube workload: FFT sine transforms (default) or split-BF16 matrix-core products")
     ap.add_argument("--no-corrector", action="store_true",
@@ -664,6 +734,8 @@ def main():
         return bench_variable(args, torch, eife)
     if args.workload == "three":
         return bench_three(args, torch, eife)
+    if args.workload == "table3":
+        return bench_table3(args, torch, eife)
 
     N = [N_INT] * 3
     h = [1.0 / N_INT] * 3
