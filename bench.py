@@ -844,7 +844,14 @@ def main():
                                   "u0 uniform[-0.9,0.9] seed 0, EIFE2 c2=1/2 tau=0.005, "
                                   + ("split-BF16 matrix-core sine transforms" if gemm else "FP32 sine-transform path"),
                       "dofs": ndof, "tau": TAU, "scheme": "EIFE2", "transform": args.transform},
-           "roofline": roof, "cpu_baseline": cpu, "accuracy": acc, "corrector": corr, "reductions": red}
+           "roofline": roof, "cpu_baseline": cpu, "accuracy": acc, "corrector": corr, "reductions": red,
+           # the paper's only timings (Table 3), another workload on other hardware: context only
+           "paper_timings": {"table": "Table 3, Example 5.1 (2D), EIFE2, N_T = 50, FP64",
+                             "hardware": "Matlab on an Intel i5-8250U 1.8 GHz laptop, 8 GB",
+                             "s_per_step": {f"{nx}x{ny}": t for (nx, ny), t in PAPER_TABLE3.items()},
+                             "dof_steps_per_s": {f"{nx}x{ny}": round((nx - 1) * (ny - 1) / t, 1)
+                                                 for (nx, ny), t in PAPER_TABLE3.items()},
+                             "same_workload_here": "bench.py --workload table3"}}
     print(json.dumps(out), flush=True)
 
 
