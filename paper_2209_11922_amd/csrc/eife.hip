@@ -53,6 +53,11 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int kThreads = 256;
+// Generic passes over lines of at least kLongLine FFT points (one or two
+// lines fill a block's LDS) run kLongThreads threads per block: more waves per
+// compute unit and 8 instead of 32 values per thread.
+constexpr int kLongLine = 4096;
+constexpr int kLongThreads = 1024;
 constexpr size_t kLdsBudget = 80 * 1024;  // per block, two blocks per CU fit in 160 KB
 constexpr int kNormBlocksMax = 8192;
 constexpr int kTabArrays = 8;  // lam, w, M, Q, Mc, R, Mc3, Qc3 per axis
@@ -670,75 +675,75 @@ bool try_col_fast(const eife_grid_s* g, int var, int axis, int mode, int outer, 
   return false;
 }
 
-template <typename T, bool BATR>
+template <typename T, bool BATR, int NT = kThreads>
 void row_generic_go(int mode, dim3 grid, size_t shm, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
                     const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
   if (mode == ROW_PHYS)
-    hipLaunchKernelGGL((row_pass<T, ROW_PHYS, BATR>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F, ri);
+    hipLaunchKernelGGL((row_pass<T, ROW_PHYS, BATR, NT>), grid, dim3(NT), shm, s, src, dst, dst2, rg, tw, F, ri);
   else if (mode == ROW_FWD_USER)
-    hipLaunchKernelGGL((row_pass<T, ROW_FWD_USER, BATR>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F, ri);
+    hipLaunchKernelGGL((row_pass<T, ROW_FWD_USER, BATR, NT>), grid, dim3(NT), shm, s, src, dst, dst2, rg, tw, F, ri);
   else
-    hipLaunchKernelGGL((row_pass<T, ROW_INV_USER, BATR>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F, ri);
+    hipLaunchKernelGGL((row_pass<T, ROW_INV_USER, BATR, NT>), grid, dim3(NT), shm, s, src, dst, dst2, rg, tw, F, ri);
 }
 
-template <typename T, bool BATC>
+template <typename T, bool BATC, int NT = kThreads>
 void col_generic_go(int mode, dim3 grid, size_t shm, hipStream_t s, T* W, T* H, const ColGeom& cg, const Cx<T>* tw,
                     const Diag& dg, const ColInst<T>* ci) {
   if constexpr (!BATC) {
     if (mode == COL_S3_1) {
-      hipLaunchKernelGGL((col_pass<T, COL_S3_1, false>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+      hipLaunchKernelGGL((col_pass<T, COL_S3_1, false, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg, ci);
       return;
     }
     if (mode == COL_S3_2) {
-      hipLaunchKernelGGL((col_pass<T, COL_S3_2, false>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+      hipLaunchKernelGGL((col_pass<T, COL_S3_2, false, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg, ci);
       return;
     }
     if (mode == COL_S3_3) {
-      hipLaunchKernelGGL((col_pass<T, COL_S3_3, false>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+      hipLaunchKernelGGL((col_pass<T, COL_S3_3, false, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg, ci);
       return;
     }
   }
   if (mode == COL_PLAIN)
-    hipLaunchKernelGGL((col_pass<T, COL_PLAIN, BATC>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+    hipLaunchKernelGGL((col_pass<T, COL_PLAIN, BATC, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg, ci);
   else if (mode == COL_STAGE_A)
-    hipLaunchKernelGGL((col_pass<T, COL_STAGE_A, BATC>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+    hipLaunchKernelGGL((col_pass<T, COL_STAGE_A, BATC, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg, ci);
   else if (mode == COL_STAGE_B)
-    hipLaunchKernelGGL((col_pass<T, COL_STAGE_B, BATC>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+    hipLaunchKernelGGL((col_pass<T, COL_STAGE_B, BATC, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg, ci);
   else
-    hipLaunchKernelGGL((col_pass<T, COL_ETD1, BATC>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg, ci);
+    hipLaunchKernelGGL((col_pass<T, COL_ETD1, BATC, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg, ci);
 }
 
 // Periodic lines (generic passes only).
-template <typename T>
+template <typename T, int NT = kThreads>
 void row_periodic_go(int mode, dim3 grid, size_t shm, hipStream_t s, const T* src, T* dst, T* dst2,
                      const RowGeom& rg, const Cx<T>* tw, const Forcing& F) {
   if (mode == ROW_PHYS)
-    hipLaunchKernelGGL((row_pass_per<T, ROW_PHYS>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F);
+    hipLaunchKernelGGL((row_pass_per<T, ROW_PHYS, NT>), grid, dim3(NT), shm, s, src, dst, dst2, rg, tw, F);
   else if (mode == ROW_FWD_USER)
-    hipLaunchKernelGGL((row_pass_per<T, ROW_FWD_USER>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F);
+    hipLaunchKernelGGL((row_pass_per<T, ROW_FWD_USER, NT>), grid, dim3(NT), shm, s, src, dst, dst2, rg, tw, F);
   else
-    hipLaunchKernelGGL((row_pass_per<T, ROW_INV_USER>), grid, dim3(kThreads), shm, s, src, dst, dst2, rg, tw, F);
+    hipLaunchKernelGGL((row_pass_per<T, ROW_INV_USER, NT>), grid, dim3(NT), shm, s, src, dst, dst2, rg, tw, F);
 }
 
-template <typename T>
+template <typename T, int NT = kThreads>
 void col_periodic_go(int mode, dim3 grid, size_t shm, hipStream_t s, T* W, T* H, const ColGeom& cg,
                      const Cx<T>* tw, const Diag& dg) {
   if (mode == COL_PLAIN)
-    hipLaunchKernelGGL((col_pass_per<T, COL_PLAIN>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+    hipLaunchKernelGGL((col_pass_per<T, COL_PLAIN, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg);
   else if (mode == COL_PLAIN_INV)
-    hipLaunchKernelGGL((col_pass_per<T, COL_PLAIN_INV>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+    hipLaunchKernelGGL((col_pass_per<T, COL_PLAIN_INV, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg);
   else if (mode == COL_STAGE_A)
-    hipLaunchKernelGGL((col_pass_per<T, COL_STAGE_A>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+    hipLaunchKernelGGL((col_pass_per<T, COL_STAGE_A, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg);
   else if (mode == COL_STAGE_B)
-    hipLaunchKernelGGL((col_pass_per<T, COL_STAGE_B>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+    hipLaunchKernelGGL((col_pass_per<T, COL_STAGE_B, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg);
   else if (mode == COL_S3_1)
-    hipLaunchKernelGGL((col_pass_per<T, COL_S3_1>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+    hipLaunchKernelGGL((col_pass_per<T, COL_S3_1, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg);
   else if (mode == COL_S3_2)
-    hipLaunchKernelGGL((col_pass_per<T, COL_S3_2>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+    hipLaunchKernelGGL((col_pass_per<T, COL_S3_2, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg);
   else if (mode == COL_S3_3)
-    hipLaunchKernelGGL((col_pass_per<T, COL_S3_3>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+    hipLaunchKernelGGL((col_pass_per<T, COL_S3_3, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg);
   else
-    hipLaunchKernelGGL((col_pass_per<T, COL_ETD1>), grid, dim3(kThreads), shm, s, W, H, cg, tw, dg);
+    hipLaunchKernelGGL((col_pass_per<T, COL_ETD1, NT>), grid, dim3(NT), shm, s, W, H, cg, tw, dg);
 }
 
 // ---------------------------------------------------------------------------
@@ -937,11 +942,17 @@ int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, i
     dim3 grid((rg.nrows + 2 * rg.P - 1) / (2 * rg.P), B.count);
     if (g->per[0]) {
       if (ri || mode == ROW_FWD_PHYS) return fail(EIFE_EUNSUPPORTED, "periodic row pass variant");
-      row_periodic_go<T>(mode, grid, shm, s, src, dst, dst2, rg, tw, F);
+      if (rg.pl.L >= kLongLine)
+        row_periodic_go<T, kLongThreads>(mode, grid, shm, s, src, dst, dst2, rg, tw, F);
+      else
+        row_periodic_go<T>(mode, grid, shm, s, src, dst, dst2, rg, tw, F);
     } else if (ri)
       row_generic_go<T, true>(mode, grid, shm, s, src, dst, dst2, rg, tw, F, ri);
     else
-      row_generic_go<T, false>(mode, grid, shm, s, src, dst, dst2, rg, tw, F, ri);
+      if (rg.pl.L >= kLongLine)
+        row_generic_go<T, false, kLongThreads>(mode, grid, shm, s, src, dst, dst2, rg, tw, F, ri);
+      else
+        row_generic_go<T, false>(mode, grid, shm, s, src, dst, dst2, rg, tw, F, ri);
   }
   HIP_TRY(hipGetLastError());
   prof_end(g, pidx, s);
@@ -990,11 +1001,17 @@ int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, h
     dim3 grid(g->pitch / (2 * cg.P), outer, B.count);
     if (g->per[axis]) {
       if (ci) return fail(EIFE_EUNSUPPORTED, "periodic batched column pass");
-      col_periodic_go<T>(mode, grid, shm, s, W, H, cg, tw, dg);
+      if (cg.pl.L >= kLongLine)
+        col_periodic_go<T, kLongThreads>(mode, grid, shm, s, W, H, cg, tw, dg);
+      else
+        col_periodic_go<T>(mode, grid, shm, s, W, H, cg, tw, dg);
     } else if (ci)
       col_generic_go<T, true>(mode, grid, shm, s, W, H, cg, tw, dg, ci);
     else
-      col_generic_go<T, false>(mode, grid, shm, s, W, H, cg, tw, dg, ci);
+      if (cg.pl.L >= kLongLine)
+        col_generic_go<T, false, kLongThreads>(mode, grid, shm, s, W, H, cg, tw, dg, ci);
+      else
+        col_generic_go<T, false>(mode, grid, shm, s, W, H, cg, tw, dg, ci);
   }
   HIP_TRY(hipGetLastError());
   prof_end(g, pidx, s);

@@ -72,14 +72,16 @@ struct Dft<T, 4> {
   }
 };
 
-// Per-thread element budget of one in-place Stockham stage: P * L <= kMaxElems * blockDim.
+// Per-thread element budget of one in-place Stockham stage: P * L <= kMaxElems * 256
+// (a 256-thread block holds 32 values per thread; the 1024-thread variants for
+// long lines hold 8).
 constexpr int kMaxElems = 32;
 
 // One radix-R stage on P lines of length L stored at lds + p * ls.  Ns is the
 // product of the radices already applied; tw[j] = exp(-2 pi i j / L).
-template <typename T, int R>
+template <typename T, int R, int ME>
 __device__ void stockham_stage(Cx<T>* lds, int ls, int L, int P, int Ns, const Cx<T>* __restrict__ tw) {
-  constexpr int MAXB = (kMaxElems + R - 1) / R;
+  constexpr int MAXB = (ME + R - 1) / R;
   const int nbf = L / R;
   const int total = P * nbf;
   const int tws = L / (Ns * R);
@@ -123,19 +125,20 @@ struct FftPlan {
 
 // Forward FFT of P lines in LDS (natural order in and out).  Callers must
 // __syncthreads() before (inputs written) -- stages synchronise internally.
-template <typename T>
+// ME: values per thread the block's size allows (P * L <= ME * blockDim).
+template <typename T, int ME>
 __device__ void fft_lines(Cx<T>* lds, int ls, int P, FftPlan pl, const Cx<T>* __restrict__ tw) {
   int Ns = 1;
   for (int i = 0; i < pl.n4; ++i) {
-    stockham_stage<T, 4>(lds, ls, pl.L, P, Ns, tw);
+    stockham_stage<T, 4, ME>(lds, ls, pl.L, P, Ns, tw);
     Ns *= 4;
   }
   for (int i = 0; i < pl.n2; ++i) {
-    stockham_stage<T, 2>(lds, ls, pl.L, P, Ns, tw);
+    stockham_stage<T, 2, ME>(lds, ls, pl.L, P, Ns, tw);
     Ns *= 2;
   }
   for (int i = 0; i < pl.n3; ++i) {
-    stockham_stage<T, 3>(lds, ls, pl.L, P, Ns, tw);
+    stockham_stage<T, 3, ME>(lds, ls, pl.L, P, Ns, tw);
     Ns *= 3;
   }
 }
@@ -507,8 +510,8 @@ __device__ __forceinline__ void row_inst_ptrs(const RowInst<T>* insts, const T*&
   }
 }
 
-template <typename T, int MODE, bool BAT>
-__global__ void __launch_bounds__(256) row_pass(const T* src, T* dst, T* dst2, RowGeom g,
+template <typename T, int MODE, bool BAT, int NT = 256>
+__global__ void __launch_bounds__(NT) row_pass(const T* src, T* dst, T* dst2, RowGeom g,
                                                 const Cx<T>* __restrict__ tw, Forcing F,
                                                 const RowInst<T>* __restrict__ insts) {
   if constexpr (BAT) row_inst_ptrs<T, MODE>(insts, src, dst, dst2, F);
@@ -534,7 +537,7 @@ __global__ void __launch_bounds__(256) row_pass(const T* src, T* dst, T* dst2, R
     put_odd(lds + p * g.ls, L, m + 1, a, b);
   }
   __syncthreads();
-  fft_lines(lds, g.ls, P, g.pl, tw);
+  fft_lines<T, kMaxElems * 256 / NT>(lds, g.ls, P, g.pl, tw);
 
   if (MODE == ROW_INV_USER) {
     for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
@@ -583,7 +586,7 @@ __global__ void __launch_bounds__(256) row_pass(const T* src, T* dst, T* dst2, R
     }
   }
   __syncthreads();
-  fft_lines(lds, g.ls, P, g.pl, tw);
+  fft_lines<T, kMaxElems * 256 / NT>(lds, g.ls, P, g.pl, tw);
   for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
     const int p = i / n;
     const int m = i - p * n;
@@ -667,8 +670,8 @@ __device__ __forceinline__ void col_inst_ptrs(const ColInst<T>* insts, T*& W, T*
   dg.D = I.D;
 }
 
-template <typename T, int MODE, bool BAT>
-__global__ void __launch_bounds__(256) col_pass(T* W, T* H, ColGeom g, const Cx<T>* __restrict__ tw, Diag dg,
+template <typename T, int MODE, bool BAT, int NT = 256>
+__global__ void __launch_bounds__(NT) col_pass(T* W, T* H, ColGeom g, const Cx<T>* __restrict__ tw, Diag dg,
                                                 const ColInst<T>* __restrict__ insts) {
   if constexpr (BAT) col_inst_ptrs<T>(insts, W, H, dg);
   extern __shared__ unsigned char smem_raw[];
@@ -691,7 +694,7 @@ __global__ void __launch_bounds__(256) col_pass(T* W, T* H, ColGeom g, const Cx<
     put_odd(lds + p * g.ls, L, m + 1, v.re, v.im);
   }
   __syncthreads();
-  fft_lines(lds, g.ls, P, g.pl, tw);
+  fft_lines<T, kMaxElems * 256 / NT>(lds, g.ls, P, g.pl, tw);
 
   if (MODE == COL_PLAIN) {
     for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
@@ -760,7 +763,7 @@ __global__ void __launch_bounds__(256) col_pass(T* W, T* H, ColGeom g, const Cx<
     }
   }
   __syncthreads();
-  fft_lines(lds, g.ls, P, g.pl, tw);
+  fft_lines<T, kMaxElems * 256 / NT>(lds, g.ls, P, g.pl, tw);
   for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
     const int m = i / P;
     const int p = i - m * P;
@@ -837,8 +840,8 @@ __device__ __forceinline__ Cx<T> per_nodal(Cx<T> X, T s1) {
 }
 
 // Row pass of periodic lines (x): ROW_FWD_USER, ROW_INV_USER or ROW_PHYS.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(256) row_pass_per(const T* src, T* dst, T* dst2, RowGeom g,
+template <typename T, int MODE, int NT = 256>
+__global__ void __launch_bounds__(NT) row_pass_per(const T* src, T* dst, T* dst2, RowGeom g,
                                                     const Cx<T>* __restrict__ tw, Forcing F) {
   extern __shared__ unsigned char smem_raw[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem_raw);
@@ -859,7 +862,7 @@ __global__ void __launch_bounds__(256) row_pass_per(const T* src, T* dst, T* dst
     // inverse transform to nodal values
     per_pack(lds, g.ls, P, n);
     __syncthreads();
-    fft_lines(lds, g.ls, P, g.pl, tw);
+    fft_lines<T, kMaxElems * 256 / NT>(lds, g.ls, P, g.pl, tw);
     for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
       const int p = i / n;
       const int m = i - p * n;
@@ -879,7 +882,7 @@ __global__ void __launch_bounds__(256) row_pass_per(const T* src, T* dst, T* dst
     __syncthreads();
   }
   // forward transform
-  fft_lines(lds, g.ls, P, g.pl, tw);
+  fft_lines<T, kMaxElems * 256 / NT>(lds, g.ls, P, g.pl, tw);
   per_unpack(lds, g.ls, P, n);
   __syncthreads();
   for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
@@ -902,8 +905,8 @@ __global__ void __launch_bounds__(256) row_pass_per(const T* src, T* dst, T* dst
 // or a stage (forward, diagonal stage, inverse).  Tiles as col_pass.
 enum { COL_PLAIN_INV = 4 };
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(256) col_pass_per(T* W, T* H, ColGeom g, const Cx<T>* __restrict__ tw, Diag dg) {
+template <typename T, int MODE, int NT = 256>
+__global__ void __launch_bounds__(NT) col_pass_per(T* W, T* H, ColGeom g, const Cx<T>* __restrict__ tw, Diag dg) {
   extern __shared__ unsigned char smem_raw[];
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem_raw);
   const int n = g.n;  // = N, the FFT length
@@ -922,7 +925,7 @@ __global__ void __launch_bounds__(256) col_pass_per(T* W, T* H, ColGeom g, const
   if (MODE == COL_PLAIN_INV) {
     per_pack(lds, g.ls, P, n);
     __syncthreads();
-    fft_lines(lds, g.ls, P, g.pl, tw);
+    fft_lines<T, kMaxElems * 256 / NT>(lds, g.ls, P, g.pl, tw);
     for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
       const int m = i / P;
       const int p = i - m * P;
@@ -931,7 +934,7 @@ __global__ void __launch_bounds__(256) col_pass_per(T* W, T* H, ColGeom g, const
     }
     return;
   }
-  fft_lines(lds, g.ls, P, g.pl, tw);
+  fft_lines<T, kMaxElems * 256 / NT>(lds, g.ls, P, g.pl, tw);
   per_unpack(lds, g.ls, P, n);
   __syncthreads();
   if (MODE == COL_PLAIN) {
@@ -990,7 +993,7 @@ __global__ void __launch_bounds__(256) col_pass_per(T* W, T* H, ColGeom g, const
   __syncthreads();
   per_pack(lds, g.ls, P, n);
   __syncthreads();
-  fft_lines(lds, g.ls, P, g.pl, tw);
+  fft_lines<T, kMaxElems * 256 / NT>(lds, g.ls, P, g.pl, tw);
   for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
     const int m = i / P;
     const int p = i - m * P;

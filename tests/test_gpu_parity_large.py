@@ -77,3 +77,30 @@ def test_3d_384x192x96_f64_eife1():
     u0 = seeded_inputs.uniform_field(6, N)
     got, ref = _run_both(N, 4e-4, u0, 0.005, 3, 1, 1, problems.allen_cahn(), "f64")
     assert _rel(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("N,dtype", [([2048, 1024], "f64"), ([3072, 16], "f32"), ([48, 4096], "f64")],
+                         ids=["table3-grid", "radix3-rows", "long-columns"])
+def test_long_lines_1024_thread_passes(N, dtype):
+    """Lines of 4096 FFT points and more run the 1024-thread generic passes (rows and columns)."""
+    u0 = seeded_inputs.uniform_field(7, N)
+    got, ref = _run_both(N, 0.01, u0, 0.01, 3, 2, 1, problems.allen_cahn(), dtype)
+    err = _rel(got, ref)
+    print(f"long lines {N} {dtype}: {err:.2e}")
+    assert err <= (1e-12 if dtype == "f64" else 1e-5)
+
+
+def test_long_periodic_lines():
+    import paper_2209_11922_amd as eife
+    N = [4096, 12]
+    h = [1.0 / n for n in N]
+    u0 = np.random.default_rng(8).uniform(-0.9, 0.9, (12, 4096))
+    g = eife.Grid(N, h, 1e-3, "f64", bc=eife.BC_PERIODIC)
+    g.set_phi(0.01, 2)
+    u = torch.tensor(u0, device="cuda")
+    g.step(u, 3, eife.F_ALLEN_CAHN)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    g.close()
+    ref = stepper.run(spectral.make_basis("C", N, h, 1e-3, bc="periodic"), u0, problems.allen_cahn(), 0.01, 3, 2)
+    assert _rel(got, ref) <= 1e-12
