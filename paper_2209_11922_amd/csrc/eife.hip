@@ -53,11 +53,17 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int kThreads = 256;
-// Generic passes over lines of at least kLongLine FFT points (one or two
+// Generic FP64 passes over lines of at least kLongLine FFT points (one or two
 // lines fill a block's LDS) run kLongThreads threads per block: more waves per
 // compute unit and 8 instead of 32 values per thread.
 constexpr int kLongLine = 4096;
 constexpr int kLongThreads = 1024;
+// FP64 only: FP32 long lines measured slower with the larger blocks (two
+// 256-thread blocks of one FP32 line each share a compute unit instead).
+template <typename T>
+bool long_lines(int L) {
+  return sizeof(T) == 8 && L >= kLongLine;
+}
 constexpr size_t kLdsBudget = 80 * 1024;  // per block, two blocks per CU fit in 160 KB
 constexpr int kNormBlocksMax = 8192;
 constexpr int kTabArrays = 8;  // lam, w, M, Q, Mc, R, Mc3, Qc3 per axis
@@ -942,14 +948,14 @@ int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, i
     dim3 grid((rg.nrows + 2 * rg.P - 1) / (2 * rg.P), B.count);
     if (g->per[0]) {
       if (ri || mode == ROW_FWD_PHYS) return fail(EIFE_EUNSUPPORTED, "periodic row pass variant");
-      if (rg.pl.L >= kLongLine)
+      if (long_lines<T>(rg.pl.L))
         row_periodic_go<T, kLongThreads>(mode, grid, shm, s, src, dst, dst2, rg, tw, F);
       else
         row_periodic_go<T>(mode, grid, shm, s, src, dst, dst2, rg, tw, F);
     } else if (ri)
       row_generic_go<T, true>(mode, grid, shm, s, src, dst, dst2, rg, tw, F, ri);
     else
-      if (rg.pl.L >= kLongLine)
+      if (long_lines<T>(rg.pl.L))
         row_generic_go<T, false, kLongThreads>(mode, grid, shm, s, src, dst, dst2, rg, tw, F, ri);
       else
         row_generic_go<T, false>(mode, grid, shm, s, src, dst, dst2, rg, tw, F, ri);
@@ -1001,14 +1007,14 @@ int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, h
     dim3 grid(g->pitch / (2 * cg.P), outer, B.count);
     if (g->per[axis]) {
       if (ci) return fail(EIFE_EUNSUPPORTED, "periodic batched column pass");
-      if (cg.pl.L >= kLongLine)
+      if (long_lines<T>(cg.pl.L))
         col_periodic_go<T, kLongThreads>(mode, grid, shm, s, W, H, cg, tw, dg);
       else
         col_periodic_go<T>(mode, grid, shm, s, W, H, cg, tw, dg);
     } else if (ci)
       col_generic_go<T, true>(mode, grid, shm, s, W, H, cg, tw, dg, ci);
     else
-      if (cg.pl.L >= kLongLine)
+      if (long_lines<T>(cg.pl.L))
         col_generic_go<T, false, kLongThreads>(mode, grid, shm, s, W, H, cg, tw, dg, ci);
       else
         col_generic_go<T, false>(mode, grid, shm, s, W, H, cg, tw, dg, ci);

@@ -79,10 +79,10 @@ def test_3d_384x192x96_f64_eife1():
     assert _rel(got, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("N,dtype", [([2048, 1024], "f64"), ([3072, 16], "f32"), ([48, 4096], "f64")],
+@pytest.mark.parametrize("N,dtype", [([2048, 1024], "f64"), ([3072, 16], "f64"), ([48, 4096], "f64")],
                          ids=["table3-grid", "radix3-rows", "long-columns"])
 def test_long_lines_1024_thread_passes(N, dtype):
-    """Lines of 4096 FFT points and more run the 1024-thread generic passes (rows and columns)."""
+    """FP64 lines of 4096 FFT points and more run the 1024-thread generic passes (rows and columns)."""
     u0 = seeded_inputs.uniform_field(7, N)
     got, ref = _run_both(N, 0.01, u0, 0.01, 3, 2, 1, problems.allen_cahn(), dtype)
     err = _rel(got, ref)
