@@ -73,8 +73,12 @@ int g_cus = 256;                     // compute units of the device (set at grid
 
 bool factor_plan(int L, FftPlan* pl) {
   pl->L = L;
-  pl->n4 = pl->n2 = pl->n3 = 0;
+  pl->n8 = pl->n4 = pl->n2 = pl->n3 = 0;
   int r = L;
+  while (r % 8 == 0) {
+    r /= 8;
+    pl->n8++;
+  }
   while (r % 4 == 0) {
     r /= 4;
     pl->n4++;

@@ -72,6 +72,28 @@ struct Dft<T, 4> {
   }
 };
 
+// 8 points: two 4-point transforms of the even and odd inputs, then
+// X_k = E_k + W^k O_k, X_{k+4} = E_k - W^k O_k with W = exp(-i pi/4).
+template <typename T>
+struct Dft<T, 8> {
+  static __device__ __forceinline__ void run(Cx<T>* v) {
+    const T s = T(0.70710678118654752440);
+    Cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    Cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<T, 4>::run(e);
+    Dft<T, 4>::run(o);
+    const Cx<T> t[4] = {o[0],
+                        Cx<T>{s * (o[1].re + o[1].im), s * (o[1].im - o[1].re)},
+                        cmnegi(o[2]),
+                        Cx<T>{s * (o[3].im - o[3].re), -s * (o[3].re + o[3].im)}};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = cadd(e[k], t[k]);
+      v[k + 4] = csub(e[k], t[k]);
+    }
+  }
+};
+
 // Per-thread element budget of one in-place Stockham stage: P * L <= kMaxElems * 256
 // (a 256-thread block holds 32 values per thread; the 1024-thread variants for
 // long lines hold 8).
@@ -120,7 +142,7 @@ __device__ void stockham_stage(Cx<T>* lds, int ls, int L, int P, int Ns, const C
 
 struct FftPlan {
   int L;      // FFT length (2N)
-  int n4, n2, n3;  // number of radix-4, radix-2, radix-3 stages
+  int n8, n4, n2, n3;  // number of radix-8, radix-4, radix-2, radix-3 stages
 };
 
 // Forward FFT of P lines in LDS (natural order in and out).  Callers must
@@ -129,6 +151,10 @@ struct FftPlan {
 template <typename T, int ME>
 __device__ void fft_lines(Cx<T>* lds, int ls, int P, FftPlan pl, const Cx<T>* __restrict__ tw) {
   int Ns = 1;
+  for (int i = 0; i < pl.n8; ++i) {
+    stockham_stage<T, 8, ME>(lds, ls, pl.L, P, Ns, tw);
+    Ns *= 8;
+  }
   for (int i = 0; i < pl.n4; ++i) {
     stockham_stage<T, 4, ME>(lds, ls, pl.L, P, Ns, tw);
     Ns *= 4;
