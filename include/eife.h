@@ -165,10 +165,14 @@ int eife_set_forcing(eife_grid g, double c0, double c1);
 /* Advance the nodal values u (device pointer, in place) by n_steps >= 0
  * uniform steps of the scheme fixed by eife_set_phi, from time t0: step n
  * evaluates f at t0 + n tau (and at t0 + (n + c2) tau for the second EIFE2
- * stage, eq. (2.10)).  u must hold the grid's element count in its dtype.
- * Enqueued on `stream` (a hipStream_t, NULL = default stream); returns
- * after enqueueing.  Errors: EIFE_EINVAL (null u, negative n_steps, unknown
- * f_kind, EX51 with d != 2), EIFE_ESTATE (no eife_set_phi), EIFE_EHIP. */
+ * stage, eq. (2.10); at t0 + (n + c_i) tau for stage i of the three-stage
+ * scheme).  u must hold the grid's element count in its dtype.  Enqueued on
+ * `stream` (a hipStream_t, NULL = default stream); returns after
+ * enqueueing.  Errors: EIFE_EINVAL (null u, negative n_steps, unknown f_kind,
+ * EX51 with d != 2, EIFE_F_TRAVELING_WAVE without eps), EIFE_ESTATE (no
+ * eife_set_phi since the last change of c2 or the nodes), EIFE_EUNSUPPORTED
+ * (a Dirichlet-only f_kind on a periodic grid, the traveling wave with the
+ * nodal load, three stages with the split-BF16 transform), EIFE_EHIP. */
 int eife_step(eife_grid g, void* u, int64_t n_steps, int f_kind, double t0, void* stream);
 
 /* Variable step sizes (Section 2.2 lets the step vary): advance u (device,
