@@ -64,3 +64,18 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(binding, "library_path", lambda: str(tmp_path / "libeife.so"))
     with pytest.raises(RuntimeError):
         binding.load_library()
+
+
+def test_binding_constants_match_the_header():
+    """The Python constants carry the values the header's enumerations give."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "eife.h")).read()
+    vals = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(EIFE_[A-Z0-9_]+)\s*=\s*(-?\d+)", hdr)}
+    from paper_2209_11922_amd import binding as b
+    pairs = {"F_ZERO": "EIFE_F_ZERO", "F_ALLEN_CAHN": "EIFE_F_ALLEN_CAHN", "F_MMS_U2": "EIFE_F_MMS_U2",
+             "F_EX51": "EIFE_F_EX51", "F_CONST": "EIFE_F_CONST", "F_AFFINE_T": "EIFE_F_AFFINE_T",
+             "F_FLORY_HUGGINS": "EIFE_F_FLORY_HUGGINS", "F_TRAVELING_WAVE": "EIFE_F_TRAVELING_WAVE",
+             "BC_DIRICHLET": "EIFE_BC_DIRICHLET", "BC_PERIODIC": "EIFE_BC_PERIODIC",
+             "LOAD_LUMPED": "EIFE_LOAD_LUMPED", "LOAD_NODAL": "EIFE_LOAD_NODAL"}
+    for py, c in pairs.items():
+        assert getattr(b, py) == vals[c], (py, c)
