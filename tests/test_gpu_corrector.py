@@ -45,6 +45,42 @@ def _forward_bf16(p, un, uc):
     return b6[0] + sum(cr.shift(Y, dy, dx) @ W6[t] for t, (dy, dx) in enumerate(cr.TAPS))
 
 
+def _grad_bf16(p, un, uc, uf, s_out):
+    """The reference loss gradient with the kernels' rounding points: activations and the
+    weights of the 32 -> 32 and output layers in BF16 (as in the forward pass), the output
+    layer's data gradient formed with its FP32 weights, and every stored pre-activation
+    gradient dZ rounded to BF16.  Returns the flat gradient (FP64 arithmetic otherwise)."""
+    L = cr.unpack(p)
+    X0 = cr.features(un, uc)
+    W1, b1 = L[0]
+    acts = [X0, _bf16(np.maximum(b1 + sum(cr.shift(X0, dy, dx) @ W1[t] for t, (dy, dx) in enumerate(cr.TAPS)), 0))]
+    for W, b in L[1:1 + cr.N_MID]:
+        Wb = _bf16(W)
+        acts.append(_bf16(np.maximum(b + sum(cr.shift(acts[-1], dy, dx) @ Wb[t].T
+                                             for t, (dy, dx) in enumerate(cr.TAPS)), 0)))
+    W6, b6 = L[-1]
+    Y5 = acts[-1]
+    o = b6[0] + sum(cr.shift(Y5, dy, dx) @ _bf16(W6)[t] for t, (dy, dx) in enumerate(cr.TAPS))
+    c = cr.change_scale(un, uc)[:, None, None]
+    e = o - (np.asarray(uf, np.float64) - np.asarray(uc, np.float64)) / (s_out * c)
+    g = 2.0 * e / e.size
+    grads = [None] * len(L)
+    grads[-1] = (np.stack([np.einsum("byx,byxc->c", g, cr.shift(Y5, dy, dx)) for dy, dx in cr.TAPS]),
+                 np.array([g.sum()]))
+    dY = sum(cr.shift(g[..., None] * W6[t], -dy, -dx) for t, (dy, dx) in enumerate(cr.TAPS))
+    dZ = _bf16(dY * (Y5 > 0))
+    for li in range(cr.N_MID, 0, -1):
+        Yin = acts[li]
+        dW = np.stack([np.einsum("byxo,byxi->oi", dZ, cr.shift(Yin, dy, dx)) for dy, dx in cr.TAPS])
+        grads[li] = (dW, dZ.sum(axis=(0, 1, 2)))
+        Wb = _bf16(L[li][0])
+        dY = sum(cr.shift(dZ @ Wb[t], -dy, -dx) for t, (dy, dx) in enumerate(cr.TAPS))
+        dZ = _bf16(dY * (Yin > 0))
+    grads[0] = (np.stack([np.einsum("byxc,byxo->co", cr.shift(X0, dy, dx), dZ) for dy, dx in cr.TAPS]),
+                dZ.sum(axis=(0, 1, 2)))
+    return cr.pack(grads)
+
+
 def _smooth(rng, B, ny, nx, k=4):
     """Random fields made of the first k x k sine modes (the shape of the
     network's inputs: smooth states and smooth coarse changes)."""
@@ -97,8 +133,13 @@ def test_forward_matches_reference(B, ny, nx):
     ref64, _ = cr.forward(p.astype(np.float64), unf, ucf)
     refbf = _forward_bf16(p.astype(np.float64), unf, ucf)
     e64, ebf = _rel2(got, ref64), _rel2(got, refbf)
-    print(f"forward {B}x{ny}x{nx}: rel 2-norm vs FP64 {e64:.2e}, vs BF16-rounded reference {ebf:.2e}")
+    # element-wise against the rounding-point reference: what remains is FP32 accumulation
+    # order and the rare activation that lands on the other side of a BF16 rounding boundary
+    emax = float(np.max(np.abs(got - refbf)) / np.max(np.abs(refbf)))
+    print(f"forward {B}x{ny}x{nx}: rel 2-norm vs FP64 {e64:.2e}, vs BF16-rounded reference {ebf:.2e}, "
+          f"element-wise max {emax:.2e}")
     assert ebf <= 2e-3
+    assert emax <= 2e-3
     assert e64 <= 2e-2
     c.close()
 
@@ -115,11 +156,18 @@ def test_gradient_matches_reference(B, ny, nx):
     loss, g = c.grad(_dev(un), _dev(uc), _dev(uf))
     f = lambda a: np.float32(a).astype(np.float64)  # noqa: E731
     rloss, rg = cr.loss_and_grad(p.astype(np.float64), f(un), f(uc), f(uf), s)
+    rgb = _grad_bf16(p.astype(np.float64), f(un), f(uc), f(uf), s)
     assert abs(loss - rloss) <= 2e-2 * rloss
     bounds = np.cumsum([0] + cr.SIZES)
     for k, (lo, hi) in enumerate(zip(bounds[:-1], bounds[1:])):
         e = _rel2(g[lo:hi].astype(np.float64), rg[lo:hi])
-        print(f"grad block {k} ({hi - lo} values): rel 2-norm {e:.2e}")
+        eb = _rel2(g[lo:hi].astype(np.float64), rgb[lo:hi])
+        print(f"grad block {k} ({hi - lo} values): rel 2-norm vs FP64 {e:.2e}, vs BF16 rounding points {eb:.2e}")
+        # against the reference that rounds where the kernels round only the FP32
+        # accumulation order and rare rounding-boundary flips remain (measured <= 3.3e-4):
+        # ten times inside the 2e-2 per-layer bound of the BF16 backward
+        assert eb <= 2e-3, k
+        # against plain FP64: the BF16 backward's own error (2^-9 per rounding, six layers deep)
         assert e <= 5e-2, k
     cos = float(np.dot(g, rg) / (np.linalg.norm(g) * np.linalg.norm(rg)))
     assert cos >= 0.999
@@ -200,6 +248,44 @@ def test_infer_step_accepts_and_falls_back():
     for g in (coarse, fine):
         g.close()
     c.close()
+
+
+def test_indicator_matches_oracle_on_trained_network():
+    """The committed network on an unseen 511^2 state: the indicator r and max|u_c + delta|
+    that eife_corr_infer_step reports equal oracle.corrector.indicator evaluated on the
+    same u_n, the coarse step's u_c and the network's delta."""
+    import os
+    from paper_2209_11922_amd import corrector as cor
+    eife = _lib()
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2209_11922_amd",
+                        "weights", "corrector_ac512.npz")
+    p, s_out, theta, guard = cor.load(path)
+    coarse, fine = cor.make_grids(512, 0.02, 0.016, 8)
+    net = eife.Corrector(511, 511, 1)
+    net.set_params(p)
+    net.set_scale(s_out)
+    un = torch.tensor(seeded_inputs.uniform_field(2031, [512, 512]), dtype=torch.float32, device="cuda")
+    fine.step(un, 40, eife.F_ALLEN_CAHN, 0.0)  # past the transient of the random start
+    t = 40 * 0.002
+    for k in range(3):
+        uc = un.clone()
+        coarse.step(uc, 1, eife.F_ALLEN_CAHN, t)
+        delta = net.forward(un, uc)
+        u = un.clone()
+        fb, r, umax = net.infer_step(coarse, fine, u, t, 8, 1e30)
+        torch.cuda.synchronize()
+        a, b, d = (x.cpu().numpy().astype(np.float64) for x in (un, uc, delta))
+        r_ref, umax_ref, _ = cr.indicator(a, b, d)
+        print(f"step {k}: r {r:.9e} (oracle {r_ref:.9e}), max|u| {umax:.9f} (oracle {umax_ref:.9f})")
+        assert not fb and r_ref > 1e-6  # a non-zero correction
+        assert abs(r - r_ref) <= 1e-6 * r_ref
+        assert abs(umax - umax_ref) <= 1e-6 * umax_ref
+        assert torch.equal(u, uc + delta)
+        un = u
+        t += 0.016
+    for g in (coarse, fine):
+        g.close()
+    net.close()
 
 
 def test_corrector_argument_errors():
