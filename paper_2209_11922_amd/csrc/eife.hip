@@ -29,6 +29,7 @@
 #include "eife_kernels.hpp"
 #include "eife_fast.hpp"
 #include "eife_gemm.hpp"
+#include "eife_long.hpp"
 
 using namespace eife;
 
@@ -434,11 +435,30 @@ bool fast_len(int N) {
   return N == 64 || N == 128 || N == 256 || N == 512 || N == 192 || (N == 384 && sizeof(T) == 4);
 }
 
+// Host-side checks of a specialised launch: the argument blocks fit the
+// kernel-argument segment, block sizes are within the limits (a block may be a
+// fraction of a wavefront: one 16-lane line pair), static LDS fits a workgroup
+// (160 KB on gfx950), and the grid is non-empty and within range.  A failed
+// check skips the launch and is reported by launch_row / launch_col.
+static_assert(3 * sizeof(void*) + sizeof(RowGeom) + sizeof(void*) + sizeof(Forcing) + sizeof(void*) <= 1024,
+              "row pass arguments");
+static_assert(2 * sizeof(void*) + sizeof(ColGeom) + sizeof(void*) + sizeof(Diag) + sizeof(void*) <= 1024,
+              "column pass arguments");
+thread_local const char* g_bad_launch = nullptr;
+
+bool launch_shape_ok(dim3 grid, int threads, size_t lds_static) {
+  const bool ok = grid.x >= 1 && grid.y >= 1 && grid.z >= 1 && grid.x <= 0x7fffffffu && grid.y <= 65535u &&
+                  grid.z <= 65535u && threads >= 1 && threads <= 1024 && lds_static <= 160 * 1024;
+  if (!ok) g_bad_launch = "specialised pass launch shape out of range";
+  return ok;
+}
+
 template <typename T, int L, int PB, bool BAT>
 void row_fast_go(int mode, int nrows, int count, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
                  const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
   constexpr int NT = PB * fast::Line<T, L>::LP;
   dim3 grid((nrows + 2 * PB - 1) / (2 * PB), count);
+  if (!launch_shape_ok(grid, NT, size_t(PB) * fast::Line<T, L>::BUF * sizeof(Cx<T>))) return;
   if (mode == ROW_PHYS) {
     if (F.kind == FK_AC)
       hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_PHYS, fast::RK_AC, BAT>), grid, dim3(NT), 0, s, src, dst,
@@ -488,6 +508,7 @@ void col_fast_go(int mode, int pitch, int outer, int count, bool pipe, hipStream
   constexpr int PPW = col_ppw<T, L, PB>();
   constexpr int NT = PB / PPW * fast::Line<T, L>::LP;
   dim3 grid(pitch / (2 * PB), outer, count);
+  if (!launch_shape_ok(grid, NT, size_t(PB) * fast::Line<T, L>::BUF * sizeof(Cx<T>))) return;
   if (mode == COL_PLAIN) {
     if (pipe && !ci) {
       const int ntx = pitch / (2 * PB);
@@ -642,12 +663,62 @@ bool try_col_fast_per(const eife_grid_s* g, int axis, int mode, int outer, int c
   return false;
 }
 
+// Lines of 2048 and 4096 intervals (4096- and 8192-point odd extensions): one
+// line pair per block (eife_long.hpp); single grids, non-periodic.
+inline bool long_len(int N) { return N == 2048 || N == 4096; }
+
+template <typename T, int L>
+void row_long_launch(int mode, int nrows, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
+                     const Cx<T>* tw, const Forcing& F) {
+  constexpr int NT = lng::Shape<L>::NT;
+  const dim3 grid((nrows + 1) / 2);
+  if (!launch_shape_ok(grid, NT, lng::Shape<L>::BUF * sizeof(Cx<T>))) return;
+  if (mode == ROW_PHYS) {
+    if (F.kind == FK_AC)
+      hipLaunchKernelGGL((lng::row_long<T, L, ROW_PHYS, fast::RK_AC>), grid, dim3(NT), 0, s, src, dst, dst2, rg, tw, F);
+    else
+      hipLaunchKernelGGL((lng::row_long<T, L, ROW_PHYS, fast::RK_GENERIC>), grid, dim3(NT), 0, s, src, dst, dst2, rg, tw,
+                         F);
+  } else if (mode == ROW_FWD_USER) {
+    hipLaunchKernelGGL((lng::row_long<T, L, ROW_FWD_USER, fast::RK_GENERIC>), grid, dim3(NT), 0, s, src, dst, dst2, rg,
+                       tw, F);
+  } else {
+    hipLaunchKernelGGL((lng::row_long<T, L, ROW_INV_USER, fast::RK_GENERIC>), grid, dim3(NT), 0, s, src, dst, dst2, rg,
+                       tw, F);
+  }
+}
+
+template <typename T, int L>
+void col_long_launch(int mode, int pitch, int outer, hipStream_t s, T* W, T* H, const ColGeom& cg, const Cx<T>* tw,
+                     const Diag& dg) {
+  constexpr int NT = lng::Shape<L>::NT;
+  const dim3 grid(pitch / 2, outer);
+  if (!launch_shape_ok(grid, NT, lng::Shape<L>::BUF * sizeof(Cx<T>))) return;
+  if (mode == COL_PLAIN)
+    hipLaunchKernelGGL((lng::col_long<T, L, COL_PLAIN>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+  else if (mode == COL_STAGE_A)
+    hipLaunchKernelGGL((lng::col_long<T, L, COL_STAGE_A>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+  else if (mode == COL_STAGE_B)
+    hipLaunchKernelGGL((lng::col_long<T, L, COL_STAGE_B>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+  else
+    hipLaunchKernelGGL((lng::col_long<T, L, COL_ETD1>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+}
+
 template <typename T>
 bool try_row_fast(const eife_grid_s* g, int var, int mode, int count, hipStream_t s, const T* src, T* dst, T* dst2,
                   const RowGeom& rg, const Cx<T>* tw, const Forcing& F, const RowInst<T>* ri) {
   if (g->per[0]) return try_row_fast_per<T>(g, mode, count, s, src, dst, dst2, rg, tw, F, ri);
   // the traveling wave's boundary code runs in the generic row pass only
-  if (g->transform != EIFE_TX_FFT || !fast_len<T>(g->N[0]) || F.kind == FK_EX52) return false;
+  if (g->transform != EIFE_TX_FFT || F.kind == FK_EX52) return false;
+  if (long_len(g->N[0])) {
+    if (count != 1 || ri || (mode != ROW_PHYS && mode != ROW_FWD_USER && mode != ROW_INV_USER)) return false;
+    if (g->N[0] == 2048)
+      row_long_launch<T, 4096>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F);
+    else
+      row_long_launch<T, 8192>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F);
+    return true;
+  }
+  if (!fast_len<T>(g->N[0])) return false;
   switch (g->N[0]) {
     case 64: row_fast_launch<T, 128>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
     case 128: row_fast_launch<T, 256>(var, mode, rg.nrows, count, s, src, dst, dst2, rg, tw, F, ri); return true;
@@ -668,7 +739,16 @@ template <typename T>
 bool try_col_fast(const eife_grid_s* g, int var, int axis, int mode, int outer, int count, hipStream_t s, T* W, T* H,
                   const ColGeom& cg, const Cx<T>* tw, const Diag& dg, const ColInst<T>* ci) {
   if (g->per[axis]) return try_col_fast_per<T>(g, axis, mode, outer, count, s, W, H, cg, tw, dg, ci);
-  if (g->transform != EIFE_TX_FFT || !fast_len<T>(g->N[axis])) return false;
+  if (g->transform != EIFE_TX_FFT) return false;
+  if (long_len(g->N[axis])) {
+    if (count != 1 || ci || mode > COL_ETD1) return false;
+    if (g->N[axis] == 2048)
+      col_long_launch<T, 4096>(mode, g->pitch, outer, s, W, H, cg, tw, dg);
+    else
+      col_long_launch<T, 8192>(mode, g->pitch, outer, s, W, H, cg, tw, dg);
+    return true;
+  }
+  if (!fast_len<T>(g->N[axis])) return false;
   switch (g->N[axis]) {
     case 64: col_fast_launch<T, 128>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
     case 128: col_fast_launch<T, 256>(var, mode, g->pitch, outer, count, s, W, H, cg, tw, dg, ci); return true;
@@ -946,6 +1026,7 @@ int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, i
                                  : (mode == ROW_FWD_USER || mode == ROW_FWD_PHYS) ? EIFE_PASS_ROW_FWD
                                                                                    : EIFE_PASS_ROW_INV, s);
   if (mode == ROW_FWD_PHYS && !fused_first_row<T>(g, F.kind)) return fail(EIFE_EUNSUPPORTED, "fused first row pass");
+  g_bad_launch = nullptr;
   if (!(B.count == 1 && !ri && try_row_gemm<T>(g, mode, s, src, dst, dst2, rg, F)) &&
       !try_row_fast<T>(g, B.var_row, mode, B.count, s, src, dst, dst2, rg, tw, F, ri)) {
     const size_t shm = lds_bytes(g, rg.P, rg.pl.L);
@@ -964,6 +1045,7 @@ int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, i
       else
         row_generic_go<T, false>(mode, grid, shm, s, src, dst, dst2, rg, tw, F, ri);
   }
+  if (g_bad_launch) return fail(EIFE_EINVAL, "%s", g_bad_launch);
   HIP_TRY(hipGetLastError());
   prof_end(g, pidx, s);
   return EIFE_OK;
@@ -1005,6 +1087,7 @@ int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, h
   const int pidx = prof_begin(g, kind, s);
   // the three-stage column passes: specialised (one tile per block) or generic kernels, no matrix-core variant
   const bool s3 = mode >= COL_S3_1;
+  g_bad_launch = nullptr;
   if ((s3 || !(B.count == 1 && !ci && try_col_gemm<T>(g, axis, mode, outer, s, W, H, cg, dg))) &&
       !try_col_fast<T>(g, B.var_col, axis, mode, outer, B.count, s, W, H, cg, tw, dg, ci)) {
     const size_t shm = lds_bytes(g, cg.P, cg.pl.L);
@@ -1023,6 +1106,7 @@ int launch_col(eife_grid_s* g, int axis, int mode, T* W, T* H, const Diag& dg, h
       else
         col_generic_go<T, false>(mode, grid, shm, s, W, H, cg, tw, dg, ci);
   }
+  if (g_bad_launch) return fail(EIFE_EINVAL, "%s", g_bad_launch);
   HIP_TRY(hipGetLastError());
   prof_end(g, pidx, s);
   return EIFE_OK;
@@ -1171,33 +1255,47 @@ NormGeom make_norm_geom(const eife_grid_s* g, int pot = NORM_POT_DOUBLE_WELL) {
   return ng;
 }
 
+// Block partial sums of the norm reduction into `partials` (at most
+// kNormBlocksMax rows of kNormAcc doubles); returns the number of rows in *nb.
 template <typename T>
-int run_norms(eife_grid_s* g, const void* u, const void* uref, hipStream_t s, int pot = NORM_POT_DOUBLE_WELL) {
+int launch_norm_partials(eife_grid_s* g, const void* u, const void* uref, hipStream_t s, int pot, double* partials,
+                         int* nb_out) {
   const NormGeom ng = make_norm_geom(g, pot);
   const int64_t total = int64_t(g->n[0]) * g->n[1] * g->n[2];
-  const int64_t tiles = int64_t((g->n[0] + kNtX - 1) / kNtX) * ((g->n[1] + kNtY - 1) / kNtY);
+  const int64_t wpb = kNwThreads / 64;  // waves per block of the 3D reduction
+  const int nxw = (g->n[0] + kNwOwn - 1) / kNwOwn;
+  const int tiles_y = (g->n[1] + kNwRows - 1) / kNwRows;
   int nb;
-  if (g->d == 3 && tiles <= kNormBlocksMax / 2) {
-    // 3D: tiles of (x, y) columns marching over chunks of z planes: about 2048
-    // blocks, at least 8 planes per chunk (each chunk also loads the plane
-    // before and after it)
+  if (g->d == 3 && int64_t(nxw) * tiles_y <= wpb * kNormBlocksMax) {
+    // 3D: waves of 62 x positions x 4 rows marching over z chunks (up to 16
+    // chunks, as many as the partial rows allow; each also reads the plane
+    // before it)
     const int nz = g->n[2];
-    int64_t want = std::min<int64_t>(kNormBlocksMax / tiles, std::max<int64_t>(1, 2048 / tiles));
-    want = std::min<int64_t>(want, std::max(1, nz / 8));
-    int nzc = int(std::max<int64_t>(1, std::min<int64_t>(nz, want)));
+    const int64_t fit = std::max<int64_t>(1, wpb * (kNormBlocksMax - 8) / (int64_t(nxw) * tiles_y));
+    int nzc = int(std::max<int64_t>(1, std::min<int64_t>({int64_t(nz), 16, fit})));
     const int zc = (nz + nzc - 1) / nzc;
     nzc = (nz + zc - 1) / zc;
-    nb = int(tiles) * nzc;
-    const dim3 grid(unsigned((g->n[0] + kNtX - 1) / kNtX), unsigned((g->n[1] + kNtY - 1) / kNtY), unsigned(nzc));
-    hipLaunchKernelGGL((norm_tile<T>), grid, dim3(kNormThreads), 0, s, static_cast<const T*>(u),
-                       static_cast<const T*>(uref), ng, zc, g->partials);
+    const int64_t ntasks = int64_t(nxw) * tiles_y * nzc;
+    nb = int(((ntasks + wpb - 1) / wpb + 7) / 8 * 8);
+    if (nb > kNormBlocksMax) return fail(EIFE_EINVAL, "norm reduction needs %d partial rows (at most %d)", nb,
+                                         kNormBlocksMax);
+    hipLaunchKernelGGL((norm_waves<T>), dim3(nb), dim3(kNwThreads), 0, s, static_cast<const T*>(u),
+                       static_cast<const T*>(uref), ng, zc, nxw, tiles_y, int(ntasks), partials);
   } else {
     nb = int(std::min<int64_t>(kNormBlocksMax, (total + kNormThreads - 1) / kNormThreads));
     nb = std::max(nb, 1);
     hipLaunchKernelGGL((norm_partial<T>), dim3(nb), dim3(kNormThreads), 0, s, static_cast<const T*>(u),
-                       static_cast<const T*>(uref), ng, g->partials);
+                       static_cast<const T*>(uref), ng, partials);
   }
   HIP_TRY(hipGetLastError());
+  *nb_out = nb;
+  return EIFE_OK;
+}
+
+template <typename T>
+int run_norms(eife_grid_s* g, const void* u, const void* uref, hipStream_t s, int pot = NORM_POT_DOUBLE_WELL) {
+  int nb = 0;
+  RET_IF(launch_norm_partials<T>(g, u, uref, s, pot, g->partials, &nb));
   hipLaunchKernelGGL(norm_final, dim3(1), dim3(kNormFinalThreads), 0, s, g->partials, nb, g->out5);
   HIP_TRY(hipGetLastError());
   return EIFE_OK;

@@ -696,6 +696,21 @@ __device__ __forceinline__ void col_inst_ptrs(const ColInst<T>* insts, T*& W, T*
   dg.D = I.D;
 }
 
+// Block order of the generic column passes: the hardware hands linear block b
+// (x fastest) to XCD b mod 8, so adjacent column pairs -- which share 128-byte
+// lines -- would land on different XCDs and each XCD's L2 would fetch the whole
+// line for a few bytes of it.  Logical block (b mod 8) * (nb / 8) + b / 8 gives
+// every XCD a contiguous run of column pairs instead (a bijection; blocks past
+// the last multiple of 8 keep their index).
+__device__ __forceinline__ void xcd_block(int& bx, int& by) {
+  const int nb = int(gridDim.x * gridDim.y);
+  const int b = int(blockIdx.x + gridDim.x * blockIdx.y);
+  const int q = nb / 8;
+  const int l = b < 8 * q ? (b % 8) * q + b / 8 : b;
+  bx = l % int(gridDim.x);
+  by = l / int(gridDim.x);
+}
+
 template <typename T, int MODE, bool BAT, int NT = 256>
 __global__ void __launch_bounds__(NT) col_pass(T* W, T* H, ColGeom g, const Cx<T>* __restrict__ tw, Diag dg,
                                                 const ColInst<T>* __restrict__ insts) {
@@ -706,8 +721,9 @@ __global__ void __launch_bounds__(NT) col_pass(T* W, T* H, ColGeom g, const Cx<T
   const int L = g.pl.L;
   const int N = L / 2;
   const int P = g.P;
-  const int c0 = blockIdx.x * 2 * P;
-  const int outer = blockIdx.y;
+  int bx, outer;
+  xcd_block(bx, outer);
+  const int c0 = bx * 2 * P;
   const int64_t base = int64_t(outer) * g.ld_outer + c0;
   const T scale = T(1.0 / sqrt(double(L)));
 
@@ -937,8 +953,9 @@ __global__ void __launch_bounds__(NT) col_pass_per(T* W, T* H, ColGeom g, const 
   Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem_raw);
   const int n = g.n;  // = N, the FFT length
   const int P = g.P;
-  const int c0 = blockIdx.x * 2 * P;
-  const int outer = blockIdx.y;
+  int bx, outer;
+  xcd_block(bx, outer);
+  const int c0 = bx * 2 * P;
   const int64_t base = int64_t(outer) * g.ld_outer + c0;
   const T s1 = T(1.0 / sqrt(double(n)));
   for (int i = threadIdx.x; i < P * n; i += blockDim.x) {
@@ -1129,128 +1146,146 @@ __global__ void __launch_bounds__(kNormThreads) norm_partial(const T* __restrict
   if (threadIdx.x < kNormAcc) partials[blockIdx.x * kNormAcc + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// The same five sums with the tensor structure used directly: M = A_z (x) A_y (x)
-// A_x and K_1 = B_z (x) A_y (x) A_x + A_z (x) (A_y (x) B_x + B_y (x) A_x).  A block
-// owns a tile of kNtX x kNtY (x, y) columns and marches over a chunk of z
-// planes.  Per plane the tile with a one-node halo is staged in LDS (e and u,
-// zero outside a Dirichlet boundary, wrapped on periodic axes) and every
-// thread forms the in-plane 9-point sums wA = (A_y (x) A_x) v and wB = (A_y (x)
-// B_x + B_y (x) A_x) v for v = e and v = u; the z coupling comes from the
-// previous and next planes' sums, kept in registers:
-//   (M e)_z = ad wA_z + ao (wA_{z-1} + wA_{z+1}),
-//   (K_1 e)_z = bd wA_z + bo (wA_{z-1} + wA_{z+1}) + ad wB_z + ao (wB_{z-1} + wB_{z+1}).
-// Global reads: one per node and array plus the halo.  Block partials as
-// norm_partial.
-constexpr int kNtX = 64, kNtY = 4;  // kNtX * kNtY = kNormThreads
+// The same five sums for 3D grids, without LDS or barriers: a wavefront covers
+// 64 consecutive x positions (it owns the middle 62; lanes 0 and 63 hold the
+// neighbours x0 - 1 and x0 + 62) of kNwRows rows and marches over a chunk of z
+// planes.  With P_A = A_y (x) A_x and P_B = A_y (x) B_x + B_y (x) A_x applied in
+// the plane, M = A_z (x) P_A, K_1 = B_z (x) P_A + A_z (x) P_B and the symmetry of
+// the z coupling,
+//   e^T M e   = sum_z e_z . (ad_z P_A e_z + 2 ao_z P_A e_{z-1}),
+//   e^T K_1 e = sum_z e_z . (bd_z P_A e_z + 2 bo_z P_A e_{z-1} + ad_z P_B e_z + 2 ao_z P_B e_{z-1}),
+// so a chunk reads one plane before it (none after it) and a lane keeps only the
+// previous plane's in-plane sums.  Per plane a lane loads its column of the rows
+// y0 - 1 .. y0 + kNwRows (the next plane's while it computes this one), takes the
+// x neighbours from the adjacent lanes (DPP shifts) and forms the in-plane sums
+// separably.  Waves are ordered so that the blocks one XCD runs together own
+// neighbouring rows of one z chunk: their shared halo rows come from that XCD's
+// L2 (block b runs on XCD b mod 8).  Block partials as norm_partial; the grid is
+// padded to a multiple of 8 blocks, waves without a task add nothing.
+constexpr int kNwRows = 4;   // rows per wave
+constexpr int kNwOwn = 62;   // x positions a wave owns
+constexpr int kNwThreads = 256;
 
-struct PlaneSums {
-  double eA, eB, uA, uB;
-  double e, u;  // the thread's own node of the plane
-};
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffff), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, (long long)(unsigned(lo)) | ((long long)hi << 32));
+}
+__device__ __forceinline__ double from_lane_below(double x) { return dpp_double<0x138>(x); }  // lane l - 1
+__device__ __forceinline__ double from_lane_above(double x) { return dpp_double<0x130>(x); }  // lane l + 1
 
 template <typename T>
-__global__ void __launch_bounds__(kNormThreads) norm_tile(const T* __restrict__ u, const T* __restrict__ ur,
-                                                          NormGeom g, int zc, double* __restrict__ partials) {
-  constexpr int HX = kNtX + 2, HY = kNtY + 2;
-  constexpr int G = 4;  // planes staged per barrier pair (their loads overlap)
-  __shared__ double te[G][HY][HX], tu[G][HY][HX];
-  __shared__ double red[kNormAcc][kNormThreads];
+__global__ void __launch_bounds__(kNwThreads) norm_waves(const T* __restrict__ u, const T* __restrict__ ur,
+                                                         NormGeom g, int zc, int nxw, int tiles_y, int ntasks,
+                                                         double* __restrict__ partials) {
+  constexpr int KY = kNwRows;
+  __shared__ double red[kNormAcc][kNwThreads];
   double acc[kNormAcc] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const int tx = threadIdx.x % kNtX, ty = threadIdx.x / kNtX;
-  const int x0 = blockIdx.x * kNtX, y0 = blockIdx.y * kNtY;
-  const int ix = x0 + tx, iy = y0 + ty;
-  const bool own = ix < g.n[0] && iy < g.n[1];
-  const int nz = g.n[2];
-  const int z0 = blockIdx.z * zc;
-  const int z1 = min(nz, z0 + zc);
-  const int64_t sy = g.n[0], sz = int64_t(g.n[0]) * g.n[1];
-  // planes p = 0 .. np-1 are z = z0 - 1 .. z1; a z axis of one node couples to
-  // nothing, so there the planes before and after the chunk stay zero
-  const int np = z0 < nz ? z1 - z0 + 2 : 0;
-  PlaneSums prev{0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, cur{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int pg = 0; pg < np; pg += G) {
-    // stage planes pg .. pg+G-1 (wrapped on a periodic z axis; zero outside)
-    for (int k = threadIdx.x; k < G * HX * HY; k += kNormThreads) {
-      const int gp = k / (HX * HY), r = k - gp * (HX * HY);
-      const int hx = r % HX, hy = r / HX;
-      const int p = pg + gp;
-      int z = z0 - 1 + p;
-      if (g.per[2]) z = (z + nz) % nz;
-      const bool zin = p < np && z >= 0 && z < nz && (nz > 1 || (p >= 1 && p <= np - 2));
-      int jx = x0 + hx - 1, jy = y0 + hy - 1;
-      if (g.per[0]) jx = (jx + g.n[0]) % g.n[0];
-      if (g.per[1]) jy = (jy + g.n[1]) % g.n[1];
-      double vu = 0.0, ve = 0.0;
-      if (zin && jx >= 0 && jx < g.n[0] && jy >= 0 && jy < g.n[1]) {
-        const int64_t j = jx + jy * sy + z * sz;
-        vu = double(u[j]);
-        ve = ur ? vu - double(ur[j]) : vu;
-      }
-      tu[gp][hy][hx] = vu;
-      te[gp][hy][hx] = ve;
-    }
-    __syncthreads();
-    for (int gp = 0; gp < G && pg + gp < np; ++gp) {
-      const int p = pg + gp;
-      PlaneSums next{0.0, 0.0, 0.0, 0.0, te[gp][ty + 1][tx + 1], tu[gp][ty + 1][tx + 1]};
+  const int lane = threadIdx.x & 63;
+  const int nb = gridDim.x;
+  const int blk = (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;  // XCD-contiguous block order
+  const int task = blk * (kNwThreads / 64) + (threadIdx.x >> 6);
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  if (task < ntasks) {
+    const int xw = task % nxw;
+    const int rest = task / nxw;
+    const int ty = rest % tiles_y, zi = rest / tiles_y;
+    int x = xw * kNwOwn + lane - 1;
+    const bool own = lane >= 1 && lane <= kNwOwn && x < nx;
+    if (g.per[0]) x = (x + nx) % nx;
+    const bool xin = x >= 0 && x < nx;
+    const int y0 = ty * KY;
+    const int z0 = zi * zc, z1 = min(nz, z0 + zc);
+    const int64_t sy = nx, sz = int64_t(nx) * ny;
+    const double adx = g.ad[0], aox = g.ao[0], bdx = g.bd[0], box = g.bo[0];
+    const double ady = g.ad[1], aoy = g.ao[1], bdy = g.bd[1], boy = g.bo[1];
+    const double adz = g.ad[2], aoz2 = 2.0 * g.ao[2], bdz = g.bd[2], boz2 = 2.0 * g.bo[2];
+    double pA[KY], pB[KY], qA[KY], qB[KY];  // previous plane: P_A e, P_B e, P_A u, P_B u
 #pragma unroll
-      for (int oy = -1; oy <= 1; ++oy) {
-        const double ay = oy ? g.ao[1] : g.ad[1];
-        const double by = oy ? g.bo[1] : g.bd[1];
+    for (int j = 0; j < KY; ++j) pA[j] = pB[j] = qA[j] = qB[j] = 0.0;
+    // rows y0 - 1 .. y0 + KY of plane z at this lane's x (zero outside a Dirichlet boundary)
+    auto load_plane = [&](int z, T (&cu)[KY + 2], T (&cr)[KY + 2]) {
+      int zz = z;
+      if (g.per[2]) zz = (zz + nz) % nz;
+      const bool zin = zz >= 0 && zz < nz;
 #pragma unroll
-        for (int ox = -1; ox <= 1; ++ox) {
-          const double axv = ox ? g.ao[0] : g.ad[0];
-          const double bxv = ox ? g.bo[0] : g.bd[0];
-          const double wa = axv * ay, wb = bxv * ay + axv * by;
-          const double ej = te[gp][ty + 1 + oy][tx + 1 + ox], uj = tu[gp][ty + 1 + oy][tx + 1 + ox];
-          next.eA += wa * ej;
-          next.eB += wb * ej;
-          next.uA += wa * uj;
-          next.uB += wb * uj;
-        }
+      for (int r = 0; r < KY + 2; ++r) {
+        int yy = y0 - 1 + r;
+        if (g.per[1]) yy = (yy + ny) % ny;
+        const bool in = zin && yy >= 0 && yy < ny && xin;
+        const int64_t j = x + yy * sy + int64_t(zz) * sz;
+        cu[r] = in ? u[j] : T(0);
+        cr[r] = (in && ur) ? ur[j] : T(0);
       }
-      // plane p closes the window of the node at z = z0 - 2 + p (planes p - 2, p - 1, p)
-      if (p >= 2 && own) {
-        const double ui = cur.u, ei = cur.e;
-        const double Me = g.ad[2] * cur.eA + g.ao[2] * (prev.eA + next.eA);
-        const double Ke =
-            g.bd[2] * cur.eA + g.bo[2] * (prev.eA + next.eA) + g.ad[2] * cur.eB + g.ao[2] * (prev.eB + next.eB);
-        const double Ku =
-            g.bd[2] * cur.uA + g.bo[2] * (prev.uA + next.uA) + g.ad[2] * cur.uB + g.ao[2] * (prev.uB + next.uB);
-        acc[0] += ei * Me;
-        acc[1] += ei * Ke;
-        acc[2] = fmax(acc[2], fabs(ei));
-        acc[3] += ui * Ku;
-        if (g.pot == NORM_POT_FH) {
-          acc[4] += 0.5 * g.th * ((1.0 + ui) * log1p(ui) + (1.0 - ui) * log1p(-ui)) - 0.5 * g.thc * ui * ui;
-        } else {
-          const double q = ui * ui - 1.0;
-          acc[4] += 0.25 * q * q;
-        }
+    };
+    T cu[KY + 2], cr[KY + 2];
+    load_plane(z0 - 1, cu, cr);
+    for (int z = z0 - 1; z < z1; ++z) {
+      T nu[KY + 2], nr[KY + 2];
+      if (z + 1 < z1) load_plane(z + 1, nu, nr);
+      double sAe[KY + 2], sBe[KY + 2], sAu[KY + 2], sBu[KY + 2];
+#pragma unroll
+      for (int r = 0; r < KY + 2; ++r) {
+        const double uv = double(cu[r]);
+        const double ev = uv - double(cr[r]);
+        const double en = from_lane_below(ev) + from_lane_above(ev);
+        const double un = from_lane_below(uv) + from_lane_above(uv);
+        sAe[r] = fma(aox, en, adx * ev);
+        sBe[r] = fma(box, en, bdx * ev);
+        sAu[r] = fma(aox, un, adx * uv);
+        sBu[r] = fma(box, un, bdx * uv);
       }
-      prev = cur;
-      cur = next;
+#pragma unroll
+      for (int j = 0; j < KY; ++j) {
+        const double nAe = sAe[j] + sAe[j + 2], nAu = sAu[j] + sAu[j + 2];
+        const double wAe = fma(aoy, nAe, ady * sAe[j + 1]);
+        const double wBe = fma(aoy, sBe[j] + sBe[j + 2], fma(ady, sBe[j + 1], fma(boy, nAe, bdy * sAe[j + 1])));
+        const double wAu = fma(aoy, nAu, ady * sAu[j + 1]);
+        const double wBu = fma(aoy, sBu[j] + sBu[j + 2], fma(ady, sBu[j + 1], fma(boy, nAu, bdy * sAu[j + 1])));
+        if (z >= z0 && own && y0 + j < ny) {
+          const double ui = double(cu[j + 1]);
+          const double ei = ui - double(cr[j + 1]);
+          acc[0] = fma(ei, fma(adz, wAe, aoz2 * pA[j]), acc[0]);
+          acc[1] = fma(ei, fma(bdz, wAe, fma(boz2, pA[j], fma(adz, wBe, aoz2 * pB[j]))), acc[1]);
+          acc[2] = fmax(acc[2], fabs(ei));
+          acc[3] = fma(ui, fma(bdz, wAu, fma(boz2, qA[j], fma(adz, wBu, aoz2 * qB[j]))), acc[3]);
+          if (g.pot == NORM_POT_FH) {
+            acc[4] += 0.5 * g.th * ((1.0 + ui) * log1p(ui) + (1.0 - ui) * log1p(-ui)) - 0.5 * g.thc * ui * ui;
+          } else {
+            const double q = ui * ui - 1.0;
+            acc[4] = fma(0.25 * q, q, acc[4]);
+          }
+        }
+        pA[j] = wAe;
+        pB[j] = wBe;
+        qA[j] = wAu;
+        qB[j] = wBu;
+      }
+#pragma unroll
+      for (int r = 0; r < KY + 2; ++r) {
+        cu[r] = nu[r];
+        cr[r] = nr[r];
+      }
     }
-    __syncthreads();  // the planes are restaged by the next group
   }
 #pragma unroll
   for (int k = 0; k < kNormAcc; ++k) red[k][threadIdx.x] = acc[k];
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+  for (int h = kNwThreads / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
 #pragma unroll
       for (int k = 0; k < kNormAcc; ++k) {
         if (k == 2)
-          red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+          red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + h]);
         else
-          red[k][threadIdx.x] += red[k][threadIdx.x + s];
+          red[k][threadIdx.x] += red[k][threadIdx.x + h];
       }
     }
     __syncthreads();
   }
-  if (threadIdx.x < kNormAcc)
-    partials[((int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * kNormAcc + threadIdx.x] =
-        red[threadIdx.x][0];
+  if (threadIdx.x < kNormAcc) partials[int64_t(blockIdx.x) * kNormAcc + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Second level: 256 threads stride over the block partials, then a fixed-order

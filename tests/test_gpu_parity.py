@@ -221,6 +221,31 @@ def test_norms_match_oracle_across_z_chunks(dtype):
     assert en == pytest.approx(norms.allen_cahn_energy(N, h, 0.01, a64), rel=1e-12)
 
 
+@pytest.mark.parametrize("N,dtype", [([256, 48, 36], "f32"), ([256, 48, 36], "f64"), ([64, 9, 2], "f64"),
+                                     ([384, 12, 8], "f32")])
+def test_norms_row_tiles_and_fallback(N, dtype):
+    """3D norms with full-row tiles (rows of at most 256 nodes; a partial last row tile,
+    an odd z count, a single z plane) and the column-tile reduction for longer rows."""
+    eife = _lib()
+    h = [1.0 / n for n in N]
+    D = 0.013
+    g = eife.Grid(N, h, D, dtype)
+    a = seeded_inputs.uniform_field(15, N)
+    b = seeded_inputs.uniform_field(16, N)
+    ta = torch.tensor(a, dtype=g.torch_dtype, device="cuda")
+    tb = torch.tensor(b, dtype=g.torch_dtype, device="cuda")
+    a64, b64 = ta.double().cpu().numpy(), tb.double().cpu().numpy()
+    l2, h1, mx, en = g.norms(ta, tb)
+    l2u = g.norms(ta)[0]
+    g.close()
+    rl2, rh1, rmx = norms.discrete_norms(N, h, a64 - b64)
+    assert l2 == pytest.approx(rl2, rel=1e-12)
+    assert h1 == pytest.approx(rh1, rel=1e-12)
+    assert mx == pytest.approx(rmx, rel=1e-15)
+    assert en == pytest.approx(norms.allen_cahn_energy(N, h, D, a64), rel=1e-12)
+    assert l2u == pytest.approx(norms.discrete_norms(N, h, a64)[0], rel=1e-12)
+
+
 def test_runs_on_a_side_stream():
     eife = _lib()
     N = [64, 64]
@@ -287,6 +312,12 @@ FAST_GRIDS = [
     _case("1d-512", [512]),
     _case("2d-192x384-radix3", [192, 384]),
     _case("3d-192x64x48-radix3", [192, 64, 48]),
+    # long lines (one line pair per block): x and last axis of 2048 and 4096 intervals,
+    # a 3D grid with a long mid axis (generic there) and a long last axis
+    _case("2d-2048x16-long", [2048, 16]),
+    _case("2d-24x4096-long", [24, 4096]),
+    _case("3d-4096x6x8-long", [4096, 6, 8]),
+    _case("3d-12x8x2048-long", [12, 8, 2048]),
 ]
 
 
