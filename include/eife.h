@@ -207,6 +207,21 @@ int eife_step_variable(eife_grid g, void* u, const double* taus, int64_t n_steps
  * finite. */
 int eife_norms(eife_grid g, const void* u, const void* uref, double* out, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): eife_norms with its result left in
+ * device memory and no allocation of any kind.  Enqueues the same reduction
+ * on `stream` and writes out_dev[0..3] (a device array of 4 doubles owned by
+ * the caller) with the values eife_norms returns; does not wait for the
+ * device.  The block partial sums go to a fixed device array of the library
+ * (8192 rows of 5 doubles = 320 KB per GPU, held until the process ends;
+ * grids whose reduction would need more rows are rejected with EIFE_EINVAL,
+ * none do today) which every call on that GPU shares: calls that overlap in
+ * time on one GPU (other streams, other threads) race and must be ordered by
+ * the caller.  The grid must live on the current device.  Non-finite values
+ * are written as they are (no EIFE_ENONFINITE).
+ * Errors: EIFE_EINVAL (null pointers, another current device), EIFE_EHIP. */
+int eife_norms_noalloc(eife_grid g, const void* u, const void* uref, double* out_dev, void* stream);
+
 /* Discrete energy of the nodal values u (device array in the grid's layout
  * and dtype) for the reaction f_kind, f = -F'(u):
  *   out[0] = (D/2) u^T K_1 u + prod(h) sum_i F(u_i)

@@ -52,6 +52,7 @@ def load_library():
     lib.eife_set_transform.argtypes = [c_void_p, c_int]
     lib.eife_step.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_int, c_double, c_void_p]
     lib.eife_norms.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]
+    lib.eife_norms_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.eife_set_nodes3.argtypes = [c_void_p, c_double, c_double]
     lib.eife_step_variable.argtypes = [c_void_p, c_void_p, ctypes.POINTER(c_double), ctypes.c_int64, c_int,
                                        c_double, c_void_p]
@@ -219,6 +220,23 @@ class Grid:
         code = self._lib.eife_norms(self._g, ctypes.c_void_p(u.data_ptr()), ref, out, _stream_ptr(stream))
         _check(self._lib, code)
         return tuple(out)
+
+    def norms_noalloc(self, u, uref=None, out=None, stream=None):
+        """eife_norms_noalloc: the four values of norms() left in `out`, a float64 CUDA
+        tensor of 4 elements (created when None); enqueued on the stream, no wait."""
+        self._check_array(u, "u")
+        ref = None
+        if uref is not None:
+            self._check_array(uref, "uref")
+            ref = ctypes.c_void_p(uref.data_ptr())
+        if out is None:
+            out = torch.empty(4, dtype=torch.float64, device=u.device)
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() < 4 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 CUDA tensor of at least 4 elements")
+        code = self._lib.eife_norms_noalloc(self._g, ctypes.c_void_p(u.data_ptr()), ref,
+                                            ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+        _check(self._lib, code)
+        return out
 
     def energy(self, u, f_kind, stream=None):
         """Discrete energy (D/2) u^T K_1 u + prod(h) sum F(u_i) of the reaction f_kind, in double."""

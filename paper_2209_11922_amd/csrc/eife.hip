@@ -21,6 +21,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1301,6 +1302,30 @@ int run_norms(eife_grid_s* g, const void* u, const void* uref, hipStream_t s, in
   return EIFE_OK;
 }
 
+// Scratch of eife_norms_noalloc: the block partial rows of the reduction in a
+// file-scope device array (320 KB on every GPU the library runs on, held until
+// the process ends).  Host code never passes the array's name to a kernel: it
+// uses the per-device address from hipGetSymbolAddress.  Calls that overlap on
+// one GPU share the array and race.
+static __device__ __align__(256) double scratch[kNormBlocksMax * kNormAcc];
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Address of the scratch array on `dev` (the current device), resolved once per device.
+int scratch_on(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(EIFE_EUNSUPPORTED, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(EIFE_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<double*>(g_scratch_ptr[dev]);
+  return EIFE_OK;
+}
+
 int check_grid(eife_grid g) {
   if (!g) return fail(EIFE_EINVAL, "null grid");
   return EIFE_OK;
@@ -1385,6 +1410,13 @@ int eife_create_grid(int d, const int32_t* N, const double* h, double D, int bc,
     return fail(EIFE_EHIP, "no HIP device");
   }
   g->device = dev;
+  {
+    double* sp = nullptr;  // the no-allocation reduction's scratch on this device, resolved at set-up
+    if (scratch_on(dev, &sp) != EIFE_OK) {
+      delete g;
+      return EIFE_EHIP;
+    }
+  }
   int maxlds = 65536;
   if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxlds = 65536;
   g->max_lds = size_t(maxlds);
@@ -1631,6 +1663,25 @@ int eife_norms(eife_grid g, const void* u, const void* uref, double* out, void* 
   out[3] = 0.5 * g->D * r[3] + cellvol * r[4];
   for (int k = 0; k < 4; ++k)
     if (!std::isfinite(out[k])) return fail(EIFE_ENONFINITE, "norm %d is not finite", k);
+  return EIFE_OK;
+}
+
+int eife_norms_noalloc(eife_grid g, const void* u, const void* uref, double* out_dev, void* stream) {
+  RET_IF(check_grid(g));
+  if (!u || !out_dev) return fail(EIFE_EINVAL, "u and out_dev must not be null");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != g->device) return fail(EIFE_EINVAL, "the grid lives on device %d, the current device is %d", g->device, dev);
+  double* part = nullptr;
+  RET_IF(scratch_on(dev, &part));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int nb = 0;
+  RET_IF(g->dtype == EIFE_F32 ? launch_norm_partials<float>(g, u, uref, s, NORM_POT_DOUBLE_WELL, part, &nb)
+                              : launch_norm_partials<double>(g, u, uref, s, NORM_POT_DOUBLE_WELL, part, &nb));
+  double cellvol = 1.0;
+  for (int a = 0; a < g->d; ++a) cellvol *= g->h[a];
+  hipLaunchKernelGGL(norm_finish, dim3(1), dim3(kNormFinalThreads), 0, s, part, nb, g->D, cellvol, out_dev);
+  HIP_TRY(hipGetLastError());
   return EIFE_OK;
 }
 

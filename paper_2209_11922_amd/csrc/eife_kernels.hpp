@@ -1315,4 +1315,36 @@ __global__ void __launch_bounds__(kNormFinalThreads) norm_final(const double* __
   if (t < kNormAcc) out5[t] = red[t][0];
 }
 
+// norm_final's reduction followed by the finishing arithmetic of eife_norms on
+// the device: out4 = (||e||_0, ||e||_1, max|e|, energy) with ||e||_0^2 = e^T M e,
+// ||e||_1^2 = e^T M e + e^T K_1 e and energy = (D/2) u^T K_1 u + cellvol sum F(u_i).
+__global__ void __launch_bounds__(kNormFinalThreads) norm_finish(const double* __restrict__ partials, int nblocks,
+                                                                 double D, double cellvol, double* __restrict__ out4) {
+  __shared__ double red[kNormAcc][kNormFinalThreads];
+  const int t = threadIdx.x;
+  double s[kNormAcc] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = t; b < nblocks; b += kNormFinalThreads)
+#pragma unroll
+    for (int k = 0; k < kNormAcc; ++k) {
+      const double v = partials[b * kNormAcc + k];
+      s[k] = (k == 2) ? fmax(s[k], v) : s[k] + v;
+    }
+#pragma unroll
+  for (int k = 0; k < kNormAcc; ++k) red[k][t] = s[k];
+  __syncthreads();
+  for (int h = kNormFinalThreads / 2; h > 0; h >>= 1) {
+    if (t < h)
+#pragma unroll
+      for (int k = 0; k < kNormAcc; ++k)
+        red[k][t] = (k == 2) ? fmax(red[k][t], red[k][t + h]) : red[k][t] + red[k][t + h];
+    __syncthreads();
+  }
+  if (t == 0) {
+    out4[0] = sqrt(fmax(red[0][0], 0.0));
+    out4[1] = sqrt(fmax(red[0][0] + red[1][0], 0.0));
+    out4[2] = red[2][0];
+    out4[3] = 0.5 * D * red[3][0] + cellvol * red[4][0];
+  }
+}
+
 }  // namespace eife
