@@ -118,21 +118,33 @@ def settle(torch, g, u, f_kind, seconds=SETTLE_S, chunk=50):
 
 
 def reduction_rate(torch, g, u, ndof, calls=10):
-    """The FP64 norm and energy reduction (eife_norms) on the benchmark grid against a second
-    array: wall time per call (it returns the four values to the host) and the algorithmic
-    rate, two FP32 arrays read once."""
+    """The FP64 norm and energy reduction on the benchmark grid against a second array: the
+    device time per call (eife_norms_noalloc, values left in device memory, event-timed on
+    the stream it runs on), the wall time of eife_norms (it returns the four values to the
+    host) and the algorithmic rate, two FP32 arrays read once."""
     ref = torch.zeros_like(u)
     g.norms(u, ref)
+    out = torch.empty(4, dtype=torch.float64, device=u.device)
+    stream = torch.cuda.current_stream()
+    g.norms_noalloc(u, ref, out, stream)
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(calls):
+        g.norms_noalloc(u, ref, out, stream)
+    e1.record(stream)
+    e1.synchronize()
+    dev = e0.elapsed_time(e1) * 1e-3 / calls
     t0 = time.perf_counter()
     for _ in range(calls):
         vals = g.norms(u, ref)
     dt = (time.perf_counter() - t0) / calls
-    gbs = 2 * 4 * ndof / dt / 1e9
-    log(f"bench: eife_norms {dt * 1e6:.1f} us per call (host round trip included), {gbs:.1f} GB/s algorithmic "
-        f"({gbs / HBM_PEAK_GBS * 100:.1f}% of HBM peak)")
+    gbs = 2 * 4 * ndof / dev / 1e9
+    log(f"bench: norms {dev * 1e6:.1f} us per call on the device, {gbs:.1f} GB/s algorithmic "
+        f"({gbs / HBM_PEAK_GBS * 100:.1f}% of HBM peak); {dt * 1e6:.1f} us with the host round trip")
     del ref
-    return {"us_per_call": round(dt * 1e6, 1), "alg_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+    return {"us_per_call": round(dev * 1e6, 1), "us_per_call_host_round_trip": round(dt * 1e6, 1),
+            "alg_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
             "bytes_per_call": 2 * 4 * ndof, "values": list(vals)}
 
 
@@ -158,6 +170,30 @@ def accuracy_vs_f64(torch, eife, u0, N, h, D, steps):
     log(f"bench: after {steps} steps, rel max error vs FP64: FFT FP32 {out['fft_f32']:.2e}, "
         f"split-BF16 GEMM {out['gemm_bf16x3']:.2e}")
     return out
+
+
+def f64_rate(torch, eife, u0, N, h, D, steps, settle_s):
+    """The same 255^3 problem in FP64 (the paper's precision): event-free wall timing of
+    `steps` steps after a settle and 5 warm-up steps, with the step's algorithmic HBM rate
+    (every pass reads and writes FP64 arrays: twice the FP32 bytes, 160 B/DoF)."""
+    g = eife.Grid(N, h, D, "f64")
+    g.set_phi(TAU, 2)
+    u = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    if settle_s > 0:
+        settle(torch, g, u, eife.F_ALLEN_CAHN, min(settle_s, 0.5))
+    g.step(u, 5, eife.F_ALLEN_CAHN, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(u, steps, eife.F_ALLEN_CAHN, 5 * TAU)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    g.close()
+    ndof = int(np.prod([n - 1 for n in N]))
+    gbs = 160 * ndof / dt / 1e9
+    log(f"bench: FP64 {dt * 1e3:.3f} ms/step, {ndof / dt:.4e} DoF-steps/s, {gbs:.1f} GB/s algorithmic "
+        f"({gbs / HBM_PEAK_GBS * 100:.1f}% of HBM peak)")
+    return {"ms_per_step": round(dt * 1e3, 4), "dof_steps_per_s": ndof / dt, "bytes_per_dof": 160,
+            "alg_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "steps": steps}
 
 
 def corrector_comparison(nseeds):
@@ -733,6 +769,9 @@ def main():
     ap.add_argument("--no-corrector", action="store_true",
                     help="skip the learned-corrector comparison (2D Allen-Cahn 511^2, plain vs corrected EIFE2)")
     ap.add_argument("--corr-seeds", type=int, default=10, help="unseen seeds of the corrector comparison (a plain step must meet the bound on all of them)")
+    ap.add_argument("--settle", type=float, default=SETTLE_S,
+                    help="seconds of untimed stepping before the warm-up (0 for counter runs, which record "
+                         "every dispatch)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain device copy of one work array's size (counter calibration)")
     args = ap.parse_args()
@@ -784,8 +823,8 @@ def main():
     g.set_phi(TAU, 2)
     u = torch.tensor(u0, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
-    settled = settle(torch, g, u, eife.F_ALLEN_CAHN)
-    log(f"bench: settle {settled} untimed steps on a scratch copy ({SETTLE_S:.1f} s)")
+    settled = settle(torch, g, u, eife.F_ALLEN_CAHN, args.settle) if args.settle > 0 else 0
+    log(f"bench: settle {settled} untimed steps on a scratch copy ({args.settle:.1f} s)")
     if args.warmup > 0:
         g.step(u, args.warmup, eife.F_ALLEN_CAHN, 0.0)
     torch.cuda.synchronize()
@@ -814,7 +853,8 @@ def main():
     log(f"bench: plain device copy {copy_gbs:.1f} GB/s ({copy_gbs / HBM_PEAK_GBS * 100:.1f}% of HBM peak)")
 
     # per-pass event timing over a second run of the same K steps
-    settle(torch, g, u, eife.F_ALLEN_CAHN, 0.3)
+    if args.settle > 0:
+        settle(torch, g, u, eife.F_ALLEN_CAHN, min(args.settle, 0.3))
     g.profile(True)
     g.step(u, args.steps, eife.F_ALLEN_CAHN, t_start + args.steps * TAU)
     prof = g.profile_read()
@@ -854,6 +894,7 @@ def main():
     g.close()
     del u
     acc = accuracy_vs_f64(torch, eife, u0, N, h, D, args.steps)
+    f64 = None if gemm else f64_rate(torch, eife, u0, N, h, D, args.steps, args.settle)
 
     corr = None
     if not args.no_corrector and not gemm:
@@ -873,6 +914,7 @@ def main():
                                   + ("split-BF16 matrix-core sine transforms" if gemm else "FP32 sine-transform path"),
                       "dofs": ndof, "tau": TAU, "scheme": "EIFE2", "transform": args.transform},
            "roofline": roof, "cpu_baseline": cpu, "accuracy": acc, "corrector": corr, "reductions": red,
+           "f64": f64,
            # the paper's only timings (Table 3), another workload on other hardware: context only
            "paper_timings": {"table": "Table 3, Example 5.1 (2D), EIFE2, N_T = 50, FP64",
                              "hardware": "Matlab on an Intel i5-8250U 1.8 GHz laptop, 8 GB",

@@ -1280,8 +1280,13 @@ int launch_norm_partials(eife_grid_s* g, const void* u, const void* uref, hipStr
     nb = int(((ntasks + wpb - 1) / wpb + 7) / 8 * 8);
     if (nb > kNormBlocksMax) return fail(EIFE_EINVAL, "norm reduction needs %d partial rows (at most %d)", nb,
                                          kNormBlocksMax);
-    hipLaunchKernelGGL((norm_waves<T>), dim3(nb), dim3(kNwThreads), 0, s, static_cast<const T*>(u),
-                       static_cast<const T*>(uref), ng, zc, nxw, tiles_y, int(ntasks), partials);
+    const bool gen = ng.pot == NORM_POT_FH || ng.per[0] || ng.per[1] || ng.per[2];
+    if (gen)
+      hipLaunchKernelGGL((norm_waves<T, true>), dim3(nb), dim3(kNwThreads), 0, s, static_cast<const T*>(u),
+                         static_cast<const T*>(uref), ng, zc, nxw, tiles_y, int(ntasks), partials);
+    else
+      hipLaunchKernelGGL((norm_waves<T, false>), dim3(nb), dim3(kNwThreads), 0, s, static_cast<const T*>(u),
+                         static_cast<const T*>(uref), ng, zc, nxw, tiles_y, int(ntasks), partials);
   } else {
     nb = int(std::min<int64_t>(kNormBlocksMax, (total + kNormThreads - 1) / kNormThreads));
     nb = std::max(nb, 1);

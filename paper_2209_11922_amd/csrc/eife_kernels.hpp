@@ -1176,7 +1176,9 @@ __device__ __forceinline__ double dpp_double(double x) {
 __device__ __forceinline__ double from_lane_below(double x) { return dpp_double<0x138>(x); }  // lane l - 1
 __device__ __forceinline__ double from_lane_above(double x) { return dpp_double<0x130>(x); }  // lane l + 1
 
-template <typename T>
+// GEN = false: Dirichlet axes and the double-well potential only (fewer
+// registers, three waves per SIMD); GEN = true: periodic axes and either potential.
+template <typename T, bool GEN>
 __global__ void __launch_bounds__(kNwThreads) norm_waves(const T* __restrict__ u, const T* __restrict__ ur,
                                                          NormGeom g, int zc, int nxw, int tiles_y, int ntasks,
                                                          double* __restrict__ partials) {
@@ -1194,7 +1196,7 @@ __global__ void __launch_bounds__(kNwThreads) norm_waves(const T* __restrict__ u
     const int ty = rest % tiles_y, zi = rest / tiles_y;
     int x = xw * kNwOwn + lane - 1;
     const bool own = lane >= 1 && lane <= kNwOwn && x < nx;
-    if (g.per[0]) x = (x + nx) % nx;
+    if (GEN && g.per[0]) x = (x + nx) % nx;
     const bool xin = x >= 0 && x < nx;
     const int y0 = ty * KY;
     const int z0 = zi * zc, z1 = min(nz, z0 + zc);
@@ -1208,12 +1210,12 @@ __global__ void __launch_bounds__(kNwThreads) norm_waves(const T* __restrict__ u
     // rows y0 - 1 .. y0 + KY of plane z at this lane's x (zero outside a Dirichlet boundary)
     auto load_plane = [&](int z, T (&cu)[KY + 2], T (&cr)[KY + 2]) {
       int zz = z;
-      if (g.per[2]) zz = (zz + nz) % nz;
+      if (GEN && g.per[2]) zz = (zz + nz) % nz;
       const bool zin = zz >= 0 && zz < nz;
 #pragma unroll
       for (int r = 0; r < KY + 2; ++r) {
         int yy = y0 - 1 + r;
-        if (g.per[1]) yy = (yy + ny) % ny;
+        if (GEN && g.per[1]) yy = (yy + ny) % ny;
         const bool in = zin && yy >= 0 && yy < ny && xin;
         const int64_t j = x + yy * sy + int64_t(zz) * sz;
         cu[r] = in ? u[j] : T(0);
@@ -1251,7 +1253,7 @@ __global__ void __launch_bounds__(kNwThreads) norm_waves(const T* __restrict__ u
           acc[1] = fma(ei, fma(bdz, wAe, fma(boz2, pA[j], fma(adz, wBe, aoz2 * pB[j]))), acc[1]);
           acc[2] = fmax(acc[2], fabs(ei));
           acc[3] = fma(ui, fma(bdz, wAu, fma(boz2, qA[j], fma(adz, wBu, aoz2 * qB[j]))), acc[3]);
-          if (g.pot == NORM_POT_FH) {
+          if (GEN && g.pot == NORM_POT_FH) {
             acc[4] += 0.5 * g.th * ((1.0 + ui) * log1p(ui) + (1.0 - ui) * log1p(-ui)) - 0.5 * g.thc * ui * ui;
           } else {
             const double q = ui * ui - 1.0;
