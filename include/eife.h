@@ -357,6 +357,13 @@ int eife_corr_set_scale(eife_corr c, double s_out);
 /* delta = s_out * c * o(un, uc) for `batch` images (c per image, as above). */
 int eife_corr_forward(eife_corr c, const float* un, const float* uc, float* delta, int batch, void* stream);
 
+/* Inference path of eife_corr_forward, eife_corr_infer_step and eife_corr_run:
+ * fused != 0 (the default) runs all six layers in one kernel over 16 x 32 node
+ * tiles with the activations in on-chip memory; fused = 0 runs one kernel per
+ * layer with the activations in device memory (the training path's forward).
+ * Both give the same delta bit for bit.  Errors: EIFE_EINVAL (null corrector). */
+int eife_corr_set_fused(eife_corr c, int fused);
+
 /* Loss = mean over the batch's nodes of (o - (uf - uc) / (s_out c))^2 and its
  * gradient in the parameters, copied to grad_host (EIFE_CORR_PARAMS floats);
  * *loss (if loss is not NULL) receives the loss.  Blocks the host. */

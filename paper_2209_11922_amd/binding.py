@@ -75,6 +75,7 @@ def load_library():
     lib.eife_corr_get_params.argtypes = [c_void_p, f32p, ctypes.c_int64]
     lib.eife_corr_set_scale.argtypes = [c_void_p, c_double]
     lib.eife_corr_set_guard.argtypes = [c_void_p, c_double]
+    lib.eife_corr_set_fused.argtypes = [c_void_p, c_int]
     lib.eife_corr_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]
     lib.eife_corr_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, f32p, ctypes.POINTER(c_double),
                                    c_void_p]
@@ -87,8 +88,8 @@ def load_library():
     lib.eife_corr_last_error.restype = ctypes.c_char_p
     lib.eife_corr_last_error.argtypes = []
     for name in ("eife_corr_create", "eife_corr_destroy", "eife_corr_set_params", "eife_corr_get_params",
-                 "eife_corr_set_scale", "eife_corr_set_guard", "eife_corr_forward", "eife_corr_grad", "eife_corr_train_step",
-                 "eife_corr_infer_step", "eife_corr_run"):
+                 "eife_corr_set_scale", "eife_corr_set_guard", "eife_corr_set_fused", "eife_corr_forward",
+                 "eife_corr_grad", "eife_corr_train_step", "eife_corr_infer_step", "eife_corr_run"):
         getattr(lib, name).restype = c_int
     lib.eife_last_error.restype = ctypes.c_char_p
     lib.eife_last_error.argtypes = []
@@ -375,6 +376,10 @@ class Corrector:
 
     def set_guard(self, max_change_rms):
         _ccheck(self._lib, self._lib.eife_corr_set_guard(self._c, float(max_change_rms)))
+
+    def set_fused(self, fused):
+        """Inference through the one-kernel network (True, default) or one kernel per layer."""
+        _ccheck(self._lib, self._lib.eife_corr_set_fused(self._c, 1 if fused else 0))
 
     def forward(self, un, uc, delta=None, stream=None):
         if delta is None:

@@ -93,11 +93,14 @@ __global__ void __launch_bounds__(256) change_final(const double* __restrict__ p
 
 // ---------------------------------------------------------------------------
 // Input layer (FP32): Y1 = relu(b1 + sum_t sum_c W1[t][c][:] X0[p + off_t][c]),
-// X0 = (u_c, (u_c - u_n) / c_b).  One thread per node.
+// X0 = (u_c, (u_c - u_n) / c_b).  One thread per node; the 608 weights and
+// biases are staged in LDS and read at one address per wave (broadcast).
 __global__ void __launch_bounds__(256) conv_in_fwd(const float* __restrict__ un, const float* __restrict__ uc,
                                                    const float* __restrict__ cs, const float* __restrict__ prm,
                                                    __bf16* __restrict__ Y, int nx, int ny, int64_t npix) {
-  // the weights are read at uniform addresses (scalar loads, no LDS traffic)
+  __shared__ __attribute__((aligned(16))) float w[SZ_L1];
+  for (int i = threadIdx.x; i < SZ_L1; i += blockDim.x) w[i] = prm[i];
+  __syncthreads();
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= npix) return;
   const int x = int(p % nx);
@@ -113,18 +116,26 @@ __global__ void __launch_bounds__(256) conv_in_fwd(const float* __restrict__ un,
     a[t] = vc;
     d[t] = (vc - vn) * rc;
   }
+  float acc[C];
+#pragma unroll
+  for (int o = 0; o < C; ++o) acc[o] = w[SZ_W1 + o];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const f32x4* wa = reinterpret_cast<const f32x4*>(w + (t * 2) * C);
+    const f32x4* wd = reinterpret_cast<const f32x4*>(w + (t * 2 + 1) * C);
+#pragma unroll
+    for (int v = 0; v < C / 4; ++v) {
+      const f32x4 ka = wa[v], kd = wd[v];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[4 * v + j] = fmaf(a[t], ka[j], fmaf(d[t], kd[j], acc[4 * v + j]));
+    }
+  }
   bf16x8* dst = reinterpret_cast<bf16x8*>(Y + p * C);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     bf16x8 h;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int o = 8 * v + j;
-      float acc = prm[SZ_W1 + o];
-#pragma unroll
-      for (int t = 0; t < 9; ++t) acc = fmaf(a[t], prm[(t * 2) * C + o], fmaf(d[t], prm[(t * 2 + 1) * C + o], acc));
-      h[j] = __bf16(fmaxf(acc, 0.f));
-    }
+    for (int j = 0; j < 8; ++j) h[j] = __bf16(fmaxf(acc[8 * v + j], 0.f));
     dst[v] = h;
   }
 }
@@ -569,6 +580,251 @@ __global__ void __launch_bounds__(256) copy2(const float* __restrict__ u, float*
 }
 
 // ---------------------------------------------------------------------------
+// The whole network on one output tile of kFr x kFx nodes (inference).  The
+// input layer and the four 32 -> 32 layers write their outputs to LDS over
+// regions that shrink by one node per side and layer (halo 5, 4, 3, 2, 1 around
+// the tile); the output layer reads the last of them.  Every node's arithmetic
+// is that of conv_in_fwd and conv_patch (the same fragments, tap order and
+// roundings), so the result equals the layer-by-layer path bit for bit; nodes
+// outside the grid hold zeros, the zero padding of the next layer.
+// LDS (158 KB, one block per CU): activation buffers A (halo 5 region) and B
+// (halo 4 region), 64 bytes per node with the four 16-byte channel chunks
+// XOR-swizzled by node (16 consecutive nodes read one chunk conflict-free); the
+// input region (u_c, (u_c - u_n) / c_b) and the input layer's FP32 weights,
+// later the block's reduction rows; the current layer's BF16 weights.
+//   FUSED_INFER  out = delta
+//   FUSED_APPLY  out = u_c + delta, block sums of delta^2, (u_c - u_n)^2 and
+//                max |out| in part[3 block ..] (block = tile + tiles * image)
+enum { FUSED_INFER = 0, FUSED_APPLY = 1 };
+constexpr int kFr = 16, kFx = 32;  // output tile: rows x nodes
+constexpr int kFthreads = 512;
+constexpr int kFwaves = kFthreads / 64;
+constexpr int fused_nodes(int h) { return (kFr + 2 * h) * (kFx + 2 * h); }
+constexpr int kFnA = fused_nodes(5), kFnB = fused_nodes(4), kFnC = fused_nodes(6);
+constexpr int kFbytesA = kFnA * 64, kFbytesB = kFnB * 64;
+constexpr int kFbytesC = kFnC * 8 + SZ_L1 * 4;  // input region + input-layer weights
+constexpr int kFbytesW = SZ_WM * 2;               // one 32 -> 32 layer, BF16
+constexpr int kFbytes = kFbytesA + kFbytesB + kFbytesC + kFbytesW;
+static_assert(kFbytesC >= 3 * kFthreads * 8, "reduction rows alias the input region");
+static_assert(kFbytes <= 160 * 1024, "fused network tile exceeds the LDS");
+static_assert(kFbytesA % 16 == 0 && kFbytesB % 16 == 0 && kFbytesC % 16 == 0, "LDS carve alignment");
+
+// element offset of channel chunk k (8 channels) of node n in an activation buffer
+__device__ __forceinline__ int fsw(int n, int k) { return n * C + ((k ^ ((n >> 2) & 3)) << 3); }
+
+// copy `bytes` (a multiple of 16) from global to LDS, all threads of the block
+__device__ __forceinline__ void fused_stage(const void* __restrict__ src, void* dst, int bytes, int tid) {
+  for (int i = tid; i < bytes / 16; i += kFthreads)
+    reinterpret_cast<bf16x8*>(dst)[i] = reinterpret_cast<const bf16x8*>(src)[i];
+}
+
+// One 32 -> 32 layer from the region of halo HO + 1 (in) to the region of halo
+// HO (out); wave w takes 16-node tiles w, w + 8, ... of the output region.
+template <int HO>
+__device__ __forceinline__ void fused_mid(const __bf16* in, __bf16* out, const bf16x8 (&wa)[9][2],
+                                          const float (&bv)[2][4], int x0, int y0, int nx, int ny, int wave,
+                                          int col, int q) {
+  constexpr int XO = kFx + 2 * HO, NO = fused_nodes(HO), XI = XO + 2;
+  constexpr int NT = (NO + 15) / 16;
+  for (int tile = wave; tile < NT; tile += kFwaves) {
+    const int f = tile * 16 + col;
+    const int fc = f < NO ? f : NO - 1;
+    const int r = fc / XO, c = fc - r * XO;
+    const int n0 = (r + 1) * XI + c + 1;
+    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(in + fsw(n0 + tap_dy(t) * XI + tap_dx(t), q));
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][mt], bfr, acc[mt], 0, 0, 0);
+    }
+    if (f < NO) {
+      const int gy = y0 - HO + r, gx = x0 - HO + c;
+      const bool ing = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        bf16x4 h;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) h[e] = ing ? __bf16(fmaxf(acc[mt][e] + bv[mt][e], 0.f)) : __bf16(0.f);
+        *reinterpret_cast<bf16x4*>(out + fsw(f, 2 * mt + (q >> 1)) + 4 * (q & 1)) = h;
+      }
+    }
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict__ un, const float* __restrict__ uc,
+                                                        const float* __restrict__ cs, const float* __restrict__ prm,
+                                                        const __bf16* __restrict__ wf, const __bf16* __restrict__ w6b,
+                                                        float s_out, float* __restrict__ out,
+                                                        double* __restrict__ part, int nx, int ny) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kFbytes];
+  __bf16* bufA = reinterpret_cast<__bf16*>(smem);
+  __bf16* bufB = reinterpret_cast<__bf16*>(smem + kFbytesA);
+  float2* xin = reinterpret_cast<float2*>(smem + kFbytesA + kFbytesB);
+  float* w1 = reinterpret_cast<float*>(smem + kFbytesA + kFbytesB + kFnC * 8);
+  double* red = reinterpret_cast<double*>(smem + kFbytesA + kFbytesB);  // after the input layer
+  __bf16* wst = reinterpret_cast<__bf16*>(smem + kFbytesA + kFbytesB + kFbytesC);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, q = lane >> 4;
+  const int ntx = (nx + kFx - 1) / kFx;
+  const int x0 = int(blockIdx.x % ntx) * kFx, y0 = int(blockIdx.x / ntx) * kFr;
+  const int b = blockIdx.y;
+  const int64_t img = int64_t(b) * nx * ny;
+  const float rc = 1.f / cs[b];
+
+  // input region (halo 6) and the input layer's weights; the first 32 -> 32
+  // layer's weights
+  constexpr int XC = kFx + 12;
+  for (int i = tid; i < kFnC; i += kFthreads) {
+    const int r = i / XC, c = i - r * XC;
+    const int gy = y0 - 6 + r, gx = x0 - 6 + c;
+    float2 v = {0.f, 0.f};
+    if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
+      const int64_t p = img + int64_t(gy) * nx + gx;
+      const float vc = uc[p], vn = un[p];
+      v = float2{vc, (vc - vn) * rc};
+    }
+    xin[i] = v;
+  }
+  for (int i = tid; i < SZ_L1; i += kFthreads) w1[i] = prm[i];
+  fused_stage(wf, wst, kFbytesW, tid);
+  __syncthreads();
+
+  // input layer (FP32, as conv_in_fwd) into A over the halo 5 region
+  {
+    constexpr int X1 = kFx + 10;
+    for (int i = tid; i < kFnA; i += kFthreads) {
+      const int r = i / X1, c = i - r * X1;
+      const int gy = y0 - 5 + r, gx = x0 - 5 + c;
+      bf16x8 hv[4];
+      if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
+        float a[9], d[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const float2 v = xin[(r + 1 + tap_dy(t)) * XC + c + 1 + tap_dx(t)];
+          a[t] = v.x;
+          d[t] = v.y;
+        }
+        float acc[C];
+#pragma unroll
+        for (int o = 0; o < C; ++o) acc[o] = w1[SZ_W1 + o];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const f32x4* wa = reinterpret_cast<const f32x4*>(w1 + (t * 2) * C);
+          const f32x4* wd = reinterpret_cast<const f32x4*>(w1 + (t * 2 + 1) * C);
+#pragma unroll
+          for (int v = 0; v < C / 4; ++v) {
+            const f32x4 ka = wa[v], kd = wd[v];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[4 * v + j] = fmaf(a[t], ka[j], fmaf(d[t], kd[j], acc[4 * v + j]));
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) hv[v][j] = __bf16(fmaxf(acc[8 * v + j], 0.f));
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) hv[v] = bf16x8{};
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) *reinterpret_cast<bf16x8*>(bufA + fsw(i, v)) = hv[v];
+    }
+  }
+
+  // the four 32 -> 32 layers: A -> B -> A -> B -> A
+#pragma unroll
+  for (int l = 0; l < N_MID; ++l) {
+    __syncthreads();  // the previous layer's outputs and this layer's weights are in LDS
+    bf16x8 wa[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+        wa[t][mt] = *reinterpret_cast<const bf16x8*>(wst + (t * 32 + mt * 16 + col) * C + 8 * q);
+    float bv[2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bv[mt][e] = prm[OFF_MID + l * SZ_LM + SZ_WM + mt * 16 + 4 * q + e];
+    __syncthreads();  // every wave holds its fragments: the weight buffer is free
+    if (l + 1 < N_MID)
+      fused_stage(wf + (l + 1) * SZ_WM, wst, kFbytesW, tid);
+    else
+      fused_stage(w6b, wst, 9 * 16 * C * 2, tid);
+    if (l == 0) fused_mid<4>(bufA, bufB, wa, bv, x0, y0, nx, ny, wave, col, q);
+    if (l == 1) fused_mid<3>(bufB, bufA, wa, bv, x0, y0, nx, ny, wave, col, q);
+    if (l == 2) fused_mid<2>(bufA, bufB, wa, bv, x0, y0, nx, ny, wave, col, q);
+    if (l == 3) fused_mid<1>(bufB, bufA, wa, bv, x0, y0, nx, ny, wave, col, q);
+  }
+  __syncthreads();
+
+  // output layer (as conv_patch's output modes) from A over the tile
+  bf16x8 w6[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) w6[t] = *reinterpret_cast<const bf16x8*>(wst + (t * 16 + col) * C + 8 * q);
+  const float b6 = prm[OFF_L6 + SZ_W6];
+  const float sc = s_out * cs[b];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  constexpr int XI = kFx + 2;
+  for (int tile = wave; tile < kFr * kFx / 16; tile += kFwaves) {
+    const int f = tile * 16 + col;
+    const int r = f / kFx, c = f - r * kFx;
+    const int n0 = (r + 1) * XI + c + 1;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(bufA + fsw(n0 + tap_dy(t) * XI + tap_dx(t), q));
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w6[t], bfr, acc, 0, 0, 0);
+    }
+    const int gy = y0 + r, gx = x0 + c;
+    if (q == 0 && gy < ny && gx < nx) {
+      const int64_t p = img + int64_t(gy) * nx + gx;
+      const float vo = acc[0] + b6;
+      if (MODE == FUSED_INFER) {
+        out[p] = sc * vo;
+      } else {
+        const float cv = uc[p];
+        float dv, val;
+        {
+          // delta rounded as the inference output stores it: no contraction into the add
+#pragma clang fp contract(off)
+          dv = sc * vo;
+          val = cv + dv;
+        }
+        out[p] = val;
+        s0 += double(dv) * double(dv);
+        const double ch = double(cv) - double(un[p]);
+        s1 += ch * ch;
+        s2 = fmax(s2, fabs(double(val)));
+      }
+    }
+  }
+  if (MODE == FUSED_APPLY) {
+    red[tid] = s0;
+    red[kFthreads + tid] = s1;
+    red[2 * kFthreads + tid] = s2;
+    __syncthreads();
+    for (int k = kFthreads / 2; k > 0; k >>= 1) {
+      if (tid < k) {
+        red[tid] += red[tid + k];
+        red[kFthreads + tid] += red[kFthreads + tid + k];
+        red[2 * kFthreads + tid] = fmax(red[2 * kFthreads + tid], red[2 * kFthreads + tid + k]);
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const int64_t row = int64_t(b) * gridDim.x + blockIdx.x;
+      part[3 * row] = red[0];
+      part[3 * row + 1] = red[kFthreads];
+      part[3 * row + 2] = red[2 * kFthreads];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Corrected step: u = u_c + delta, with per-block partial sums of delta^2,
 // (u_c - u_n)^2 and the maximum of |u| (double).
 __global__ void __launch_bounds__(256) apply_indicator(const float* __restrict__ un, const float* __restrict__ uc,
@@ -694,6 +950,7 @@ struct eife_corr_s {
   float* cs = nullptr;      // per-image RMS coarse change [max_batch]
   double* cpart = nullptr;  // its partial sums [max_batch][kCsBlocks]
   double guard = INFINITY;  // fall back when the RMS coarse change exceeds this
+  int fused = 1;            // inference through corr_fused (else one kernel per layer)
 };
 
 namespace {
@@ -759,6 +1016,17 @@ int refresh_copies(eife_corr_s* c, hipStream_t s, bool step, double lr) {
   return EIFE_OK;
 }
 
+// Output tiles of the fused network per image.
+int64_t fused_tiles(const eife_corr_s* c) {
+  return int64_t((c->nx + kFx - 1) / kFx) * ((c->ny + kFr - 1) / kFr);
+}
+
+// The RMS coarse change per image (cs).
+void change_rms(eife_corr_s* c, const float* un, const float* uc, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(change_partial, dim3(kCsBlocks, batch), dim3(256), 0, s, un, uc, c->npix1, c->cpart);
+  hipLaunchKernelGGL(change_final, dim3(batch), dim3(256), 0, s, c->cpart, c->npix1, c->cs);
+}
+
 int check_batch(const eife_corr_s* c, int batch) {
   if (batch < 1 || batch > c->bmax) return cfail(EIFE_EINVAL, "batch %d outside 1..%d", batch, c->bmax);
   return EIFE_OK;
@@ -767,8 +1035,7 @@ int check_batch(const eife_corr_s* c, int batch) {
 // Forward through the first five layers: the RMS coarse change, act[1..5].
 int forward_body(eife_corr_s* c, const float* un, const float* uc, int batch, hipStream_t s) {
   const int64_t npix = c->npix1 * batch;
-  hipLaunchKernelGGL(change_partial, dim3(kCsBlocks, batch), dim3(256), 0, s, un, uc, c->npix1, c->cpart);
-  hipLaunchKernelGGL(change_final, dim3(batch), dim3(256), 0, s, c->cpart, c->npix1, c->cs);
+  change_rms(c, un, uc, batch, s);
   hipLaunchKernelGGL(conv_in_fwd, dim3(grid1(npix, 256)), dim3(256), 0, s, un, uc, c->cs, c->prm, c->act[1], c->nx,
                      c->ny, npix);
   const int64_t np = n_patches(c, batch);
@@ -851,7 +1118,8 @@ int eife_corr_create(int nx, int ny, int max_batch, eife_corr* out) {
             hipMalloc(&c->dz[0], npix * C * 2) == hipSuccess && hipMalloc(&c->dz[1], npix * C * 2) == hipSuccess &&
             hipMalloc(&c->gout, npix * 4) == hipSuccess &&
             hipMalloc(&c->part, size_t(kPartBlocks) * SZ_LM * 4) == hipSuccess &&
-            hipMalloc(&c->dpart, size_t(std::max<int64_t>(grid1(npix, 256), 4096)) * 8) == hipSuccess &&
+            hipMalloc(&c->dpart, size_t(std::max<int64_t>({grid1(npix, 256), 3 * fused_tiles(c), 4096})) * 8) ==
+                hipSuccess &&
             hipMalloc(&c->dres, 8 * 8) == hipSuccess &&
             hipHostMalloc(&c->hres, 8 * 8, hipHostMallocMapped) == hipSuccess &&
             hipMalloc(&c->cs, size_t(max_batch) * 4) == hipSuccess &&
@@ -926,12 +1194,25 @@ int eife_corr_forward(eife_corr c, const float* un, const float* uc, float* delt
   if (!c || !un || !uc || !delta) return cfail(EIFE_EINVAL, "null argument");
   CRET(check_batch(c, batch));
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->fused) {
+    change_rms(c, un, uc, batch, s);
+    hipLaunchKernelGGL((corr_fused<FUSED_INFER>), dim3(fused_tiles(c), batch), dim3(kFthreads), 0, s, un, uc, c->cs,
+                       c->prm, c->wf, c->w6b, float(c->s_out), delta, (double*)nullptr, c->nx, c->ny);
+    CHIP(hipGetLastError());
+    return EIFE_OK;
+  }
   CRET(forward_body(c, un, uc, batch, s));
   const int64_t np = n_patches(c, batch);
   hipLaunchKernelGGL((conv_patch<OUT_INFER>), dim3(patch_blocks(np)), dim3(256), 0, s, c->act[5], (void*)delta,
                      c->w6b, c->prm + OFF_L6 + SZ_W6, (const __bf16*)nullptr, float(c->s_out), c->cs,
                      (const float*)nullptr, (const float*)nullptr, (double*)nullptr, 0.0, c->nx, c->ny, np);
   CHIP(hipGetLastError());
+  return EIFE_OK;
+}
+
+int eife_corr_set_fused(eife_corr c, int fused) {
+  if (!c) return cfail(EIFE_EINVAL, "null corrector");
+  c->fused = fused != 0;
   return EIFE_OK;
 }
 
@@ -986,10 +1267,19 @@ int enqueue_corrected(eife_corr_s* c, eife_grid coarse, float* u, double t0, int
   hipLaunchKernelGGL(copy2, dim3(grid1((c->npix1 + 3) / 4, 256)), dim3(256), 0, s, u, un, uc, c->npix1, vec);
   const int r = eife_step(coarse, uc, 1, EIFE_F_ALLEN_CAHN, t0, s);
   if (r != EIFE_OK) return cfail(r, "coarse step: %s", eife_last_error());
-  CRET(eife_corr_forward(c, un, uc, c->gout, 1, s));
-  hipLaunchKernelGGL(apply_indicator, dim3(kIndBlocks), dim3(256), 0, s, un, uc, c->gout, u, c->npix1, c->dpart);
-  hipLaunchKernelGGL(reduce_indicator, dim3(1), dim3(256), 0, s, c->dpart, kIndBlocks,
-                     (c->hres_dev ? c->hres_dev : c->dres) + 4 * slot);
+  double* ind = (c->hres_dev ? c->hres_dev : c->dres) + 4 * slot;
+  if (c->fused) {
+    // network, u = u_c + delta and the indicator's block sums in one kernel
+    change_rms(c, un, uc, 1, s);
+    const int64_t nt = fused_tiles(c);
+    hipLaunchKernelGGL((corr_fused<FUSED_APPLY>), dim3(nt, 1), dim3(kFthreads), 0, s, un, uc, c->cs, c->prm, c->wf,
+                       c->w6b, float(c->s_out), u, c->dpart, c->nx, c->ny);
+    hipLaunchKernelGGL(reduce_indicator, dim3(1), dim3(256), 0, s, c->dpart, int(nt), ind);
+  } else {
+    CRET(eife_corr_forward(c, un, uc, c->gout, 1, s));
+    hipLaunchKernelGGL(apply_indicator, dim3(kIndBlocks), dim3(256), 0, s, un, uc, c->gout, u, c->npix1, c->dpart);
+    hipLaunchKernelGGL(reduce_indicator, dim3(1), dim3(256), 0, s, c->dpart, kIndBlocks, ind);
+  }
   CHIP(hipGetLastError());
   if (!c->hres_dev)
     CHIP(hipMemcpyAsync(c->hres + 4 * slot, c->dres + 4 * slot, 3 * sizeof(double), hipMemcpyDeviceToHost, s));

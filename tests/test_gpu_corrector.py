@@ -144,6 +144,77 @@ def test_forward_matches_reference(B, ny, nx):
     c.close()
 
 
+@pytest.mark.parametrize("B,ny,nx,trained", [
+    pytest.param(3, 5, 7, False, id="b3-5x7-inside-one-tile"),
+    pytest.param(2, 45, 70, False, id="b2-45x70-ragged-tiles"),
+    pytest.param(1, 16, 32, False, id="b1-16x32-one-whole-tile"),
+    pytest.param(1, 511, 511, True, id="b1-511x511-trained")])
+def test_fused_network_equals_layers(B, ny, nx, trained):
+    """The one-kernel inference (16 x 32 node tiles, activations in LDS, halo recomputed)
+    gives the layer-by-layer kernels' delta bit for bit: same fragments, tap order and
+    roundings, zero padding outside the grid."""
+    import os
+    from paper_2209_11922_amd import corrector as cor
+    eife = _lib()
+    if trained:
+        path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2209_11922_amd",
+                            "weights", "corrector_ac512.npz")
+        p, s_out, _, _ = cor.load(path)
+    else:
+        p, s_out = _params(3), 0.01
+    un, uc, _ = _data(5, B, ny, nx)
+    c = eife.Corrector(nx, ny, B)
+    c.set_params(p)
+    c.set_scale(s_out)
+    c.set_fused(False)
+    d_layers = c.forward(_dev(un), _dev(uc))
+    c.set_fused(True)
+    d_fused = c.forward(_dev(un), _dev(uc))
+    torch.cuda.synchronize()
+    assert float(d_layers.abs().max()) > 0
+    diff = int((d_fused != d_layers).sum())
+    print(f"fused vs layers {B}x{ny}x{nx}: {diff} differing values")
+    assert torch.equal(d_fused, d_layers)
+    c.close()
+
+
+def test_fused_corrected_steps_equal_layers():
+    """Corrected steps through the fused kernel (network, u = u_c + delta and the
+    indicator's block sums in one launch) equal those through the per-layer kernels bit for
+    bit, with the same fallbacks, in infer_step and in the pipelined run loop."""
+    eife = _lib()
+    n = 96
+    N, h = [n, n], [1.0 / n] * 2
+    coarse = eife.Grid(N, h, 4e-4, "f32")
+    coarse.set_phi(0.016, 2)
+    fine = eife.Grid(N, h, 4e-4, "f32")
+    fine.set_phi(0.002, 2)
+    c = eife.Corrector(n - 1, n - 1, 1)
+    c.set_params(cr.init_params(21).astype(np.float32))
+    c.set_scale(1e-4)
+    c.set_guard(0.05)
+    u0 = _dev(seeded_inputs.uniform_field(22, N))
+    out = {}
+    for fused in (False, True):
+        c.set_fused(fused)
+        a = u0.clone()
+        steps = [c.infer_step(coarse, fine, a, k * 0.016, 8, 10.0) for k in range(5)]
+        b = u0.clone()
+        fb = c.run(coarse, fine, b, 0.0, 0.016, 5, 8, 10.0)
+        torch.cuda.synchronize()
+        out[fused] = (a, steps, b, fb)
+    (a0, s0, b0, f0), (a1, s1, b1, f1) = out[False], out[True]
+    assert [x[0] for x in s0] == [x[0] for x in s1] and sum(x[0] for x in s1) < 5  # some steps accepted
+    assert f0 == f1 == sum(x[0] for x in s1)
+    for x, y in zip(s0, s1):
+        if not x[0]:
+            assert abs(x[1] - y[1]) <= 1e-12 * abs(x[1]) and x[2] == y[2]
+    assert torch.equal(a0, a1) and torch.equal(b0, b1) and torch.equal(a1, b1)
+    for g in (coarse, fine):
+        g.close()
+    c.close()
+
+
 @pytest.mark.parametrize("B,ny,nx", SHAPES[:2])
 def test_gradient_matches_reference(B, ny, nx):
     eife = _lib()
