@@ -133,8 +133,12 @@ int eife_set_nodes3(eife_grid g, double c2, double c3);
  * tables: call eife_set_phi again before stepping. */
 int eife_set_c2(eife_grid g, double c2);
 
-/* Lower corner a[0..d-1] of the rectangle (default 0); only the reaction
- * kinds that depend on x use it. */
+/* Lower corner a[0..d-1] of the rectangle (default 0), for domains that do
+ * not start at the origin (Example 5.1 of Section 5 takes x in (1/2, 5/2)).
+ * Only the reaction kinds that depend on x use it: the manufactured problem
+ * and Example 5.1, whose per-axis sin(pi x) factors at the interior nodes are
+ * recomputed here.  Waits for all work on the device first.  Errors:
+ * EIFE_EINVAL (null or non-finite origin), EIFE_EHIP. */
 int eife_set_origin(eife_grid g, const double* a);
 
 /* Load reading, EIFE_LOAD_LUMPED or EIFE_LOAD_NODAL. */
@@ -324,7 +328,10 @@ int eife_version(void);
  * first five, zero padding (the homogeneous Dirichlet boundary).  Tap
  * t = 3 (dy + 1) + (dx + 1) reads the input at (y + dy, x + dx).  The four
  * 32 -> 32 layers and the output layer run on the matrix cores with BF16
- * weights and activations and FP32 accumulation; the first layer in FP32.
+ * weights and activations and FP32 accumulation; the first layer's FP32
+ * inputs and weights enter the matrix cores split into BF16 high and low
+ * parts (three products: about 2^-16 relative, below the BF16 rounding of
+ * its stored output).
  *
  * Parameters: EIFE_CORR_PARAMS floats, in order W1 [9][2][32] (tap, input
  * channel (u_c, (u_c - u_n) / c), output), b1 [32]; four times W [9][32][32] (tap, output,

@@ -125,6 +125,7 @@ struct eife_grid_s {
   void* H = nullptr;
   void* tw[3] = {nullptr, nullptr, nullptr};
   double* tab[3] = {nullptr, nullptr, nullptr};  // kTabArrays arrays per axis
+  double* sinpi_ax[3] = {nullptr, nullptr, nullptr};  // sin(pi x) at the interior nodes of each axis
   int tablen[3] = {0, 0, 0};
   double* partials = nullptr;
   double* out5 = nullptr;
@@ -331,8 +332,24 @@ Forcing make_forcing(const eife_grid_s* g, int kind, double t) {
     F.a[a] = g->a[a];
     F.h[a] = g->h[a];
     F.n[a] = g->n[a];
+    F.sinpi_ax[a] = g->sinpi_ax[a];
   }
+  const double PI2 = 9.8696044010893586188;
+  F.et = kind == EIFE_F_EX51 ? std::exp(-PI2 * t) : std::exp(-t);
   return F;
+}
+
+// The per-axis sin(pi x) tables at the grid's current origin (device, on the
+// null stream after all work on the device; blocks the host).
+int upload_sinpi(eife_grid_s* g) {
+  HIP_TRY(hipDeviceSynchronize());  // no step in flight still reads the old tables
+  for (int a = 0; a < 3; ++a) {
+    const int n = g->n[a];
+    hipLaunchKernelGGL(sinpi_table, dim3((n + 255) / 256), dim3(256), 0, 0, g->sinpi_ax[a], n, g->a[a], g->h[a]);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipDeviceSynchronize());
+  return EIFE_OK;
 }
 
 template <typename T, bool BAT>
@@ -1344,6 +1361,7 @@ void free_grid(eife_grid_s* g) {
   for (int a = 0; a < 3; ++a) {
     hipFree(g->tw[a]);
     hipFree(g->tab[a]);
+    hipFree(g->sinpi_ax[a]);
     hipFree(g->smat[a]);
   }
   for (auto& r : g->prof_pending) {
@@ -1478,7 +1496,8 @@ int eife_create_grid(int d, const int32_t* N, const double* h, double D, int bc,
       }
     }
     g->tablen[a] = (a == 0) ? g->pitch : g->n[a];
-    if (hipMalloc(reinterpret_cast<void**>(&g->tab[a]), kTabArrays * size_t(g->tablen[a]) * sizeof(double)) != hipSuccess) {
+    if (hipMalloc(reinterpret_cast<void**>(&g->tab[a]), kTabArrays * size_t(g->tablen[a]) * sizeof(double)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&g->sinpi_ax[a]), size_t(g->n[a]) * sizeof(double)) != hipSuccess) {
       free_grid(g);
       return fail(EIFE_ENOMEM, "table allocation failed");
     }
@@ -1489,7 +1508,8 @@ int eife_create_grid(int d, const int32_t* N, const double* h, double D, int bc,
     free_grid(g);
     return fail(EIFE_ENOMEM, "norm buffers allocation failed");
   }
-  const int rt = upload_tables(g);
+  int rt = upload_tables(g);
+  if (rt == EIFE_OK) rt = upload_sinpi(g);
   if (rt != EIFE_OK) {
     free_grid(g);
     return rt;
@@ -1527,7 +1547,7 @@ int eife_set_origin(eife_grid g, const double* a) {
     if (!std::isfinite(a[i])) return fail(EIFE_EINVAL, "origin must be finite");
     g->a[i] = a[i];
   }
-  return EIFE_OK;
+  return upload_sinpi(g);
 }
 
 int eife_set_load(eife_grid g, int kind) {

@@ -11,9 +11,12 @@
 //
 // Precision: FP32 master parameters; the four 32 -> 32 layers and the output
 // layer's forward run on the matrix cores with BF16 weights and BF16
-// activations, FP32 accumulation; the 2 -> 32 input layer and the output
-// layer's gradients run in FP32 on the vector units.  Activations are stored
-// [B][ny][nx][32] BF16 (64 bytes per node).
+// activations, FP32 accumulation; the 2 -> 32 input layer's forward runs on
+// the matrix cores with its FP32 inputs and weights split into BF16 high and
+// low parts (three products, FP32 accumulation: the pre-activation to about
+// 2^-16 relative); the input and output layers' weight gradients run in FP32
+// on the vector units.  Activations are stored [B][ny][nx][32] BF16 (64 bytes
+// per node).
 //
 // Parameter vector (FP32), in order: W1 [9][2][32] (tap, input, output), b1
 // [32]; four times W [9][32][32] (tap, output, input), b [32]; W6 [9][32] (tap,
@@ -52,10 +55,23 @@ constexpr int kPartBlocks = 512;  // blocks of the weight-gradient kernels (one 
 __device__ __forceinline__ int tap_dy(int t) { return t / 3 - 1; }
 __device__ __forceinline__ int tap_dx(int t) { return t % 3 - 1; }
 
+// relu(a), relu(b) rounded to BF16 (nearest even) and packed (a in the low
+// half): the rounding commutes with the ReLU, which then clears each negative
+// BF16 by a signed 16-bit maximum with zero.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t relu_bf16x2(float a, float b) {
+  const bf16x2 h = __builtin_convertvector(f32x2{a, b}, bf16x2);
+  const i16x2 m = __builtin_elementwise_max(__builtin_bit_cast(i16x2, h), i16x2{0, 0});
+  return __builtin_bit_cast(uint32_t, m);
+}
+
 // ---------------------------------------------------------------------------
 // Per-image RMS coarse change c_b = sqrt(mean((u_c - u_n)^2)) + 1e-30: block
 // partial sums (grid kCsBlocks x batch) in double, then one fixed-order sum per
-// image.
+// image.  (A single launch whose last block adds the partials needs a
+// device-scope release per block, an L2 write-back on this chip: slower.)
 constexpr int kCsBlocks = 256;  // equals the block size of change_final
 
 __global__ void __launch_bounds__(256) change_partial(const float* __restrict__ un, const float* __restrict__ uc,
@@ -92,51 +108,105 @@ __global__ void __launch_bounds__(256) change_final(const double* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------
-// Input layer (FP32): Y1 = relu(b1 + sum_t sum_c W1[t][c][:] X0[p + off_t][c]),
-// X0 = (u_c, (u_c - u_n) / c_b).  One thread per node; the 608 weights and
-// biases are staged in LDS and read at one address per wave (broadcast).
+// Input layer: Y1 = relu(b1 + sum_t sum_c W1[t][c][:] X0[p + off_t][c]),
+// X0 = (u_c, (u_c - u_n) / c_b), as a product on the matrix cores with
+// K = 18 (k = 2 t + c, zero-padded to 32): D[o][node] = sum_k W1[k][o] X[k][node].
+// Inputs and weights are split into BF16 high and low parts (x = hi + lo to
+// 2^-16 relative) and three products W_lo X_hi + W_hi X_lo + W_hi X_hi are
+// accumulated onto the bias in FP32: the pre-activation to about 2^-16
+// relative, far below the BF16 rounding of the stored activation (2^-9).
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  // x must be the rounded FP32 value: no contraction of the product that
+  // produced x into this subtraction
+#pragma clang fp contract(off)
+  hi = __bf16(x);
+  lo = __bf16(x - float(hi));  // x - hi is exact in FP32
+}
+
+// A fragments (rows = output channels 16 mt + l % 16, k = 8 (l / 16) + j) and
+// the accumulator's starting bias for lane (col, q).
+struct InW {
+  bf16x8 hi[2], lo[2];
+  f32x4 bias[2];
+  __device__ __forceinline__ void load(const float* __restrict__ prm, int col, int q) {
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = 8 * q + j;
+        const float w = k < 18 ? prm[k * C + mt * 16 + col] : 0.f;  // W1[t][c][o] at (2 t + c) C + o
+        __bf16 h, l;
+        split_bf16(w, h, l);
+        hi[mt][j] = h;
+        lo[mt][j] = l;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bias[mt][r] = prm[SZ_W1 + mt * 16 + 4 * q + r];
+    }
+  }
+};
+
+// The 16-node tile's pre-activations: x[j] = X[8 q + j][node col].
+__device__ __forceinline__ void in_products(const InW& w, const float (&x)[8], f32x4 (&acc)[2]) {
+  bf16x8 xh, xl;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    __bf16 h, l;
+    split_bf16(x[j], h, l);
+    xh[j] = h;
+    xl[j] = l;
+  }
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.lo[mt], xh, w.bias[mt], 0, 0, 0);
+    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.hi[mt], xl, acc[mt], 0, 0, 0);
+    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w.hi[mt], xh, acc[mt], 0, 0, 0);
+  }
+}
+
+// One wave per 16-node tile of the flattened [batch][ny][nx] nodes.
 __global__ void __launch_bounds__(256) conv_in_fwd(const float* __restrict__ un, const float* __restrict__ uc,
                                                    const float* __restrict__ cs, const float* __restrict__ prm,
                                                    __bf16* __restrict__ Y, int nx, int ny, int64_t npix) {
-  __shared__ __attribute__((aligned(16))) float w[SZ_L1];
-  for (int i = threadIdx.x; i < SZ_L1; i += blockDim.x) w[i] = prm[i];
-  __syncthreads();
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= npix) return;
-  const int x = int(p % nx);
-  const int y = int((p / nx) % ny);
-  const float rc = 1.f / cs[p / (int64_t(nx) * ny)];
-  float a[9], d[9];
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, q = lane >> 4;
+  const int64_t tile = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int64_t p = tile * 16 + col;
+  if (tile * 16 >= npix) return;
+  InW w;
+  w.load(prm, col, q);
+  const int64_t pc = p < npix ? p : npix - 1;
+  const int64_t npix1 = int64_t(nx) * ny;
+  const int64_t b = pc / npix1;
+  const int x = int(pc % nx);
+  const int y = int((pc / nx) % ny);
+  const float rc = 1.f / cs[b];
+  float xv[8];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int yy = y + tap_dy(t), xx = x + tap_dx(t);
-    const bool ok = yy >= 0 && yy < ny && xx >= 0 && xx < nx;
-    const int64_t q = p + int64_t(tap_dy(t)) * nx + tap_dx(t);
-    const float vc = ok ? uc[q] : 0.f, vn = ok ? un[q] : 0.f;
-    a[t] = vc;
-    d[t] = (vc - vn) * rc;
-  }
-  float acc[C];
-#pragma unroll
-  for (int o = 0; o < C; ++o) acc[o] = w[SZ_W1 + o];
-#pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const f32x4* wa = reinterpret_cast<const f32x4*>(w + (t * 2) * C);
-    const f32x4* wd = reinterpret_cast<const f32x4*>(w + (t * 2 + 1) * C);
-#pragma unroll
-    for (int v = 0; v < C / 4; ++v) {
-      const f32x4 ka = wa[v], kd = wd[v];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[4 * v + j] = fmaf(a[t], ka[j], fmaf(d[t], kd[j], acc[4 * v + j]));
+  for (int j = 0; j < 8; j += 2) {
+    const int t = (8 * q + j) >> 1;  // k = 8 q + j (even) is channel 0 of tap t, k + 1 channel 1
+    float vc = 0.f, vn = 0.f;
+    if (t < 9) {
+      const int yy = y + tap_dy(t), xx = x + tap_dx(t);
+      if (yy >= 0 && yy < ny && xx >= 0 && xx < nx) {
+        const int64_t qi = pc + int64_t(tap_dy(t)) * nx + tap_dx(t);
+        vc = uc[qi];
+        vn = un[qi];
+      }
+    }
+    xv[j] = vc;
+    {
+#pragma clang fp contract(off)
+      xv[j + 1] = (vc - vn) * rc;
     }
   }
-  bf16x8* dst = reinterpret_cast<bf16x8*>(Y + p * C);
+  f32x4 acc[2];
+  in_products(w, xv, acc);
+  if (p < npix) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    bf16x8 h;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) h[j] = __bf16(fmaxf(acc[8 * v + j], 0.f));
-    dst[v] = h;
+    for (int mt = 0; mt < 2; ++mt)
+      *reinterpret_cast<uint2*>(Y + p * C + mt * 16 + 4 * q) =
+          uint2{relu_bf16x2(acc[mt][0], acc[mt][1]), relu_bf16x2(acc[mt][2], acc[mt][3])};
   }
 }
 
@@ -146,9 +216,9 @@ __global__ void __launch_bounds__(256) conv_in_fwd(const float* __restrict__ un,
 // with its one-node halo (6 x 66 nodes x 32 channels, BF16) in LDS, then wave w
 // computes row w as four 16-node tiles:
 //   D[oc][node] += Wk[t][oc][ic] * X[node + off_t][ic]   (9 taps, K = 32 per tap)
-// with A = weights (registers, loaded once), B = activations (LDS).  Lane
-// layout of v_mfma_f32_16x16x32_bf16: A row l%16 / B column l%16 with
-// k = 8 (l/16) + j; D[4 (l/16) + r][l%16].
+// with A = weights (registers, loaded once), B = activations (LDS), the
+// accumulator starting at the bias.  Lane layout of v_mfma_f32_16x16x32_bf16:
+// A row l%16 / B column l%16 with k = 8 (l/16) + j; D[4 (l/16) + r][l%16].
 //   CONV_FWD   Y = relu(D + bias)                           (32 outputs, BF16)
 //   CONV_BWD   Y = D where mask > 0 else 0                  (32 outputs, BF16;
 //              Wk = transposed, tap-flipped weights, mask = the activations
@@ -246,7 +316,7 @@ __global__ void __launch_bounds__(256) conv_patch(const __bf16* __restrict__ X, 
       const int xl = tile * 16 + col;  // node within the patch
       f32x4 acc[NMT];
 #pragma unroll
-      for (int mt = 0; mt < NMT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int mt = 0; mt < NMT; ++mt) acc[mt] = f32x4{bv[mt][0], bv[mt][1], bv[mt][2], bv[mt][3]};
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
         const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(
@@ -263,20 +333,20 @@ __global__ void __launch_bounds__(256) conv_patch(const __bf16* __restrict__ X, 
 #pragma unroll
         for (int mt = 0; mt < NMT; ++mt) {
           const int oc0 = mt * 16 + 4 * q;
-          bf16x4 h;
           if (MODE == CONV_FWD) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) h[r] = __bf16(fmaxf(acc[mt][r] + bv[mt][r], 0.f));
+            *reinterpret_cast<uint2*>(Y + p * C + oc0) =
+                uint2{relu_bf16x2(acc[mt][0], acc[mt][1]), relu_bf16x2(acc[mt][2], acc[mt][3])};
           } else {
             const bf16x4 m = *reinterpret_cast<const bf16x4*>(mask + p * C + oc0);
+            bf16x4 h;
 #pragma unroll
             for (int r = 0; r < 4; ++r) h[r] = (float(m[r]) > 0.f) ? __bf16(acc[mt][r]) : __bf16(0.f);
+            *reinterpret_cast<bf16x4*>(Y + p * C + oc0) = h;
           }
-          *reinterpret_cast<bf16x4*>(Y + p * C + oc0) = h;
         }
       } else if (q == 0) {
         float* o = static_cast<float*>(out);
-        const float v = acc[0][0] + bv[0][0];  // output channel 0 = D row 0 (r = 0 of lanes 0..15)
+        const float v = acc[0][0];  // output channel 0 = D row 0 (r = 0 of lanes 0..15), bias included
         const float sc = s_out * cs[b];
         if (MODE == OUT_INFER) {
           o[p] = sc * v;
@@ -588,10 +658,11 @@ __global__ void __launch_bounds__(256) copy2(const float* __restrict__ u, float*
 // roundings), so the result equals the layer-by-layer path bit for bit; nodes
 // outside the grid hold zeros, the zero padding of the next layer.
 // LDS (158 KB, one block per CU): activation buffers A (halo 5 region) and B
-// (halo 4 region), 64 bytes per node with the four 16-byte channel chunks
-// XOR-swizzled by node (16 consecutive nodes read one chunk conflict-free); the
-// input region (u_c, (u_c - u_n) / c_b) and the input layer's FP32 weights,
-// later the block's reduction rows; the current layer's BF16 weights.
+// (halo 4 region), each as four planes of 16 bytes per node (plane k holds
+// channels 8k .. 8k+7), so that 16 consecutive nodes of one plane are 256
+// contiguous bytes and a tap is a constant offset; the input region (u_c,
+// (u_c - u_n) / c_b), later the block's reduction rows; the current layer's
+// BF16 weights.
 //   FUSED_INFER  out = delta
 //   FUSED_APPLY  out = u_c + delta, block sums of delta^2, (u_c - u_n)^2 and
 //                max |out| in part[3 block ..] (block = tile + tiles * image)
@@ -602,51 +673,71 @@ constexpr int kFwaves = kFthreads / 64;
 constexpr int fused_nodes(int h) { return (kFr + 2 * h) * (kFx + 2 * h); }
 constexpr int kFnA = fused_nodes(5), kFnB = fused_nodes(4), kFnC = fused_nodes(6);
 constexpr int kFbytesA = kFnA * 64, kFbytesB = kFnB * 64;
-constexpr int kFbytesC = kFnC * 8 + SZ_L1 * 4;  // input region + input-layer weights
-constexpr int kFbytesW = SZ_WM * 2;               // one 32 -> 32 layer, BF16
+constexpr int kFbytesC = kFnC * 8 > 3 * kFthreads * 8 ? kFnC * 8 : 3 * kFthreads * 8;  // input region / reduction
+constexpr int kFbytesW = SZ_WM * 2;  // one 32 -> 32 layer, BF16
 constexpr int kFbytes = kFbytesA + kFbytesB + kFbytesC + kFbytesW;
-static_assert(kFbytesC >= 3 * kFthreads * 8, "reduction rows alias the input region");
 static_assert(kFbytes <= 160 * 1024, "fused network tile exceeds the LDS");
 static_assert(kFbytesA % 16 == 0 && kFbytesB % 16 == 0 && kFbytesC % 16 == 0, "LDS carve alignment");
 
-// element offset of channel chunk k (8 channels) of node n in an activation buffer
-__device__ __forceinline__ int fsw(int n, int k) { return n * C + ((k ^ ((n >> 2) & 3)) << 3); }
+// The next layer's weights in flight: loaded into registers before a layer's
+// products and written to LDS after them, so the load latency hides behind the
+// layer.
+constexpr int kFwChunks = (kFbytesW / 16 + kFthreads - 1) / kFthreads;
+struct FusedW {
+  bf16x8 v[kFwChunks];
+  __device__ __forceinline__ void load(const __bf16* __restrict__ src, int bytes, int tid) {
+#pragma unroll
+    for (int k = 0; k < kFwChunks; ++k) {
+      const int i = tid + kFthreads * k;
+      if (i < bytes / 16) v[k] = reinterpret_cast<const bf16x8*>(src)[i];
+    }
+  }
+  __device__ __forceinline__ void store(__bf16* dst, int bytes, int tid) const {
+#pragma unroll
+    for (int k = 0; k < kFwChunks; ++k) {
+      const int i = tid + kFthreads * k;
+      if (i < bytes / 16) reinterpret_cast<bf16x8*>(dst)[i] = v[k];
+    }
+  }
+};
 
-// copy `bytes` (a multiple of 16) from global to LDS, all threads of the block
-__device__ __forceinline__ void fused_stage(const void* __restrict__ src, void* dst, int bytes, int tid) {
-  for (int i = tid; i < bytes / 16; i += kFthreads)
-    reinterpret_cast<bf16x8*>(dst)[i] = reinterpret_cast<const bf16x8*>(src)[i];
-}
-
-// One 32 -> 32 layer from the region of halo HO + 1 (in) to the region of halo
-// HO (out); wave w takes 16-node tiles w, w + 8, ... of the output region.
-template <int HO>
+// One 32 -> 32 layer from the region of halo HO + 1 (in, planes of PI nodes)
+// to the region of halo HO (out, planes of PO nodes); wave w takes the 16-node
+// runs w, w + 8, ... of the output region in row-major order.
+template <int HO, int PI, int PO>
 __device__ __forceinline__ void fused_mid(const __bf16* in, __bf16* out, const bf16x8 (&wa)[9][2],
                                           const float (&bv)[2][4], int x0, int y0, int nx, int ny, int wave,
                                           int col, int q) {
-  constexpr int XO = kFx + 2 * HO, NO = fused_nodes(HO), XI = XO + 2;
+  constexpr int XO = kFx + 2 * HO, RO = kFr + 2 * HO, NO = RO * XO, XI = XO + 2;
   constexpr int NT = (NO + 15) / 16;
+  // the output region lies inside the grid (no zero padding to write)
+  const bool inside = x0 - HO >= 0 && y0 - HO >= 0 && x0 + kFx + HO <= nx && y0 + kFr + HO <= ny;
+  const __bf16* inq = in + q * (PI * 8);
   for (int tile = wave; tile < NT; tile += kFwaves) {
     const int f = tile * 16 + col;
     const int fc = f < NO ? f : NO - 1;
     const int r = fc / XO, c = fc - r * XO;
-    const int n0 = (r + 1) * XI + c + 1;
-    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+    const __bf16* src = inq + ((r + 1) * XI + c + 1) * 8;
+    f32x4 acc[2] = {f32x4{bv[0][0], bv[0][1], bv[0][2], bv[0][3]}, f32x4{bv[1][0], bv[1][1], bv[1][2], bv[1][3]}};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(in + fsw(n0 + tap_dy(t) * XI + tap_dx(t), q));
+      const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(src + (tap_dy(t) * XI + tap_dx(t)) * 8);
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][mt], bfr, acc[mt], 0, 0, 0);
     }
     if (f < NO) {
-      const int gy = y0 - HO + r, gx = x0 - HO + c;
-      const bool ing = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+      bool ing = true;
+      if (!inside) {
+        const int gy = y0 - HO + r, gx = x0 - HO + c;
+        ing = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+      }
+      // channels 16 mt + 4 q + e: plane 2 mt + q / 2, half q % 2 of the node's 16 bytes
+      __bf16* dst = out + (q >> 1) * (PO * 8) + f * 8 + 4 * (q & 1);
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
-        bf16x4 h;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) h[e] = ing ? __bf16(fmaxf(acc[mt][e] + bv[mt][e], 0.f)) : __bf16(0.f);
-        *reinterpret_cast<bf16x4*>(out + fsw(f, 2 * mt + (q >> 1)) + 4 * (q & 1)) = h;
+        uint2 h = {relu_bf16x2(acc[mt][0], acc[mt][1]), relu_bf16x2(acc[mt][2], acc[mt][3])};
+        if (!ing) h = uint2{0u, 0u};
+        *reinterpret_cast<uint2*>(dst + mt * (2 * PO * 8)) = h;
       }
     }
   }
@@ -662,7 +753,6 @@ __global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict_
   __bf16* bufA = reinterpret_cast<__bf16*>(smem);
   __bf16* bufB = reinterpret_cast<__bf16*>(smem + kFbytesA);
   float2* xin = reinterpret_cast<float2*>(smem + kFbytesA + kFbytesB);
-  float* w1 = reinterpret_cast<float*>(smem + kFbytesA + kFbytesB + kFnC * 8);
   double* red = reinterpret_cast<double*>(smem + kFbytesA + kFbytesB);  // after the input layer
   __bf16* wst = reinterpret_cast<__bf16*>(smem + kFbytesA + kFbytesB + kFbytesC);
   const int tid = threadIdx.x;
@@ -674,63 +764,59 @@ __global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict_
   const int64_t img = int64_t(b) * nx * ny;
   const float rc = 1.f / cs[b];
 
-  // input region (halo 6) and the input layer's weights; the first 32 -> 32
-  // layer's weights
-  constexpr int XC = kFx + 12;
-  for (int i = tid; i < kFnC; i += kFthreads) {
-    const int r = i / XC, c = i - r * XC;
-    const int gy = y0 - 6 + r, gx = x0 - 6 + c;
-    float2 v = {0.f, 0.f};
-    if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
-      const int64_t p = img + int64_t(gy) * nx + gx;
-      const float vc = uc[p], vn = un[p];
-      v = float2{vc, (vc - vn) * rc};
+  // the first 32 -> 32 layer's weights, then the input region (halo 6)
+  {
+    FusedW nw;
+    nw.load(wf, kFbytesW, tid);
+    constexpr int XC = kFx + 12;
+    for (int i = tid; i < kFnC; i += kFthreads) {
+      const int r = i / XC, c = i - r * XC;
+      const int gy = y0 - 6 + r, gx = x0 - 6 + c;
+      float2 v = {0.f, 0.f};
+      if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
+        const int64_t p = img + int64_t(gy) * nx + gx;
+        const float vc = uc[p], vn = un[p];
+        v = float2{vc, (vc - vn) * rc};
+      }
+      xin[i] = v;
     }
-    xin[i] = v;
+    nw.store(wst, kFbytesW, tid);
   }
-  for (int i = tid; i < SZ_L1; i += kFthreads) w1[i] = prm[i];
-  fused_stage(wf, wst, kFbytesW, tid);
   __syncthreads();
 
-  // input layer (FP32, as conv_in_fwd) into A over the halo 5 region
+  // input layer (as conv_in_fwd) into A over the halo 5 region, 16-node runs
+  // in row-major order
   {
-    constexpr int X1 = kFx + 10;
-    for (int i = tid; i < kFnA; i += kFthreads) {
-      const int r = i / X1, c = i - r * X1;
-      const int gy = y0 - 5 + r, gx = x0 - 5 + c;
-      bf16x8 hv[4];
-      if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
-        float a[9], d[9];
+    constexpr int X1 = kFx + 10, XC = kFx + 12;
+    constexpr int NT = (kFnA + 15) / 16;
+    InW w;
+    w.load(prm, col, q);
+    for (int tile = wave; tile < NT; tile += kFwaves) {
+      const int f = tile * 16 + col;
+      const int fc = f < kFnA ? f : kFnA - 1;
+      const int r = fc / X1, c = fc - r * X1;
+      float xv[8];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-          const float2 v = xin[(r + 1 + tap_dy(t)) * XC + c + 1 + tap_dx(t)];
-          a[t] = v.x;
-          d[t] = v.y;
-        }
-        float acc[C];
-#pragma unroll
-        for (int o = 0; o < C; ++o) acc[o] = w1[SZ_W1 + o];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-          const f32x4* wa = reinterpret_cast<const f32x4*>(w1 + (t * 2) * C);
-          const f32x4* wd = reinterpret_cast<const f32x4*>(w1 + (t * 2 + 1) * C);
-#pragma unroll
-          for (int v = 0; v < C / 4; ++v) {
-            const f32x4 ka = wa[v], kd = wd[v];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[4 * v + j] = fmaf(a[t], ka[j], fmaf(d[t], kd[j], acc[4 * v + j]));
-          }
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-          for (int j = 0; j < 8; ++j) hv[v][j] = __bf16(fmaxf(acc[8 * v + j], 0.f));
-      } else {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) hv[v] = bf16x8{};
+      for (int j = 0; j < 8; j += 2) {
+        const int t = (8 * q + j) >> 1;
+        float2 v = {0.f, 0.f};
+        if (t < 9) v = xin[(r + 1 + tap_dy(t)) * XC + c + 1 + tap_dx(t)];
+        xv[j] = v.x;
+        xv[j + 1] = v.y;
       }
+      f32x4 acc[2];
+      in_products(w, xv, acc);
+      if (f < kFnA) {
+        const int gy = y0 - 5 + r, gx = x0 - 5 + c;
+        const bool ing = gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+        __bf16* dst = bufA + (q >> 1) * (kFnA * 8) + f * 8 + 4 * (q & 1);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) *reinterpret_cast<bf16x8*>(bufA + fsw(i, v)) = hv[v];
+        for (int mt = 0; mt < 2; ++mt) {
+          uint2 h = {relu_bf16x2(acc[mt][0], acc[mt][1]), relu_bf16x2(acc[mt][2], acc[mt][3])};
+          if (!ing) h = uint2{0u, 0u};
+          *reinterpret_cast<uint2*>(dst + mt * (2 * kFnA * 8)) = h;
+        }
+      }
     }
   }
 
@@ -749,15 +835,15 @@ __global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict_
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
       for (int e = 0; e < 4; ++e) bv[mt][e] = prm[OFF_MID + l * SZ_LM + SZ_WM + mt * 16 + 4 * q + e];
-    __syncthreads();  // every wave holds its fragments: the weight buffer is free
-    if (l + 1 < N_MID)
-      fused_stage(wf + (l + 1) * SZ_WM, wst, kFbytesW, tid);
-    else
-      fused_stage(w6b, wst, 9 * 16 * C * 2, tid);
-    if (l == 0) fused_mid<4>(bufA, bufB, wa, bv, x0, y0, nx, ny, wave, col, q);
-    if (l == 1) fused_mid<3>(bufB, bufA, wa, bv, x0, y0, nx, ny, wave, col, q);
-    if (l == 2) fused_mid<2>(bufA, bufB, wa, bv, x0, y0, nx, ny, wave, col, q);
-    if (l == 3) fused_mid<1>(bufB, bufA, wa, bv, x0, y0, nx, ny, wave, col, q);
+    FusedW nw;
+    const int nbytes = l + 1 < N_MID ? kFbytesW : 9 * 16 * C * 2;
+    nw.load(l + 1 < N_MID ? wf + (l + 1) * SZ_WM : w6b, nbytes, tid);
+    if (l == 0) fused_mid<4, kFnA, kFnB>(bufA, bufB, wa, bv, x0, y0, nx, ny, wave, col, q);
+    if (l == 1) fused_mid<3, kFnB, kFnA>(bufB, bufA, wa, bv, x0, y0, nx, ny, wave, col, q);
+    if (l == 2) fused_mid<2, kFnA, kFnB>(bufA, bufB, wa, bv, x0, y0, nx, ny, wave, col, q);
+    if (l == 3) fused_mid<1, kFnB, kFnA>(bufB, bufA, wa, bv, x0, y0, nx, ny, wave, col, q);
+    __syncthreads();  // every wave is past its fragment reads: the weight buffer is free
+    nw.store(wst, nbytes, tid);
   }
   __syncthreads();
 
@@ -769,20 +855,21 @@ __global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict_
   const float sc = s_out * cs[b];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   constexpr int XI = kFx + 2;
+  const __bf16* inq = bufA + q * (kFnA * 8);
   for (int tile = wave; tile < kFr * kFx / 16; tile += kFwaves) {
     const int f = tile * 16 + col;
     const int r = f / kFx, c = f - r * kFx;
-    const int n0 = (r + 1) * XI + c + 1;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const __bf16* src = inq + ((r + 1) * XI + c + 1) * 8;
+    f32x4 acc = {b6, b6, b6, b6};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(bufA + fsw(n0 + tap_dy(t) * XI + tap_dx(t), q));
+      const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(src + (tap_dy(t) * XI + tap_dx(t)) * 8);
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w6[t], bfr, acc, 0, 0, 0);
     }
     const int gy = y0 + r, gx = x0 + c;
     if (q == 0 && gy < ny && gx < nx) {
       const int64_t p = img + int64_t(gy) * nx + gx;
-      const float vo = acc[0] + b6;
+      const float vo = acc[0];
       if (MODE == FUSED_INFER) {
         out[p] = sc * vo;
       } else {
@@ -1036,7 +1123,7 @@ int check_batch(const eife_corr_s* c, int batch) {
 int forward_body(eife_corr_s* c, const float* un, const float* uc, int batch, hipStream_t s) {
   const int64_t npix = c->npix1 * batch;
   change_rms(c, un, uc, batch, s);
-  hipLaunchKernelGGL(conv_in_fwd, dim3(grid1(npix, 256)), dim3(256), 0, s, un, uc, c->cs, c->prm, c->act[1], c->nx,
+  hipLaunchKernelGGL(conv_in_fwd, dim3(grid1(npix, 64)), dim3(256), 0, s, un, uc, c->cs, c->prm, c->act[1], c->nx,
                      c->ny, npix);
   const int64_t np = n_patches(c, batch);
   const int blocks = patch_blocks(np);

@@ -365,7 +365,19 @@ struct Forcing {
   double a[3];
   double h[3];
   int n[3];  // interior nodes per axis (unused axes 1)
+  // position-dependent forcings: sin(pi x_a) at the interior nodes of each axis
+  // (device tables) and their time factor (e^-t for the manufactured problem,
+  // e^(-pi^2 t) for Example 5.1), formed once per launch instead of per node
+  const double* sinpi_ax[3];
+  double et;
 };
+
+// sin(pi (a + (i + 1) h)) for i < n: the per-axis factors of the manufactured
+// solution and of Example 5.1's forcing.
+__global__ void sinpi_table(double* __restrict__ out, int n, double a, double h) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = sinpi(a + (i + 1) * h);
+}
 
 enum FKind { FK_ZERO = 0, FK_AC = 1, FK_MMS = 2, FK_EX51 = 3, FK_CONST = 4, FK_AFFINE = 5, FK_FH = 6, FK_EX52 = 7 };
 
@@ -468,10 +480,10 @@ __device__ __forceinline__ T reaction(const Forcing& F, T u, int ix, int iy, int
       }
     }
     case FK_MMS: {
-      double s = sinpi(F.a[0] + (ix + 1) * F.h[0]);
-      if (F.d > 1) s *= sinpi(F.a[1] + (iy + 1) * F.h[1]);
-      if (F.d > 2) s *= sinpi(F.a[2] + (iz + 1) * F.h[2]);
-      const double e = exp(-F.t);
+      double s = F.sinpi_ax[0][ix];
+      if (F.d > 1) s *= F.sinpi_ax[1][iy];
+      if (F.d > 2) s *= F.sinpi_ax[2][iz];
+      const double e = F.et;  // e^-t
       const double PI2 = 9.8696044010893586188;
       const double g = (F.d * PI2 * F.D - 1.0) * e * s - e * e * s * s;
       const double ud = double(u);
@@ -479,8 +491,8 @@ __device__ __forceinline__ T reaction(const Forcing& F, T u, int ix, int iy, int
     }
     case FK_EX51: {
       const double PI2 = 9.8696044010893586188;
-      const double s = sinpi(F.a[0] + (ix + 1) * F.h[0]) * sinpi(F.a[1] + (iy + 1) * F.h[1]);
-      return T(-0.5 * PI2 * double(u) + 0.5 * PI2 * exp(-PI2 * F.t) * s);
+      const double s = F.sinpi_ax[0][ix] * F.sinpi_ax[1][iy];
+      return T(-0.5 * PI2 * double(u) + 0.5 * PI2 * F.et * s);  // et = e^(-pi^2 t)
     }
     default:
       return T(0);

@@ -1,12 +1,14 @@
 """Corrector kernels (eife_corr_*) against the FP64 NumPy reference.
 
 Tolerances come from the arithmetic: the 32 -> 32 layers round weights and
-activations to BF16 (relative 2^-9 per rounding), accumulate in FP32.
+activations to BF16 (relative 2^-9 per rounding), accumulate in FP32; the input
+layer takes its FP32 inputs and weights as BF16 high + low parts (three
+products, about 2^-16 relative) and rounds its output to BF16.
 Against the plain FP64 reference the network output agrees to a few 1e-3
 (relative 2-norm); against the same reference with BF16 rounding applied at
 the points where the kernels round (weights of the 32 -> 32 and output
-layers, the five stored activations) only accumulation order and rare rounding-boundary flips
-remain.  Gradients (BF16 backward) are compared per layer.
+layers, the split input layer, the five stored activations) only accumulation order and rare
+rounding-boundary flips remain.  Gradients (BF16 backward) are compared per layer.
 """
 import numpy as np
 import pytest
@@ -31,12 +33,29 @@ def _bf16(a):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def _split(a):
+    """FP32 values as BF16 high and low parts (a = hi + lo to about 2^-16 relative)."""
+    f = np.asarray(a, np.float32)
+    hi = _bf16(f)
+    return hi, _bf16(f - hi.astype(np.float32))
+
+
+def _input_layer_bf16(X0, W1, b1):
+    """The input layer as the kernels compute it: inputs and weights split into BF16 high
+    and low parts, W_lo X_hi + W_hi X_lo + W_hi X_hi onto the bias, output rounded to BF16."""
+    Xh, Xl = _split(X0)
+    Wh, Wl = _split(W1)
+    pre = b1 + sum(cr.shift(Xh, dy, dx) @ (Wh[t] + Wl[t]) + cr.shift(Xl, dy, dx) @ Wh[t]
+                   for t, (dy, dx) in enumerate(cr.TAPS))
+    return _bf16(np.maximum(pre, 0))
+
+
 def _forward_bf16(p, un, uc):
     """The reference forward with the kernels' rounding points."""
     L = cr.unpack(p)
     X0 = cr.features(un, uc)
     W1, b1 = L[0]
-    Y = _bf16(np.maximum(b1 + sum(cr.shift(X0, dy, dx) @ W1[t] for t, (dy, dx) in enumerate(cr.TAPS)), 0))
+    Y = _input_layer_bf16(X0, W1, b1)
     for W, b in L[1:1 + cr.N_MID]:
         Wb = _bf16(W)
         Y = _bf16(np.maximum(b + sum(cr.shift(Y, dy, dx) @ Wb[t].T for t, (dy, dx) in enumerate(cr.TAPS)), 0))
@@ -53,7 +72,7 @@ def _grad_bf16(p, un, uc, uf, s_out):
     L = cr.unpack(p)
     X0 = cr.features(un, uc)
     W1, b1 = L[0]
-    acts = [X0, _bf16(np.maximum(b1 + sum(cr.shift(X0, dy, dx) @ W1[t] for t, (dy, dx) in enumerate(cr.TAPS)), 0))]
+    acts = [X0, _input_layer_bf16(X0, W1, b1)]
     for W, b in L[1:1 + cr.N_MID]:
         Wb = _bf16(W)
         acts.append(_bf16(np.maximum(b + sum(cr.shift(acts[-1], dy, dx) @ Wb[t].T
