@@ -686,6 +686,67 @@ def bench_three(args, torch, eife):
 PAPER_TABLE3 = {(512, 256): 1.121, (1024, 512): 4.444, (2048, 1024): 17.516, (4096, 2048): 75.944}
 
 
+def bench_longlines(args, torch, eife):
+    """The long-line passes on the manufactured problem's grid: 4096^2 intervals (4095^2 DoFs,
+    8192-point odd extensions on both axes), EIFE2 tau = 2^-10 from the exact initial state,
+    FP32 and FP64.  Per precision: K timed steps in one call after a settle and warm-up, then a
+    second run of K steps with per-pass event timing and each pass's algorithmic HBM rate
+    (x pass: W read and written; y stage passes: W and H read and written)."""
+    n_int = 4096
+    N, h = [n_int, n_int], [1.0 / n_int] * 2
+    ndof = (n_int - 1) ** 2
+    tau = 2.0 ** -10
+    steps = args.steps if args.steps != 200 else 20
+    warm = args.warmup if args.warmup != 20 else 5
+    s1 = np.sin(np.pi * np.arange(1, n_int) / n_int)
+    base = np.outer(s1, s1)
+    out = {}
+    log(f"bench: long lines, manufactured 2D {n_int - 1}^2 DoFs, EIFE2 tau=2^-10, steps={steps}")
+    for dt, tdt, esz in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
+        g = eife.Grid(N, h, 1.0, dt)
+        g.set_phi(tau, 2)
+        u = torch.tensor(base, dtype=tdt, device="cuda")
+        if args.settle > 0:
+            settle(torch, g, u, eife.F_MMS_U2, min(args.settle, 0.5), chunk=10)
+        g.step(u, warm, eife.F_MMS_U2, 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(u, steps, eife.F_MMS_U2, warm * tau)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        g.profile(True)
+        g.step(u, steps, eife.F_MMS_U2, (warm + steps) * tau)
+        prof = g.profile_read()
+        g.profile(False)
+        torch.cuda.synchronize()
+        g.close()
+        passes = {}
+        for name, (ms, cnt) in prof.items():
+            if cnt == 0:
+                continue
+            avg = ms / cnt * 1e-3
+            nbytes = BYTES_PER_DOF[name] * (esz // 4) * ndof
+            gbs = nbytes / avg / 1e9
+            passes[name] = {"launches": cnt, "avg_us": round(avg * 1e6, 2), "bytes_per_launch": nbytes,
+                            "alg_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+            log(f"  {dt} pass {name:10s} launches={cnt:5d} avg={avg * 1e6:8.2f} us alg={gbs:8.1f} GB/s "
+                f"({gbs / HBM_PEAK_GBS * 100:5.1f}% of HBM peak)")
+        out[dt] = {"ms_per_step": round(wall * 1e3, 4), "dof_steps_per_s": ndof / wall, "passes": passes}
+        log(f"bench: {dt} {wall * 1e3:.3f} ms/step, {ndof / wall:.4e} DoF-steps/s")
+    dom = max(out["f32"]["passes"].items(), key=lambda kv: kv[1]["avg_us"] * kv[1]["launches"])
+    line = {"metric": "long-line EIFE2 DoF-steps/s (4095^2 manufactured problem, 8192-point lines)",
+            "value": out["f32"]["dof_steps_per_s"], "unit": "DoF-steps/s", "n_gpus": 1, "steps": steps,
+            "warmup": warm, "ms_per_step": out["f32"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "manufactured 2D u_t = Lap u + u^2 + g, 4096^2 intervals, EIFE2 tau = 2^-10, "
+                                   "exact initial state; value: FP32 (FP64 under 'f64')", "dofs": ndof},
+            "roofline": {"bound": "hbm", "achieved": dom[1]["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": dom[1]["frac"], "traffic": None, "kernel": dom[0],
+                         "kernel_avg_us": dom[1]["avg_us"], "bytes_per_launch": dom[1]["bytes_per_launch"]},
+            "cpu_baseline": None, "f32": out["f32"], "f64": out["f64"]}
+    print(json.dumps(line), flush=True)
+
+
 def bench_table3(args, torch, eife):
     """The paper's timing table (Table 3): Example 5.1, u_t = (1/2) Lap u - (pi^2/2) u + (pi^2/2) e^{-pi^2 t}
     sin(pi x) sin(pi y) on (1/2, 5/2) x (0, 1), exact u = e^{-pi^2 t} (sin(pi x) - 1) sin(pi y), EIFE2 with
@@ -757,13 +818,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--workload", choices=["cube", "batched", "manufactured", "ex53", "ex52", "variable", "three", "table3",
-                                           "corrnet"], default="cube",
+                                           "corrnet", "longlines"], default="cube",
                     help="cube: 3D Allen-Cahn 255^3 (default line); batched: 512 independent 2D instances; "
                          "manufactured: 4095^2 orders, errors and rates; ex53: periodic 128^3 Flory-Huggins "
                          "grain coarsening to T = 20; ex52: traveling wave with Dirichlet data (Table 4); "
                          "variable: the cube problem with varying step sizes; three: the three-stage scheme; "
                          "table3: the paper's timing table (Example 5.1); corrnet: the corrector network's "
-                         "kernels alone (matrix-core rate)")
+                         "kernels alone (matrix-core rate); longlines: the 4095^2 manufactured grid's "
+                         "8192-point line passes, per-pass HBM rates")
     ap.add_argument("--transform", choices=["fft", "gemm"], default="fft",
                     help="cube workload: FFT sine transforms (default) or split-BF16 matrix-core products")
     ap.add_argument("--no-corrector", action="store_true",
@@ -799,6 +861,8 @@ def main():
         return bench_table3(args, torch, eife)
     if args.workload == "corrnet":
         return bench_corrnet(args, torch, eife)
+    if args.workload == "longlines":
+        return bench_longlines(args, torch, eife)
 
     N = [N_INT] * 3
     h = [1.0 / N_INT] * 3

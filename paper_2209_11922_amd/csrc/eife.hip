@@ -681,9 +681,10 @@ bool try_col_fast_per(const eife_grid_s* g, int axis, int mode, int outer, int c
   return false;
 }
 
-// Lines of 2048 and 4096 intervals (4096- and 8192-point odd extensions): one
-// line pair per block (eife_long.hpp); single grids, non-periodic.
-inline bool long_len(int N) { return N == 2048 || N == 4096; }
+// Lines of 1024, 2048 and 4096 intervals (2048-, 4096- and 8192-point odd
+// extensions): one line pair per block (eife_long.hpp); single grids,
+// non-periodic.
+inline bool long_len(int N) { return N == 1024 || N == 2048 || N == 4096; }
 
 template <typename T, int L>
 void row_long_launch(int mode, int nrows, hipStream_t s, const T* src, T* dst, T* dst2, const RowGeom& rg,
@@ -730,7 +731,9 @@ bool try_row_fast(const eife_grid_s* g, int var, int mode, int count, hipStream_
   if (g->transform != EIFE_TX_FFT || F.kind == FK_EX52) return false;
   if (long_len(g->N[0])) {
     if (count != 1 || ri || (mode != ROW_PHYS && mode != ROW_FWD_USER && mode != ROW_INV_USER)) return false;
-    if (g->N[0] == 2048)
+    if (g->N[0] == 1024)
+      row_long_launch<T, 2048>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F);
+    else if (g->N[0] == 2048)
       row_long_launch<T, 4096>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F);
     else
       row_long_launch<T, 8192>(mode, rg.nrows, s, src, dst, dst2, rg, tw, F);
@@ -760,7 +763,9 @@ bool try_col_fast(const eife_grid_s* g, int var, int axis, int mode, int outer, 
   if (g->transform != EIFE_TX_FFT) return false;
   if (long_len(g->N[axis])) {
     if (count != 1 || ci || mode > COL_ETD1) return false;
-    if (g->N[axis] == 2048)
+    if (g->N[axis] == 1024)
+      col_long_launch<T, 2048>(mode, g->pitch, outer, s, W, H, cg, tw, dg);
+    else if (g->N[axis] == 2048)
       col_long_launch<T, 4096>(mode, g->pitch, outer, s, W, H, cg, tw, dg);
     else
       col_long_launch<T, 8192>(mode, g->pitch, outer, s, W, H, cg, tw, dg);

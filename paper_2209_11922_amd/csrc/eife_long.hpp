@@ -1,13 +1,15 @@
-// Sine-transform passes for long lines: N = 2048 and 4096 intervals (complex
-// FFTs of L = 4096 and 8192 points of the odd extension of a line pair, as in
-// Section 4's per-dimension transforms; the packing is the one of eife_kernels.hpp).
+// Sine-transform passes for long lines: N = 1024, 2048 and 4096 intervals
+// (complex FFTs of L = 2048, 4096 and 8192 points of the odd extension of a
+// line pair, as in Section 4's per-dimension transforms; the packing is the one
+// of eife_kernels.hpp).
 //
 // A wavefront cannot hold such a line, so one block transforms one line pair:
 // NT = L / 16 threads with 16 complex values each, Stockham stages of radix 16
-// (16^3 = 4096; an 8192-point line adds a final radix-2 stage) whose exchanges
-// go through the pair's LDS buffer with block barriers, and the last stage's
-// outputs left in registers.  The generic passes do every stage as a full LDS
-// sweep; here the values stay in registers between exchanges.
+// (16^3 = 4096; a 2048-point line ends with a radix-8 stage, an 8192-point line
+// adds a final radix-2 stage) whose exchanges go through the pair's LDS buffer
+// with block barriers, and the last stage's outputs left in registers.  The
+// generic passes do every stage as a full LDS sweep; here the values stay in
+// registers between exchanges.
 #pragma once
 
 #include "eife_kernels.hpp"
@@ -24,12 +26,13 @@ struct Shape {
   static constexpr int E = 16;                        // complex values per thread
   static constexpr int NT = L / E;                    // threads per line pair
   static constexpr int BUF = ((L + L / 8 + 63) / 64) * 64 + 2;  // padded exchange buffer
-  static constexpr int RL = (L == 8192) ? 2 : 16;     // radix of the last stage
-  static_assert(L == 4096 || L == 8192, "long-line passes: 4096 or 8192 FFT points");
+  static constexpr int RL = (L == 8192) ? 2 : (L == 2048 ? 8 : 16);  // radix of the last stage
+  static_assert(L == 2048 || L == 4096 || L == 8192, "long-line passes: 2048, 4096 or 8192 FFT points");
 };
 
 // Registers per thread: FP32 8192-point lines fit 4 waves per SIMD (two blocks
-// per compute unit); the other shapes take what they need.
+// per compute unit); the other shapes take what they need (FP32 2048-point
+// stage passes spill at 4).
 template <typename T, int L>
 struct LongWaves {
   static constexpr int value = (sizeof(T) == 4 && L == 8192) ? 4 : 1;
@@ -105,6 +108,12 @@ __device__ __forceinline__ void odd_fft(Cx<T> (&v)[16], const Cx<T>* node, Cx<T>
   __syncthreads();
   stage<T, L, 16, 16, false>(v, buf, tw, t);
   __syncthreads();
+  if constexpr (L == 2048) {
+    gather<T, L, 8>(v, buf, t);
+    stage<T, L, 8, 256, true>(v, buf, tw, t);
+    __syncthreads();  // the buffer may be rewritten next
+    return;
+  }
   gather<T, L, 16>(v, buf, t);
   if constexpr (L == 8192) {
     __syncthreads();

@@ -18,5 +18,5 @@ def test_every_workload_is_listed_in_the_help():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
                        timeout=300)
     assert r.returncode == 0
-    for w in ("cube", "batched", "manufactured", "ex53", "ex52", "variable", "three", "table3", "corrnet"):
+    for w in ("cube", "batched", "manufactured", "ex53", "ex52", "variable", "three", "table3", "corrnet", "longlines"):
         assert w in r.stdout

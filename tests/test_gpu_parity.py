@@ -312,8 +312,10 @@ FAST_GRIDS = [
     _case("1d-512", [512]),
     _case("2d-192x384-radix3", [192, 384]),
     _case("3d-192x64x48-radix3", [192, 64, 48]),
-    # long lines (one line pair per block): x and last axis of 2048 and 4096 intervals,
-    # a 3D grid with a long mid axis (generic there) and a long last axis
+    # long lines (one line pair per block): x and last axis of 1024, 2048 and 4096
+    # intervals, a 3D grid with a long mid axis (generic there) and a long last axis
+    _case("2d-1024x24-long", [1024, 24]),
+    _case("2d-12x1024-long", [12, 1024]),
     _case("2d-2048x16-long", [2048, 16]),
     _case("2d-24x4096-long", [24, 4096]),
     _case("3d-4096x6x8-long", [4096, 6, 8]),
