@@ -293,7 +293,13 @@ int eife_batch_set_phi(eife_batch b, double tau, int stages);
 int eife_batch_step(eife_batch b, void* u, int64_t n_steps, int f_kind, double t0, void* stream);
 
 /* Choose, per size class, the launch shapes of the passes by timing the
- * candidates on the device (eife_batch_set_phi must come first).  With a
+ * candidates on the device (eife_batch_set_phi must come first): for the
+ * specialised line lengths two row tile widths and, for columns, two tile
+ * widths with one tile per block plus (FP32) the widest tiles in a persistent
+ * stage pass that prefetches each next tile across instances; for the other
+ * lengths the line pairs per block of both passes.  Every choice gives the
+ * same results bit for bit.  Before tuning, FP32 classes of 512-interval
+ * columns use the persistent stage pass, the others the widest tiles.  With a
  * non-null cache_path, choices recorded there for this device, dtype and
  * class are reused, and new ones are added to the file (JSON).  Blocks the
  * host.  The timing runs leave the batch's internal state undefined; the
@@ -302,8 +308,9 @@ int eife_batch_autotune(eife_batch b, const char* cache_path, void* stream);
 
 /* Launch shape chosen for size class k (order of first appearance):
  * out[0] = class N_x, out[1] = N_y, out[2] = instances, out[3] = row-pass
- * variant, out[4] = column-pass variant.  Returns EIFE_EINVAL past the last
- * class. */
+ * variant, out[4] = column-pass variant (specialised lengths: 0 / 1 tile
+ * widths, 2 the persistent stage pass; other lengths: line pairs per block).
+ * Returns EIFE_EINVAL past the last class. */
 int eife_batch_class_info(eife_batch b, int k, int32_t* out);
 
 /* Number of unknown nodes of the grid (elements of a nodal array). */

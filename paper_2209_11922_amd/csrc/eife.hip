@@ -553,13 +553,40 @@ void col_fast_go(int mode, int pitch, int outer, int count, bool pipe, hipStream
     if (pipe && ntiles >= kStagePipeMinTiles * nblk && mode < COL_S3_1) {
       if (mode == COL_STAGE_A)
         hipLaunchKernelGGL((fast::col_stage_pipe<T, L, PB, PPW, COL_STAGE_A>), dim3(nblk), dim3(NT), 0, s, W, H, cg,
-                           tw, dg, ntx, ntiles);
+                           tw, dg, ntx, ntiles, (const ColInst<T>*)nullptr, 0);
       else if (mode == COL_STAGE_B)
         hipLaunchKernelGGL((fast::col_stage_pipe<T, L, PB, PPW, COL_STAGE_B>), dim3(nblk), dim3(NT), 0, s, W, H, cg,
-                           tw, dg, ntx, ntiles);
+                           tw, dg, ntx, ntiles, (const ColInst<T>*)nullptr, 0);
       else
         hipLaunchKernelGGL((fast::col_stage_pipe<T, L, PB, PPW, COL_ETD1>), dim3(nblk), dim3(NT), 0, s, W, H, cg,
-                           tw, dg, ntx, ntiles);
+                           tw, dg, ntx, ntiles, (const ColInst<T>*)nullptr, 0);
+      return;
+    }
+  }
+  // batched FP32 classes, column variant 2: the pipelined stage pass over
+  // every tile of every instance (faster for 1024-point lines, where one
+  // 8-wave block fills a CU; slower for 768-point lines: the autotuner decides)
+  if constexpr (BAT && sizeof(T) == 4) {
+    if (pipe && ci && (mode == COL_STAGE_A || mode == COL_STAGE_B || mode == COL_ETD1)) {
+      const int ntx = pitch / (2 * PB);
+      const int tpi = ntx * outer;
+      const int ntiles = tpi * count;
+      auto go = [&](auto kern) {
+        static int per_cu = 0;
+        if (per_cu == 0 &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), NT, 0) !=
+                hipSuccess)
+          per_cu = 1;
+        const int nblk = std::min(ntiles, g_cus * std::max(1, per_cu));
+        if (!launch_shape_ok(dim3(nblk), NT, size_t(PB) * fast::Line<T, L>::BUF * sizeof(Cx<T>))) return;
+        hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), 0, s, W, H, cg, tw, dg, ntx, ntiles, ci, tpi);
+      };
+      if (mode == COL_STAGE_A)
+        go(fast::col_stage_pipe<T, L, PB, PPW, COL_STAGE_A, true>);
+      else if (mode == COL_STAGE_B)
+        go(fast::col_stage_pipe<T, L, PB, PPW, COL_STAGE_B, true>);
+      else
+        go(fast::col_stage_pipe<T, L, PB, PPW, COL_ETD1, true>);
       return;
     }
   }
@@ -587,10 +614,12 @@ template <typename T, int L>
 void col_fast_launch(int var, int mode, int pitch, int outer, int count, hipStream_t s, T* W, T* H,
                      const ColGeom& cg, const Cx<T>* tw, const Diag& dg, const ColInst<T>* ci) {
   if (ci) {
-    if (var == 0)
-      col_fast_go<T, L, col_pb<T, L>(0), true>(mode, pitch, outer, count, false, s, W, H, cg, tw, dg, ci);
-    else
+    // batched variants: 0 / 1 the two tile widths (one tile per block), 2 the
+    // widest tiles in the persistent pipelined stage pass
+    if (var == 1)
       col_fast_go<T, L, col_pb<T, L>(1), true>(mode, pitch, outer, count, false, s, W, H, cg, tw, dg, ci);
+    else
+      col_fast_go<T, L, col_pb<T, L>(0), true>(mode, pitch, outer, count, var == 2, s, W, H, cg, tw, dg, ci);
   } else {
     // a single grid with few column tiles (2D grids): narrower tiles
     constexpr int pb0 = col_pb<T, L>(0);
@@ -1951,8 +1980,9 @@ int tune_class(eife_batch_s* b, eife_batch_s::Class& c, const char* path, hipStr
   const bool fast = g->transform == EIFE_TX_FFT && fast_len<T>(g->N[0]) && fast_len<T>(g->N[1]);
   std::vector<std::array<int, 4>> cands;
   if (fast) {
+    const int ncol = sizeof(T) == 4 ? 3 : 2;  // FP32: also the pipelined stage pass
     for (int r = 0; r < 2; ++r)
-      for (int cc = 0; cc < 2; ++cc) cands.push_back({r, cc, 0, 0});
+      for (int cc = 0; cc < ncol; ++cc) cands.push_back({r, cc, 0, 0});
   } else {
     for (int pr : {4, 8, 16})
       for (int pc : {4, 8, 16}) cands.push_back({0, 0, pr, pc});
@@ -2027,6 +2057,12 @@ int eife_create_batch(int B, const int32_t* N, const double* h, const double* D,
       found = int(b->classes.size()) - 1;
     }
     b->classes[found].members.push_back(i);
+  }
+  // default column variant before any tuning: FP32 classes of 512-interval
+  // columns take the pipelined stage pass (measured faster)
+  for (auto& c : b->classes) {
+    const eife_grid_s* g0 = b->inst[c.members[0]];
+    if (dtype == EIFE_F32 && g0->N[1] == 512 && g0->transform == EIFE_TX_FFT) c.var_col = 2;
   }
   const int r = dtype == EIFE_F32 ? build_batch_tables<float>(b) : build_batch_tables<double>(b);
   if (r != EIFE_OK) {

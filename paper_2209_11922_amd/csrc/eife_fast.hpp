@@ -771,9 +771,10 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
 // transform and the tile's stores.  H is read inside the stage: holding the
 // next tile's H values too exceeds the 128 registers per lane that 4 waves per
 // SIMD leave (the FP64 stage spills), and measured slower.
-template <typename T, int L, int PB, int PPW, int MODE>
+template <typename T, int L, int PB, int PPW, int MODE, bool BAT = false>
 __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::value))
-    col_stage_pipe(T* __restrict__ W, T* __restrict__ H, ColGeom g, const Cx<T>* tw, Diag dg, int ntx, int ntiles) {
+    col_stage_pipe(T* __restrict__ W, T* __restrict__ H, ColGeom g, const Cx<T>* tw, Diag dg, int ntx, int ntiles,
+                   const ColInst<T>* __restrict__ insts, int tiles_per_inst) {
   using Ln = Line<T, L>;
   constexpr int N = L / 2;
   constexpr int n = N - 1;
@@ -791,29 +792,47 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
   const int m0 = tid / PB;
   const int ldl = int(g.ld_line);
   const T scale = T(1.0 / sqrt(double(L)));
-  const double tau = dg.tau, D = dg.D;
+  const double tau = dg.tau;
   const double rtc2 = 1.0 / (tau * dg.c2);
-  const AxisTab ta0 = dg.ax[0], ta1 = dg.ax[1], ta2 = dg.ax[2];
-  const AxisTab line_tab = g.last_is_z ? ta2 : ta1;
   typename Ln::Tw twl;
   twl.load(tw, lane);
   Cx<T>* ltile = lds + tq * BUF + m0;
+  // tile t: instance t / tiles_per_inst of a batched launch (else the grid),
+  // outer index and column tile of the rest
+  auto inst_of = [&](int t) { return BAT ? t / tiles_per_inst : 0; };
+  auto local = [&](int t) { return BAT ? t - inst_of(t) * tiles_per_inst : t; };
+  auto wbase = [&](int t) -> T* { return BAT ? insts[inst_of(t)].W : W; };
   // element offset of this thread's first tile value (pair tq, row m0) in tile t
   auto offset = [&](int t) -> int64_t {
-    return int64_t(t / ntx) * g.ld_outer + ((t % ntx) * 2 * PB + m0 * ldl + 2 * tq);
+    const int lt = local(t);
+    return int64_t(lt / ntx) * g.ld_outer + ((lt % ntx) * 2 * PB + m0 * ldl + 2 * tq);
   };
   Cx<T> pw[CIT];
   int t = blockIdx.x;
   if (t < ntiles) {
-    const Cx<T>* gw = reinterpret_cast<const Cx<T>*>(W + offset(t));
+    const Cx<T>* gw = reinterpret_cast<const Cx<T>*>(wbase(t) + offset(t));
 #pragma unroll
     for (int it = 0; it < CIT; ++it)
       if (m0 + MS * it < n) pw[it] = gw[(MS * it * ldl) / 2];
   }
   for (; t < ntiles; t += gridDim.x) {
-    const int outer = t / ntx;
-    const int kx0 = (t % ntx) * 2 * PB + 2 * tq;  // first column of this thread's pair
+    const int lt = local(t);
+    const int outer = lt / ntx;
+    const int kx0 = (lt % ntx) * 2 * PB + 2 * tq;  // first column of this thread's pair
     const int64_t off = offset(t);
+    T* const Wt = wbase(t);
+    T* const Ht = BAT ? insts[inst_of(t)].H : H;
+    // per-instance tables of a batched launch are held in separate locals
+    AxisTab ta0 = dg.ax[0], ta1 = dg.ax[1], ta2 = dg.ax[2];
+    double D = dg.D;
+    if constexpr (BAT) {
+      const ColInst<T>& I = insts[inst_of(t)];
+      ta0 = I.ax[0];
+      ta1 = I.ax[1];
+      ta2 = I.ax[2];
+      D = I.D;
+    }
+    const AxisTab line_tab = g.last_is_z ? ta2 : ta1;
 #pragma unroll
     for (int it = 0; it < CIT; ++it)
       if (m0 + MS * it < n) ltile[MS * it] = mask_pad(pw[it], kx0, g.ncols);
@@ -833,7 +852,7 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
       const Sep so = g.last_is_z ? sep_load(ta1, outer) : sep_load(ta2, 0);
       sxy[0] = sep_combine(sep_load(ta0, kx0), so);
       sxy[1] = sep_combine(sep_load(ta0, kx0 + 1), so);
-      Cx<T>* hrow = reinterpret_cast<Cx<T>*>(H + off);
+      Cx<T>* hrow = reinterpret_cast<Cx<T>*>(Ht + off);
 #pragma unroll
       for (int it = 0; it < CIT; ++it) {
         const int m = m0 + MS * it;
@@ -850,7 +869,7 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
       }
     }
     if (tn < ntiles) {
-      const Cx<T>* gw = reinterpret_cast<const Cx<T>*>(W + offset(tn));
+      const Cx<T>* gw = reinterpret_cast<const Cx<T>*>(wbase(tn) + offset(tn));
 #pragma unroll
       for (int it = 0; it < CIT; ++it)
         if (m0 + MS * it < n) pw[it] = gw[(MS * it * ldl) / 2];
@@ -863,7 +882,7 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
       Ln::outputs(v, lane, tw, [&](int k, Cx<T> Z) { my[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
     }
     __syncthreads();
-    Cx<T>* gd = reinterpret_cast<Cx<T>*>(W + off);
+    Cx<T>* gd = reinterpret_cast<Cx<T>*>(Wt + off);
 #pragma unroll
     for (int it = 0; it < CIT; ++it)
       if (m0 + MS * it < n) gd[(MS * it * ldl) / 2] = mask_pad(ltile[MS * it], kx0, g.ncols);

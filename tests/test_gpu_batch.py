@@ -70,6 +70,21 @@ def test_batch_equals_single_grids_bitwise(dtype, stages):
     b.close()
 
 
+@pytest.mark.parametrize("stages", [1, 2])
+def test_batch_long_column_classes_equal_single_grids_bitwise(stages):
+    """FP32 classes of 1024-point columns (512 intervals) run the pipelined stage pass
+    over every tile of every instance (768-point columns the one-tile form); each
+    instance equals its single grid (one tile per block) bit for bit."""
+    inst = [(512, 512, 4e-4), (512, 512, 2.5e-3), (512, 512, 1e-4), (384, 384, 9e-4), (384, 384, 1.6e-3),
+            (256, 512, 1e-3)]
+    u0s = _inputs(inst, 300)
+    b, outs = _batch_run(inst, u0s, 0.01, 4, stages, "f32")
+    for (nx, ny, D), u0, got in zip(inst, u0s, outs):
+        ref = _single(nx, ny, D, u0, 0.01, 4, stages, "f32")
+        assert np.array_equal(got, ref), (nx, ny, D)
+    b.close()
+
+
 def test_batch_matches_oracle():
     inst = _mixed_instances()
     u0s = _inputs(inst, 7)
