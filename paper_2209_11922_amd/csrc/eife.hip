@@ -75,7 +75,7 @@ int g_cus = 256;                     // compute units of the device (set at grid
 
 bool factor_plan(int L, FftPlan* pl) {
   pl->L = L;
-  pl->n8 = pl->n4 = pl->n2 = pl->n3 = 0;
+  pl->n8 = pl->n4 = pl->n2 = pl->n3 = pl->n5 = pl->n7 = 0;
   int r = L;
   while (r % 8 == 0) {
     r /= 8;
@@ -92,6 +92,14 @@ bool factor_plan(int L, FftPlan* pl) {
   while (r % 3 == 0) {
     r /= 3;
     pl->n3++;
+  }
+  while (r % 5 == 0) {
+    r /= 5;
+    pl->n5++;
+  }
+  while (r % 7 == 0) {
+    r /= 7;
+    pl->n7++;
   }
   return r == 1;
 }
@@ -1457,7 +1465,7 @@ int eife_create_grid(int d, const int32_t* N, const double* h, double D, int bc,
     if (!factor_plan(g->per[a] ? g->N[a] : 2 * g->N[a], &g->plan[a])) {
       const int bad = g->N[a];
       delete g;
-      return fail(EIFE_EUNSUPPORTED, "N = %d is not of the form 2^i 3^j", bad);
+      return fail(EIFE_EUNSUPPORTED, "N = %d is not of the form 2^i 3^j 5^k 7^l", bad);
     }
   }
   g->pitch = ((g->n[0] + 31) / 32) * 32;

@@ -7,7 +7,7 @@
 // length L = 2N (z_m = c_m, z_{2N-m} = -c_m, z_0 = z_N = 0), a complex FFT of
 // length L gives Z_k = -2i (P a + i P b)_k, so the orthonormal transform
 // S = sqrt(2/N) P is (S a)_k = -Im Z_k / sqrt(2N), (S b)_k = Re Z_k / sqrt(2N).
-// The FFT is a mixed radix-4/2/3 Stockham autosort on lines held in LDS.
+// The FFT is a mixed radix-8/4/2/3/5/7 Stockham autosort on lines held in LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -94,6 +94,61 @@ struct Dft<T, 8> {
   }
 };
 
+// Odd prime P: with a_r = v_r + v_{P-r}, b_r = v_r - v_{P-r} (r = 1 .. (P-1)/2)
+// and theta = 2 pi r k / P,
+//   X_k     = v_0 + sum_r a_r cos(theta) - i sum_r b_r sin(theta),
+//   X_{P-k} = v_0 + sum_r a_r cos(theta) + i sum_r b_r sin(theta);
+// cs[m-1], sn[m-1] hold cos and sin of 2 pi m / P for m = 1 .. (P-1)/2.
+template <typename T, int P>
+__device__ __forceinline__ void dft_odd_prime(Cx<T>* v, const T (&cs)[(P - 1) / 2], const T (&sn)[(P - 1) / 2]) {
+  constexpr int Hh = (P - 1) / 2;
+  Cx<T> a[Hh], b[Hh];
+  Cx<T> sum = v[0];
+#pragma unroll
+  for (int r = 1; r <= Hh; ++r) {
+    a[r - 1] = cadd(v[r], v[P - r]);
+    b[r - 1] = csub(v[r], v[P - r]);
+    sum = cadd(sum, a[r - 1]);
+  }
+  Cx<T> out[P];
+  out[0] = sum;
+#pragma unroll
+  for (int k = 1; k <= Hh; ++k) {
+    Cx<T> re = v[0], im = {T(0), T(0)};
+#pragma unroll
+    for (int r = 1; r <= Hh; ++r) {
+      const int m = (r * k) % P;
+      const int i = m <= Hh ? m : P - m;
+      const T c = cs[i - 1];
+      const T sg = m <= Hh ? sn[i - 1] : -sn[i - 1];
+      re = Cx<T>{re.re + c * a[r - 1].re, re.im + c * a[r - 1].im};
+      im = Cx<T>{im.re + sg * b[r - 1].re, im.im + sg * b[r - 1].im};
+    }
+    out[k] = Cx<T>{re.re + im.im, re.im - im.re};      // re - i im
+    out[P - k] = Cx<T>{re.re - im.im, re.im + im.re};  // re + i im
+  }
+#pragma unroll
+  for (int q = 0; q < P; ++q) v[q] = out[q];
+}
+
+template <typename T>
+struct Dft<T, 5> {
+  static __device__ __forceinline__ void run(Cx<T>* v) {
+    const T cs[2] = {T(0.30901699437494742410), T(-0.80901699437494742410)};
+    const T sn[2] = {T(0.95105651629515357212), T(0.58778525229247312917)};
+    dft_odd_prime<T, 5>(v, cs, sn);
+  }
+};
+
+template <typename T>
+struct Dft<T, 7> {
+  static __device__ __forceinline__ void run(Cx<T>* v) {
+    const T cs[3] = {T(0.62348980185873353053), T(-0.22252093395631440429), T(-0.90096886790241912624)};
+    const T sn[3] = {T(0.78183148246802980871), T(0.97492791218182360702), T(0.43388373911755812048)};
+    dft_odd_prime<T, 7>(v, cs, sn);
+  }
+};
+
 // Per-thread element budget of one in-place Stockham stage: P * L <= kMaxElems * 256
 // (a 256-thread block holds 32 values per thread; the 1024-thread variants for
 // long lines hold 8).
@@ -142,7 +197,7 @@ __device__ void stockham_stage(Cx<T>* lds, int ls, int L, int P, int Ns, const C
 
 struct FftPlan {
   int L;      // FFT length (2N)
-  int n8, n4, n2, n3;  // number of radix-8, radix-4, radix-2, radix-3 stages
+  int n8, n4, n2, n3, n5, n7;  // number of radix-8, -4, -2, -3, -5 and -7 stages
 };
 
 // Forward FFT of P lines in LDS (natural order in and out).  Callers must
@@ -166,6 +221,14 @@ __device__ void fft_lines(Cx<T>* lds, int ls, int P, FftPlan pl, const Cx<T>* __
   for (int i = 0; i < pl.n3; ++i) {
     stockham_stage<T, 3, ME>(lds, ls, pl.L, P, Ns, tw);
     Ns *= 3;
+  }
+  for (int i = 0; i < pl.n5; ++i) {
+    stockham_stage<T, 5, ME>(lds, ls, pl.L, P, Ns, tw);
+    Ns *= 5;
+  }
+  for (int i = 0; i < pl.n7; ++i) {
+    stockham_stage<T, 7, ME>(lds, ls, pl.L, P, Ns, tw);
+    Ns *= 7;
   }
 }
 

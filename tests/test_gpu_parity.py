@@ -265,7 +265,7 @@ def test_runs_on_a_side_stream():
 def test_abi_errors():
     eife = _lib()
     with pytest.raises(eife.EIFEError) as e:
-        eife.Grid([10, 8], [0.1, 0.1], 1.0)  # 2N = 20 has a factor 5
+        eife.Grid([11, 8], [0.1, 0.1], 1.0)  # 2N = 22 has a factor 11
     assert e.value.code == -3
     with pytest.raises(eife.EIFEError) as e:
         eife.Grid([8, 8], [0.1, -0.1], 1.0)
@@ -274,7 +274,7 @@ def test_abi_errors():
         eife.Grid([8, 8], [0.1, 0.1], 1.0, bc=7)  # no such boundary condition
     assert e.value.code == -1
     with pytest.raises(eife.EIFEError) as e:
-        eife.Grid([10, 8], [0.1, 0.1], 1.0, bc=eife.BC_PERIODIC)  # periodic N = 10 has a factor 5
+        eife.Grid([22, 8], [0.1, 0.1], 1.0, bc=eife.BC_PERIODIC)  # periodic N = 22 has a factor 11
     assert e.value.code == -3
     g = eife.Grid([8, 8], [0.1, 0.1], 1.0)
     u = torch.zeros(7, 7, dtype=torch.float64, device="cuda")
@@ -346,6 +346,54 @@ def test_specialised_passes_match_generic_and_oracle(N, dtype, stages):
     assert _rel(outs[0], ref) <= TOL[dtype]
     assert _rel(outs[1], ref) <= TOL[dtype]
     assert _rel(outs[0], outs[1]) <= TOL[dtype]
+
+
+SMOOTH_GRIDS = [
+    _case("1d-35", [35]),                  # 2N = 70 = 2 5 7
+    _case("2d-10x14", [10, 14]),           # radix 5 and radix 7 stages
+    _case("2d-100x49", [100, 49]),         # 2N = 200 = 8 25, 98 = 2 49
+    _case("3d-20x21x25", [20, 21, 25]),    # 2, 3, 5 and 7 mixed
+    _case("2d-1000x6", [1000, 6]),         # a long 5-smooth row
+]
+
+
+@pytest.mark.parametrize("N", SMOOTH_GRIDS)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_radix5_radix7_sizes_match_oracle(N, dtype):
+    """Sizes whose 2N has factors 5 and 7 (generic radix-5 / radix-7 Stockham stages)
+    against the oracle (scipy's DST-I: any N), EIFE2, both precisions."""
+    eife = _lib()
+    h = [1.0 / n for n in N]
+    D = 2e-3
+    u0 = seeded_inputs.uniform_field(41, N)
+    g = eife.Grid(N, h, D, dtype)
+    g.set_phi(0.01, 2)
+    u = torch.tensor(u0, dtype=g.torch_dtype, device="cuda")
+    g.step(u, 5, eife.F_ALLEN_CAHN)
+    torch.cuda.synchronize()
+    ref = _oracle("C", N, h, D, u0, problems.allen_cahn(), 0.01, 5, 2)
+    err = _rel(u.double().cpu().numpy(), ref)
+    print(f"{N} {dtype}: {err:.2e}")
+    assert err <= TOL[dtype]
+    g.close()
+
+
+@pytest.mark.parametrize("N", [[25, 35], [20, 14, 10]])
+def test_radix5_radix7_periodic_match_oracle(N):
+    """Periodic grids of 5- and 7-smooth sizes (FFT length N) against the oracle."""
+    eife = _lib()
+    h = [1.0 / n for n in N]
+    D = 1e-3
+    u0 = seeded_inputs.uniform_field(42, [n + 1 for n in N])  # N nodes per axis
+    g = eife.Grid(N, h, D, "f64", bc=eife.BC_PERIODIC)
+    g.set_phi(0.01, 2)
+    u = torch.tensor(u0, device="cuda")
+    g.step(u, 5, eife.F_ALLEN_CAHN)
+    torch.cuda.synchronize()
+    basis = spectral.make_basis("C", N, h, D, bc="periodic")
+    ref = stepper.run(basis, u0, problems.allen_cahn(), 0.01, 5, 2)
+    assert _rel(u.cpu().numpy(), ref) <= 1e-12
+    g.close()
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
