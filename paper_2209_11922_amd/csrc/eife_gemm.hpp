@@ -71,8 +71,11 @@ struct Acc {
   f32x4 v[Shape<KP>::MPW][Shape<KP>::LT];
 };
 
-// acc = S * B over the block's lines for the wave's mode tiles.
-template <int KP>
+// acc = S * B over the block's lines for the wave's mode tiles.  PF: the S
+// fragments of the next k step are loaded (from L2) while this step's products
+// run (the passes whose stage code already needs more than 128 registers keep
+// PF off: the extra registers would cost them a wave per SIMD, measured slower).
+template <int KP, bool PF = true>
 __device__ __forceinline__ void gemm_block(Acc<KP>& acc, const __bf16* bhi, const __bf16* blo, SMat S, int wave,
                                            int lane) {
   using Sh = Shape<KP>;
@@ -82,7 +85,43 @@ __device__ __forceinline__ void gemm_block(Acc<KP>& acc, const __bf16* bhi, cons
   for (int i = 0; i < Sh::MPW; ++i)
 #pragma unroll
     for (int t = 0; t < Sh::LT; ++t) acc.v[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (!PF) {
+    for (int kk = 0; kk < KP; kk += 32) {
+      bf16x8 xh[Sh::LT], xl[Sh::LT];
+#pragma unroll
+      for (int t = 0; t < Sh::LT; ++t) {
+        const int o = (t * 16 + row) * Sh::LS + kk + kq;
+        xh[t] = *reinterpret_cast<const bf16x8*>(bhi + o);
+        xl[t] = *reinterpret_cast<const bf16x8*>(blo + o);
+      }
+#pragma unroll
+      for (int i = 0; i < Sh::MPW; ++i) {
+        const size_t off = size_t((wave + Sh::WV * i) * 16 + row) * KP + kk + kq;
+        const bf16x8 sh = *reinterpret_cast<const bf16x8*>(S.hi + off);
+        const bf16x8 sl = *reinterpret_cast<const bf16x8*>(S.lo + off);
+#pragma unroll
+        for (int t = 0; t < Sh::LT; ++t) {
+          acc.v[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, xh[t], acc.v[i][t], 0, 0, 0);
+          acc.v[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, xl[t], acc.v[i][t], 0, 0, 0);
+          acc.v[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sl, xh[t], acc.v[i][t], 0, 0, 0);
+        }
+      }
+    }
+    return;
+  }
+  bf16x8 sh[Sh::MPW], sl[Sh::MPW];
+  auto load_s = [&](int kk, bf16x8 (&h)[Sh::MPW], bf16x8 (&l)[Sh::MPW]) {
+#pragma unroll
+    for (int i = 0; i < Sh::MPW; ++i) {
+      const size_t off = size_t((wave + Sh::WV * i) * 16 + row) * KP + kk + kq;
+      h[i] = *reinterpret_cast<const bf16x8*>(S.hi + off);
+      l[i] = *reinterpret_cast<const bf16x8*>(S.lo + off);
+    }
+  };
+  load_s(0, sh, sl);
   for (int kk = 0; kk < KP; kk += 32) {
+    bf16x8 shn[Sh::MPW], sln[Sh::MPW];
+    if (kk + 32 < KP) load_s(kk + 32, shn, sln);
     bf16x8 xh[Sh::LT], xl[Sh::LT];
 #pragma unroll
     for (int t = 0; t < Sh::LT; ++t) {
@@ -92,15 +131,18 @@ __device__ __forceinline__ void gemm_block(Acc<KP>& acc, const __bf16* bhi, cons
     }
 #pragma unroll
     for (int i = 0; i < Sh::MPW; ++i) {
-      const int mt = wave + Sh::WV * i;
-      const size_t off = size_t(mt * 16 + row) * KP + kk + kq;
-      const bf16x8 sh = *reinterpret_cast<const bf16x8*>(S.hi + off);
-      const bf16x8 sl = *reinterpret_cast<const bf16x8*>(S.lo + off);
 #pragma unroll
       for (int t = 0; t < Sh::LT; ++t) {
-        acc.v[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, xh[t], acc.v[i][t], 0, 0, 0);
-        acc.v[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, xl[t], acc.v[i][t], 0, 0, 0);
-        acc.v[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sl, xh[t], acc.v[i][t], 0, 0, 0);
+        acc.v[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh[i], xh[t], acc.v[i][t], 0, 0, 0);
+        acc.v[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh[i], xl[t], acc.v[i][t], 0, 0, 0);
+        acc.v[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sl[i], xh[t], acc.v[i][t], 0, 0, 0);
+      }
+    }
+    if (kk + 32 < KP) {
+#pragma unroll
+      for (int i = 0; i < Sh::MPW; ++i) {
+        sh[i] = shn[i];
+        sl[i] = sln[i];
       }
     }
   }
@@ -195,8 +237,9 @@ __global__ void __launch_bounds__(Shape<KP>::THREADS) gemm_row(const float* src,
     split_bf16(x, bhi[l * Sh::LS + k], blo[l * Sh::LS + k]);
   }
   __syncthreads();
+  constexpr bool PF = AC || MODE != ROW_PHYS;
   Acc<KP> acc;
-  gemm_block<KP>(acc, bhi, blo, S, wave, lane);
+  gemm_block<KP, PF>(acc, bhi, blo, S, wave, lane);
   if (MODE == ROW_PHYS) {
     for_acc<KP>(acc, wave, lane, [&](int m, int l, float& v) {
       const int r = r0 + l;
@@ -205,7 +248,7 @@ __global__ void __launch_bounds__(Shape<KP>::THREADS) gemm_row(const float* src,
     __syncthreads();
     acc_to_b<KP>(acc, bhi, blo, n, wave, lane);
     __syncthreads();
-    gemm_block<KP>(acc, bhi, blo, S, wave, lane);
+    gemm_block<KP, PF>(acc, bhi, blo, S, wave, lane);
   }
   __syncthreads();
   acc_to_stage<KP>(acc, stage, wave, lane);
@@ -261,8 +304,9 @@ __global__ void __launch_bounds__(Shape<KP>::THREADS) gemm_col(float* W, float* 
     *reinterpret_cast<bf16x8*>(blo + l * Sh::LS + k0) = lo;
   }
   __syncthreads();
+  constexpr bool PF = MODE == COL_PLAIN;
   Acc<KP> acc;
-  gemm_block<KP>(acc, bhi, blo, S, wave, lane);
+  gemm_block<KP, PF>(acc, bhi, blo, S, wave, lane);
   if (MODE != COL_PLAIN) {
     // diagonal stage: the x (and fixed outer-axis) factors of a lane's LT
     // columns are combined once, the line-axis factor per mode
@@ -296,7 +340,7 @@ __global__ void __launch_bounds__(Shape<KP>::THREADS) gemm_col(float* W, float* 
     __syncthreads();
     acc_to_b<KP>(acc, bhi, blo, n, wave, lane);
     __syncthreads();
-    gemm_block<KP>(acc, bhi, blo, S, wave, lane);
+    gemm_block<KP, PF>(acc, bhi, blo, S, wave, lane);
   }
   __syncthreads();
   acc_to_stage_t<KP>(acc, stage, wave, lane);
