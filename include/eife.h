@@ -179,6 +179,15 @@ int eife_set_forcing(eife_grid g, double c0, double c1);
  * nodal load, three stages with the split-BF16 transform), EIFE_EHIP. */
 int eife_step(eife_grid g, void* u, int64_t n_steps, int f_kind, double t0, void* stream);
 
+/* eife_step out of place: the steps start from u_in and their result goes to
+ * u_out (both device pointers holding the grid's element count; u_in is read
+ * only by the first pass of the call, so the two may be the same or overlap,
+ * and u_in is otherwise left as it was).  With n_steps = 0, u_in is copied to
+ * u_out.  The recurrence and its results are those of eife_step, bit for bit.
+ * Errors: those of eife_step, and EIFE_EINVAL for a null u_in or u_out. */
+int eife_step_out(eife_grid g, const void* u_in, void* u_out, int64_t n_steps, int f_kind, double t0,
+                  void* stream);
+
 /* Variable step sizes (Section 2.2 lets the step vary): advance u (device,
  * in place) by n_steps steps of sizes taus[0 .. n_steps-1] (host array, each
  * > 0 and finite), t_{n+1} = t_n + tau_n from t_0 = t0 (a running sum in
@@ -295,7 +304,7 @@ int eife_batch_step(eife_batch b, void* u, int64_t n_steps, int f_kind, double t
 /* Choose, per size class, the launch shapes of the passes by timing the
  * candidates on the device (eife_batch_set_phi must come first): for the
  * specialised line lengths two row tile widths and, for columns, two tile
- * widths with one tile per block plus (FP32) the widest tiles in a persistent
+ * widths with one tile per block plus (FP32) both widths in a persistent
  * stage pass that prefetches each next tile across instances; for the other
  * lengths the line pairs per block of both passes.  Every choice gives the
  * same results bit for bit.  Before tuning, FP32 classes of 512-interval
@@ -309,7 +318,8 @@ int eife_batch_autotune(eife_batch b, const char* cache_path, void* stream);
 /* Launch shape chosen for size class k (order of first appearance):
  * out[0] = class N_x, out[1] = N_y, out[2] = instances, out[3] = row-pass
  * variant, out[4] = column-pass variant (specialised lengths: 0 / 1 tile
- * widths, 2 the persistent stage pass; other lengths: line pairs per block).
+ * widths, 2 / 3 the persistent stage pass at those widths; other lengths:
+ * line pairs per block).
  * Returns EIFE_EINVAL past the last class. */
 int eife_batch_class_info(eife_batch b, int k, int32_t* out);
 
@@ -413,7 +423,10 @@ int eife_corr_infer_step(eife_corr c, eife_grid coarse, eife_grid fine, float* u
  * eife_corr_infer_step bit for bit.  Step k + 1 is enqueued before the host
  * reads step k's indicator (assuming acceptance) and enqueued again after a
  * fallback, so the device does not idle while the host decides; the host
- * still waits once per step. */
+ * still waits once per step.  The state moves between u and two buffers of
+ * the corrector (no copy per step; one copy into u at the end when the last
+ * state is elsewhere), so u holds intermediate states until the call's work
+ * has run. */
 int eife_corr_run(eife_corr c, eife_grid coarse, eife_grid fine, float* u, double t0, double tau_coarse,
                   int64_t n_steps, int64_t fine_steps, double theta, int64_t* fallbacks, void* stream);
 

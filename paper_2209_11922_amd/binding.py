@@ -51,6 +51,7 @@ def load_library():
     lib.eife_set_forcing.argtypes = [c_void_p, c_double, c_double]
     lib.eife_set_transform.argtypes = [c_void_p, c_int]
     lib.eife_step.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_int, c_double, c_void_p]
+    lib.eife_step_out.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_int64, c_int, c_double, c_void_p]
     lib.eife_norms.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]
     lib.eife_norms_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.eife_set_nodes3.argtypes = [c_void_p, c_double, c_double]
@@ -95,7 +96,7 @@ def load_library():
     lib.eife_last_error.argtypes = []
     lib.eife_version.argtypes = []
     for name in ("eife_create_grid", "eife_destroy_grid", "eife_set_phi", "eife_set_c2", "eife_set_origin",
-                 "eife_set_load", "eife_set_forcing", "eife_step", "eife_step_variable", "eife_set_nodes3", "eife_norms", "eife_energy", "eife_grid_size",
+                 "eife_set_load", "eife_set_forcing", "eife_step", "eife_step_out", "eife_step_variable", "eife_set_nodes3", "eife_norms", "eife_energy", "eife_grid_size",
                  "eife_version", "eife_profile", "eife_profile_read", "eife_set_transform", "eife_create_batch",
                  "eife_destroy_batch", "eife_batch_offsets", "eife_batch_set_phi", "eife_batch_step",
                  "eife_batch_autotune", "eife_batch_class_info"):
@@ -190,6 +191,15 @@ class Grid:
         _check(self._lib, self._lib.eife_step(self._g, ctypes.c_void_p(u.data_ptr()), int(n_steps), int(f_kind),
                                               float(t0), _stream_ptr(stream)))
         return u
+
+    def step_out(self, u_in, u_out, n_steps, f_kind, t0=0.0, stream=None):
+        """n_steps steps from u_in into u_out (eife_step_out; u_in is left as it was)."""
+        self._check_array(u_in, "u_in")
+        self._check_array(u_out, "u_out")
+        _check(self._lib, self._lib.eife_step_out(self._g, ctypes.c_void_p(u_in.data_ptr()),
+                                                  ctypes.c_void_p(u_out.data_ptr()), int(n_steps), int(f_kind),
+                                                  float(t0), _stream_ptr(stream)))
+        return u_out
 
     def step_variable(self, u, taus, f_kind, t0=0.0, stream=None):
         """Advance u in place by len(taus) steps of sizes taus[n] (eife_step_variable)."""

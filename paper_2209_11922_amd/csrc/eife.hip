@@ -622,10 +622,10 @@ template <typename T, int L>
 void col_fast_launch(int var, int mode, int pitch, int outer, int count, hipStream_t s, T* W, T* H,
                      const ColGeom& cg, const Cx<T>* tw, const Diag& dg, const ColInst<T>* ci) {
   if (ci) {
-    // batched variants: 0 / 1 the two tile widths (one tile per block), 2 the
-    // widest tiles in the persistent pipelined stage pass
-    if (var == 1)
-      col_fast_go<T, L, col_pb<T, L>(1), true>(mode, pitch, outer, count, false, s, W, H, cg, tw, dg, ci);
+    // batched variants: 0 / 1 the two tile widths (one tile per block), 2 / 3
+    // the same widths in the persistent pipelined stage pass
+    if (var == 1 || var == 3)
+      col_fast_go<T, L, col_pb<T, L>(1), true>(mode, pitch, outer, count, var == 3, s, W, H, cg, tw, dg, ci);
     else
       col_fast_go<T, L, col_pb<T, L>(0), true>(mode, pitch, outer, count, var == 2, s, W, H, cg, tw, dg, ci);
   } else {
@@ -1217,8 +1217,8 @@ int ensure_step_tables(eife_grid_s* g) {
 // (running sum in double), every factor formed with tau_n; null: uniform
 // steps of the grid's tau, t_n = t0 + n tau.
 template <typename T>
-int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipStream_t s,
-              const double* taus = nullptr) {
+int run_steps(eife_grid_s* g, const T* u, int64_t n_steps, int f_kind, double t0, hipStream_t s,
+              const double* taus = nullptr, T* u_out = nullptr) {
   T* W = static_cast<T*>(g->W);
   T* H = static_cast<T*>(g->H);
   const Diag dg_fixed = make_diag(g);
@@ -1283,8 +1283,8 @@ int run_steps(eife_grid_s* g, T* u, int64_t n_steps, int f_kind, double t0, hipS
       if (three) RET_IF(launch_col<T>(g, 1, inv_plain, W, H, dg, s));
     }
   }
-  // epilogue: u = S_x^{-1} W
-  RET_IF(launch_row<T>(g, ROW_INV_USER, W, g->pitch, u, g->n[0], nullptr, F0, s));
+  // epilogue: u = S_x^{-1} W (u_out: only the prologue reads u)
+  RET_IF(launch_row<T>(g, ROW_INV_USER, W, g->pitch, u_out, g->n[0], nullptr, F0, s));
   return EIFE_OK;
 }
 
@@ -1692,8 +1692,28 @@ int eife_step(eife_grid g, void* u, int64_t n_steps, int f_kind, double t0, void
     return fail(EIFE_EUNSUPPORTED, "the three-stage scheme runs on the FFT transforms only");
   if (n_steps == 0) return EIFE_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (g->dtype == EIFE_F32) return run_steps<float>(g, static_cast<float*>(u), n_steps, f_kind, t0, s);
-  return run_steps<double>(g, static_cast<double*>(u), n_steps, f_kind, t0, s);
+  if (g->dtype == EIFE_F32)
+    return run_steps<float>(g, static_cast<float*>(u), n_steps, f_kind, t0, s, nullptr, static_cast<float*>(u));
+  return run_steps<double>(g, static_cast<double*>(u), n_steps, f_kind, t0, s, nullptr, static_cast<double*>(u));
+}
+
+int eife_step_out(eife_grid g, const void* u_in, void* u_out, int64_t n_steps, int f_kind, double t0,
+                  void* stream) {
+  if (!u_in || !u_out) return fail(EIFE_EINVAL, "u_in or u_out is null");
+  if (n_steps < 0) return fail(EIFE_EINVAL, "n_steps must be >= 0");
+  // the checks of eife_step (grid, f_kind, t0, state), without running anything
+  RET_IF(eife_step(g, const_cast<void*>(u_in), 0, f_kind, t0, stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n_steps == 0) {
+    const size_t bytes = size_t(g->n[0]) * g->n[1] * g->n[2] * g->esz;
+    if (u_in != u_out) HIP_TRY(hipMemcpyAsync(u_out, u_in, bytes, hipMemcpyDeviceToDevice, s));
+    return EIFE_OK;
+  }
+  if (g->dtype == EIFE_F32)
+    return run_steps<float>(g, static_cast<const float*>(u_in), n_steps, f_kind, t0, s, nullptr,
+                            static_cast<float*>(u_out));
+  return run_steps<double>(g, static_cast<const double*>(u_in), n_steps, f_kind, t0, s, nullptr,
+                           static_cast<double*>(u_out));
 }
 
 int eife_step_variable(eife_grid g, void* u, const double* taus, int64_t n_steps, int f_kind, double t0,
@@ -1710,8 +1730,9 @@ int eife_step_variable(eife_grid g, void* u, const double* taus, int64_t n_steps
   RET_IF(eife_step(g, u, 0, f_kind, t0, stream));
   RET_IF(ensure_step_tables(g));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (g->dtype == EIFE_F32) return run_steps<float>(g, static_cast<float*>(u), n_steps, f_kind, t0, s, taus);
-  return run_steps<double>(g, static_cast<double*>(u), n_steps, f_kind, t0, s, taus);
+  if (g->dtype == EIFE_F32)
+    return run_steps<float>(g, static_cast<float*>(u), n_steps, f_kind, t0, s, taus, static_cast<float*>(u));
+  return run_steps<double>(g, static_cast<double*>(u), n_steps, f_kind, t0, s, taus, static_cast<double*>(u));
 }
 
 int eife_norms(eife_grid g, const void* u, const void* uref, double* out, void* stream) {
@@ -1976,25 +1997,35 @@ void tune_store(const char* path, const std::string& key, const int v[4], double
 template <typename T>
 int tune_class(eife_batch_s* b, eife_batch_s::Class& c, const char* path, hipStream_t s) {
   const std::string key = tune_key(b, c);
+  eife_grid_s* g = b->inst[c.members[0]];
+  const bool fast = g->transform == EIFE_TX_FFT && fast_len<T>(g->N[0]) && fast_len<T>(g->N[1]);
+  const int ncol = sizeof(T) == 4 ? 4 : 2;  // FP32: also the pipelined stage pass
+  // a launch shape this class can take: the specialised kernels' variants, or
+  // line pairs per block whose LDS regions fit and whose tiles divide the pitch
+  auto valid = [&](const std::array<int, 4>& cd) {
+    if (fast) return cd[0] >= 0 && cd[0] < 2 && cd[1] >= 0 && cd[1] < ncol && cd[2] == 0 && cd[3] == 0;
+    return cd[0] == 0 && cd[1] == 0 && cd[2] >= 1 && cd[3] >= 1 && cd[2] <= 64 && cd[3] <= 64 && pick_pairs(g, g->plan[0].L, cd[2]) == cd[2] &&
+           pick_pairs(g, g->plan[1].L, cd[3]) == cd[3] && lds_bytes(g, cd[2], g->plan[0].L) <= 65536 &&
+           lds_bytes(g, cd[3], g->plan[1].L) <= 65536 && g->pitch % (2 * cd[3]) == 0;
+  };
   int v[4];
-  if (tune_lookup(path, key, v)) {
+  if (tune_lookup(path, key, v) && valid({v[0], v[1], v[2], v[3]})) {
     c.var_row = v[0];
     c.var_col = v[1];
     c.prow = v[2];
     c.pcol = v[3];
     return EIFE_OK;
   }
-  eife_grid_s* g = b->inst[c.members[0]];
-  const bool fast = g->transform == EIFE_TX_FFT && fast_len<T>(g->N[0]) && fast_len<T>(g->N[1]);
   std::vector<std::array<int, 4>> cands;
   if (fast) {
-    const int ncol = sizeof(T) == 4 ? 3 : 2;  // FP32: also the pipelined stage pass
     for (int r = 0; r < 2; ++r)
       for (int cc = 0; cc < ncol; ++cc) cands.push_back({r, cc, 0, 0});
   } else {
     for (int pr : {4, 8, 16})
-      for (int pc : {4, 8, 16}) cands.push_back({0, 0, pr, pc});
+      for (int pc : {4, 8, 16})
+        if (valid({0, 0, pr, pc})) cands.push_back({0, 0, pr, pc});
   }
+  if (cands.empty()) return EIFE_OK;  // no candidate fits: keep the defaults
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -2005,10 +2036,6 @@ int tune_class(eife_batch_s* b, eife_batch_s::Class& c, const char* path, hipStr
     c.var_col = cd[1];
     c.prow = cd[2];
     c.pcol = cd[3];
-    if (!fast && (pick_pairs(g, g->plan[0].L, c.prow) != c.prow || pick_pairs(g, g->plan[1].L, c.pcol) != c.pcol ||
-                  lds_bytes(g, c.prow, g->plan[0].L) > 65536 || lds_bytes(g, c.pcol, g->plan[1].L) > 65536 ||
-                  g->pitch % (2 * c.pcol) != 0))
-      continue;  // shape does not fit this line length
     RET_IF(class_step<T>(b, c, EIFE_F_ALLEN_CAHN, 0.0, s));  // warm
     HIP_TRY(hipEventRecord(e0, s));
     for (int r = 0; r < 3; ++r) RET_IF(class_step<T>(b, c, EIFE_F_ALLEN_CAHN, 0.0, s));

@@ -636,20 +636,6 @@ __global__ void adam_update(float* __restrict__ p, const float* __restrict__ g, 
 }
 
 // ---------------------------------------------------------------------------
-// a = b = u (the two copies a corrected step starts from), 16 bytes per thread.
-__global__ void __launch_bounds__(256) copy2(const float* __restrict__ u, float* __restrict__ a,
-                                             float* __restrict__ b, int64_t n, int vec) {
-  const int64_t i = (int64_t(blockIdx.x) * 256 + threadIdx.x) * 4;
-  if (vec && i + 4 <= n) {
-    const f32x4 v = *reinterpret_cast<const f32x4*>(u + i);
-    *reinterpret_cast<f32x4*>(a + i) = v;
-    *reinterpret_cast<f32x4*>(b + i) = v;
-  } else {
-    for (int64_t k = i; k < n; ++k) a[k] = b[k] = u[k];
-  }
-}
-
-// ---------------------------------------------------------------------------
 // The whole network on one output tile of kFr x kFx nodes (inference).  The
 // input layer and the four 32 -> 32 layers write their outputs to LDS over
 // regions that shrink by one node per side and layer (halo 5, 4, 3, 2, 1 around
@@ -745,7 +731,8 @@ __device__ __forceinline__ void fused_mid(const __bf16* in, __bf16* out, const b
 
 template <int MODE>
 __global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict__ un, const float* __restrict__ uc,
-                                                        const float* __restrict__ cs, const float* __restrict__ prm,
+                                                        const double* __restrict__ cpart, int64_t npix1,
+                                                        const float* __restrict__ prm,
                                                         const __bf16* __restrict__ wf, const __bf16* __restrict__ w6b,
                                                         float s_out, float* __restrict__ out,
                                                         double* __restrict__ part, int nx, int ny) {
@@ -762,7 +749,19 @@ __global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict_
   const int x0 = int(blockIdx.x % ntx) * kFx, y0 = int(blockIdx.x / ntx) * kFr;
   const int b = blockIdx.y;
   const int64_t img = int64_t(b) * nx * ny;
-  const float rc = 1.f / cs[b];
+  // the RMS coarse change from change_partial's sums, by change_final's
+  // fixed-order tree (the same value, bit for bit; the reduction rows are free
+  // until the input region is written)
+  static_assert(kCsBlocks <= kFthreads && 3 * kFthreads * 8 <= kFbytesC, "reduction rows");
+  if (tid < kCsBlocks) red[tid] = cpart[b * kCsBlocks + tid];
+  __syncthreads();
+  for (int k = kCsBlocks / 2; k > 0; k >>= 1) {
+    if (tid < k) red[tid] += red[tid + k];
+    __syncthreads();
+  }
+  const float csb = float(sqrt(red[0] / double(npix1)) + 1e-30);
+  __syncthreads();
+  const float rc = 1.f / csb;
 
   // the first 32 -> 32 layer's weights, then the input region (halo 6)
   {
@@ -852,7 +851,7 @@ __global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict_
 #pragma unroll
   for (int t = 0; t < 9; ++t) w6[t] = *reinterpret_cast<const bf16x8*>(wst + (t * 16 + col) * C + 8 * q);
   const float b6 = prm[OFF_L6 + SZ_W6];
-  const float sc = s_out * cs[b];
+  const float sc = s_out * csb;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   constexpr int XI = kFx + 2;
   const __bf16* inq = bufA + q * (kFnA * 8);
@@ -1028,9 +1027,15 @@ struct eife_corr_s {
   double* dres = nullptr;      // device indicator sums, 2 slots x 4 doubles
   double* hres = nullptr;      // pinned host copy of them, 2 slots x 4 doubles
   double* hres_dev = nullptr;  // its device address (kernels write the indicator there), or null
-  // per-slot state of a corrected step: the copy of u_n, the coarse state, and
-  // the event after its indicator; two slots let eife_corr_run enqueue step
-  // k + 1 while the host still decides step k
+  // the fused corrected step's block sums, 2 slots x 3 x fused tiles doubles in
+  // mapped host memory (the host adds them up), or null
+  double* hpart = nullptr;
+  double* hpart_dev = nullptr;
+  bool host_sum[2] = {false, false};  // the slot's indicator is in hpart (not hres)
+  // two state buffers (eife_corr_run rotates the state through u and these;
+  // eife_corr_infer_step writes u_{n+1} to the first), and per slot the coarse
+  // state and the event after the step's indicator; two slots let
+  // eife_corr_run enqueue step k + 1 while the host still decides step k
   float* un_copy[2] = {nullptr, nullptr};
   float* uc[2] = {nullptr, nullptr};
   hipEvent_t ind_ev[2] = {nullptr, nullptr};
@@ -1059,6 +1064,7 @@ void free_corr(eife_corr_s* c) {
   hipFree(c->dpart);
   hipFree(c->dres);
   if (c->hres) hipHostFree(c->hres);
+  if (c->hpart) hipHostFree(c->hpart);
   for (int k = 0; k < 2; ++k) {
     hipFree(c->un_copy[k]);
     hipFree(c->uc[k]);
@@ -1108,9 +1114,13 @@ int64_t fused_tiles(const eife_corr_s* c) {
   return int64_t((c->nx + kFx - 1) / kFx) * ((c->ny + kFr - 1) / kFr);
 }
 
-// The RMS coarse change per image (cs).
-void change_rms(eife_corr_s* c, const float* un, const float* uc, int batch, hipStream_t s) {
+// The RMS coarse change per image: its partial sums (cpart; the fused kernel
+// adds them up itself), then cs.
+void change_partials(eife_corr_s* c, const float* un, const float* uc, int batch, hipStream_t s) {
   hipLaunchKernelGGL(change_partial, dim3(kCsBlocks, batch), dim3(256), 0, s, un, uc, c->npix1, c->cpart);
+}
+void change_rms(eife_corr_s* c, const float* un, const float* uc, int batch, hipStream_t s) {
+  change_partials(c, un, uc, batch, s);
   hipLaunchKernelGGL(change_final, dim3(batch), dim3(256), 0, s, c->cpart, c->npix1, c->cs);
 }
 
@@ -1223,6 +1233,11 @@ int eife_corr_create(int nx, int ny, int max_batch, eife_corr* out) {
     c->hres_dev = nullptr;  // not mapped: the indicator goes through a copy
     (void)hipGetLastError();
   }
+  if (hipHostMalloc(&c->hpart, size_t(6 * fused_tiles(c)) * 8, hipHostMallocMapped) != hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hpart_dev), c->hpart, 0) != hipSuccess) {
+    c->hpart_dev = nullptr;  // the block sums are reduced on the device instead
+    (void)hipGetLastError();
+  }
   if (hipMemset(c->prm, 0, N_PARAMS * 4) != hipSuccess || hipMemset(c->grad, 0, N_PARAMS * 4) != hipSuccess ||
       hipMemset(c->m, 0, N_PARAMS * 4) != hipSuccess || hipMemset(c->v, 0, N_PARAMS * 4) != hipSuccess ||
       hipMemset(c->wf, 0, N_MID * SZ_WM * 2) != hipSuccess || hipMemset(c->wb, 0, N_MID * SZ_WM * 2) != hipSuccess ||
@@ -1282,9 +1297,10 @@ int eife_corr_forward(eife_corr c, const float* un, const float* uc, float* delt
   CRET(check_batch(c, batch));
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (c->fused) {
-    change_rms(c, un, uc, batch, s);
-    hipLaunchKernelGGL((corr_fused<FUSED_INFER>), dim3(fused_tiles(c), batch), dim3(kFthreads), 0, s, un, uc, c->cs,
-                       c->prm, c->wf, c->w6b, float(c->s_out), delta, (double*)nullptr, c->nx, c->ny);
+    change_partials(c, un, uc, batch, s);
+    hipLaunchKernelGGL((corr_fused<FUSED_INFER>), dim3(fused_tiles(c), batch), dim3(kFthreads), 0, s, un, uc,
+                       c->cpart, c->npix1, c->prm, c->wf, c->w6b, float(c->s_out), delta, (double*)nullptr, c->nx,
+                       c->ny);
     CHIP(hipGetLastError());
     return EIFE_OK;
   }
@@ -1344,27 +1360,37 @@ int check_infer_args(eife_corr c, eife_grid coarse, eife_grid fine, float* u, in
 }
 
 // The device work of one corrected step up to the indicator, in state slot
-// `slot`: copies of u, the coarse step, the network, u = u_c + delta, the
-// indicator sums (into the mapped host buffer, else copied there), and the
-// slot's event.
-int enqueue_corrected(eife_corr_s* c, eife_grid coarse, float* u, double t0, int slot, hipStream_t s) {
-  const int vec = (reinterpret_cast<uintptr_t>(u) % 16) == 0;  // the library's own buffers are 256-byte aligned
-  float* un = c->un_copy[slot];
+// `slot`, from u_n in `in` to u_{n+1} in `out` (a different buffer: the
+// network reads u_n around every tile while other tiles write): the coarse
+// step from `in` into the slot's u_c, the network, out = u_c + delta, the
+// indicator sums (to the host through mapped memory, else copied there), and
+// the slot's event.
+int enqueue_corrected(eife_corr_s* c, eife_grid coarse, const float* in, float* out, double t0, int slot,
+                      hipStream_t s) {
   float* uc = c->uc[slot];
-  hipLaunchKernelGGL(copy2, dim3(grid1((c->npix1 + 3) / 4, 256)), dim3(256), 0, s, u, un, uc, c->npix1, vec);
-  const int r = eife_step(coarse, uc, 1, EIFE_F_ALLEN_CAHN, t0, s);
+  const int r = eife_step_out(coarse, in, uc, 1, EIFE_F_ALLEN_CAHN, t0, s);
   if (r != EIFE_OK) return cfail(r, "coarse step: %s", eife_last_error());
   double* ind = (c->hres_dev ? c->hres_dev : c->dres) + 4 * slot;
+  c->host_sum[slot] = false;
   if (c->fused) {
-    // network, u = u_c + delta and the indicator's block sums in one kernel
-    change_rms(c, un, uc, 1, s);
+    // network, out = u_c + delta and the indicator's block sums in one kernel;
+    // with mapped host memory the sums go straight to the host, which adds
+    // them up
+    change_partials(c, in, uc, 1, s);
     const int64_t nt = fused_tiles(c);
-    hipLaunchKernelGGL((corr_fused<FUSED_APPLY>), dim3(nt, 1), dim3(kFthreads), 0, s, un, uc, c->cs, c->prm, c->wf,
-                       c->w6b, float(c->s_out), u, c->dpart, c->nx, c->ny);
+    double* part = c->hpart_dev ? c->hpart_dev + 3 * nt * slot : c->dpart;
+    hipLaunchKernelGGL((corr_fused<FUSED_APPLY>), dim3(nt, 1), dim3(kFthreads), 0, s, in, uc, c->cpart, c->npix1,
+                       c->prm, c->wf, c->w6b, float(c->s_out), out, part, c->nx, c->ny);
+    if (c->hpart_dev) {
+      c->host_sum[slot] = true;
+      CHIP(hipGetLastError());
+      CHIP(hipEventRecord(c->ind_ev[slot], s));
+      return EIFE_OK;
+    }
     hipLaunchKernelGGL(reduce_indicator, dim3(1), dim3(256), 0, s, c->dpart, int(nt), ind);
   } else {
-    CRET(eife_corr_forward(c, un, uc, c->gout, 1, s));
-    hipLaunchKernelGGL(apply_indicator, dim3(kIndBlocks), dim3(256), 0, s, un, uc, c->gout, u, c->npix1, c->dpart);
+    CRET(eife_corr_forward(c, in, uc, c->gout, 1, s));
+    hipLaunchKernelGGL(apply_indicator, dim3(kIndBlocks), dim3(256), 0, s, in, uc, c->gout, out, c->npix1, c->dpart);
     hipLaunchKernelGGL(reduce_indicator, dim3(1), dim3(256), 0, s, c->dpart, kIndBlocks, ind);
   }
   CHIP(hipGetLastError());
@@ -1375,13 +1401,25 @@ int enqueue_corrected(eife_corr_s* c, eife_grid coarse, float* u, double t0, int
 }
 
 // Wait for the indicator of the step in `slot` and fall back if it fails:
-// u is restored from the slot's copy of u_n and advanced by the fine steps.
-// Work enqueued after that step (a speculative next step) is overwritten in
-// stream order by the restore.
-int decide_corrected(eife_corr_s* c, eife_grid fine, float* u, double t0, int slot, int64_t fine_steps,
-                     double theta, int* fell_back, double* out2, hipStream_t s) {
+// the fine steps go from u_n in `in` to `out`.  Work enqueued after that step
+// (a speculative next step reading `out`) precedes them in stream order.
+int decide_corrected(eife_corr_s* c, eife_grid fine, const float* in, float* out, double t0, int slot,
+                     int64_t fine_steps, double theta, int* fell_back, double* out2, hipStream_t s) {
   CHIP(hipEventSynchronize(c->ind_ev[slot]));
-  const double* hr = c->hres + 4 * slot;
+  double hr[3];
+  if (c->host_sum[slot]) {
+    // the fused kernel's block sums, in block order
+    const int64_t nt = fused_tiles(c);
+    const double* p = c->hpart + 3 * nt * slot;
+    hr[0] = hr[1] = hr[2] = 0.0;
+    for (int64_t r = 0; r < nt; ++r) {
+      hr[0] += p[3 * r];
+      hr[1] += p[3 * r + 1];
+      hr[2] = std::fmax(hr[2], p[3 * r + 2]);
+    }
+  } else {
+    for (int k = 0; k < 3; ++k) hr[k] = c->hres[4 * slot + k];
+  }
   const double ind = std::sqrt(hr[0]) / (std::sqrt(hr[1]) + 1e-12);
   const double umax = hr[2];
   const double crms = std::sqrt(hr[1] / double(c->npix1));
@@ -1392,8 +1430,7 @@ int decide_corrected(eife_corr_s* c, eife_grid fine, float* u, double t0, int sl
   *fell_back = 0;
   if (!(ind <= theta) || !(umax <= 1.0 + kMbpTol) || !(crms <= c->guard)) {
     *fell_back = 1;
-    CHIP(hipMemcpyAsync(u, c->un_copy[slot], size_t(c->npix1) * 4, hipMemcpyDeviceToDevice, s));
-    const int r = eife_step(fine, u, fine_steps, EIFE_F_ALLEN_CAHN, t0, s);
+    const int r = eife_step_out(fine, in, out, fine_steps, EIFE_F_ALLEN_CAHN, t0, s);
     if (r != EIFE_OK) return cfail(r, "fine steps: %s", eife_last_error());
   }
   return EIFE_OK;
@@ -1408,8 +1445,11 @@ int eife_corr_infer_step(eife_corr c, eife_grid coarse, eife_grid fine, float* u
   CRET(check_infer_args(c, coarse, fine, u, fine_steps, theta));
   if (!fell_back) return cfail(EIFE_EINVAL, "null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  CRET(enqueue_corrected(c, coarse, u, t0, 0, s));
-  return decide_corrected(c, fine, u, t0, 0, fine_steps, theta, fell_back, out2, s);
+  float* next = c->un_copy[0];
+  CRET(enqueue_corrected(c, coarse, u, next, t0, 0, s));
+  CRET(decide_corrected(c, fine, u, next, t0, 0, fine_steps, theta, fell_back, out2, s));
+  CHIP(hipMemcpyAsync(u, next, size_t(c->npix1) * 4, hipMemcpyDeviceToDevice, s));
+  return EIFE_OK;
 }
 
 int eife_corr_run(eife_corr c, eife_grid coarse, eife_grid fine, float* u, double t0, double tau_coarse,
@@ -1420,21 +1460,30 @@ int eife_corr_run(eife_corr c, eife_grid coarse, eife_grid fine, float* u, doubl
   *fallbacks = 0;
   if (n_steps == 0) return EIFE_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // Step k + 1 is enqueued (into the other state slot) before the host reads
-  // step k's indicator, assuming step k is accepted, so the GPU does not wait
-  // for the host's decision; when step k falls back, the fine steps overwrite
-  // u in stream order and step k + 1 is enqueued again from their result.
-  CRET(enqueue_corrected(c, coarse, u, t0, 0, s));
+  // The state rotates through u and the two slot buffers: step k goes from
+  // S[k mod 3] to S[(k + 1) mod 3].  Step k + 1 is enqueued (into the other
+  // slot) before the host reads step k's indicator, assuming step k is
+  // accepted, so the GPU does not wait for the host's decision; it writes
+  // S[(k + 2) mod 3], which leaves step k's u_n intact.  When step k falls
+  // back, the fine steps rewrite S[(k + 1) mod 3] in stream order and step
+  // k + 1 is enqueued again from their result.
+  float* S[3] = {u, c->un_copy[0], c->un_copy[1]};
+  CRET(enqueue_corrected(c, coarse, S[0], S[1], t0, 0, s));
   for (int64_t k = 0; k < n_steps; ++k) {
     const int slot = int(k & 1);
     const double tk = t0 + double(k) * tau_coarse;
+    float* in = S[k % 3];
+    float* out = S[(k + 1) % 3];
+    float* next = S[(k + 2) % 3];
     const bool ahead = k + 1 < n_steps;
-    if (ahead) CRET(enqueue_corrected(c, coarse, u, tk + tau_coarse, slot ^ 1, s));
+    if (ahead) CRET(enqueue_corrected(c, coarse, out, next, tk + tau_coarse, slot ^ 1, s));
     int fb = 0;
-    CRET(decide_corrected(c, fine, u, tk, slot, fine_steps, theta, &fb, nullptr, s));
-    if (fb && ahead) CRET(enqueue_corrected(c, coarse, u, tk + tau_coarse, slot ^ 1, s));
+    CRET(decide_corrected(c, fine, in, out, tk, slot, fine_steps, theta, &fb, nullptr, s));
+    if (fb && ahead) CRET(enqueue_corrected(c, coarse, out, next, tk + tau_coarse, slot ^ 1, s));
     *fallbacks += fb;
   }
+  if (S[n_steps % 3] != u)
+    CHIP(hipMemcpyAsync(u, S[n_steps % 3], size_t(c->npix1) * 4, hipMemcpyDeviceToDevice, s));
   return EIFE_OK;
 }
 

@@ -521,6 +521,29 @@ struct ColMinWaves {
   static constexpr int value = MODE >= COL_S3_1 ? 2 : MinWaves<T, L>::value;
 };
 
+// Block coordinates of a one-tile-per-block column pass.  The hardware hands
+// linear block b (x fastest, then y, then z) to XCD b mod 8; tiles narrower
+// than a 128-byte line share each line with the neighbouring tile, so for
+// those the linear index is renumbered (b mod 8) * (nb / 8) + b / 8 (a
+// bijection on the first 8 * (nb / 8) blocks) and the blocks of one XCD own
+// a contiguous run of tiles: a shared line is fetched into one L2, not two.
+template <typename T, int PB>
+__device__ __forceinline__ void tile_coords(int& bx, int& by, int& bz) {
+  bx = int(blockIdx.x);
+  by = int(blockIdx.y);
+  bz = int(blockIdx.z);
+  if constexpr (2 * PB * int(sizeof(T)) < 128) {
+    const int X = int(gridDim.x), Y = int(gridDim.y);
+    const int nb = X * Y * int(gridDim.z);
+    const int b = bx + X * (by + Y * bz);
+    const int q = nb / 8;
+    const int l = b < 8 * q ? (b % 8) * q + b / 8 : b;
+    bx = l % X;
+    by = (l / X) % Y;
+    bz = l / (X * Y);
+  }
+}
+
 template <typename T, int L, int PB, int PPW, int MODE, bool BAT>
 __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (ColMinWaves<T, L, MODE>::value)) col_fast(T* W, T* H, ColGeom g, const Cx<T>* tw,
                                                                         Diag dg, const ColInst<T>* __restrict__ insts) {
@@ -528,9 +551,11 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (ColMinWaves<T, L
   // modified copy of the Diag argument would live in private memory)
   AxisTab ta0 = dg.ax[0], ta1 = dg.ax[1], ta2 = dg.ax[2];
   double Dv = dg.D;
+  int bx, by, bz;
+  tile_coords<T, PB>(bx, by, bz);
   if constexpr (BAT) {
     if (insts) {
-      const ColInst<T>& I = insts[blockIdx.z];
+      const ColInst<T>& I = insts[bz];
       W = I.W;
       H = I.H;
       ta0 = I.ax[0];
@@ -548,8 +573,8 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (ColMinWaves<T, L
   constexpr int NT = SLOTS * LP;
   __shared__ Cx<T> lds[PB * BUF];
   const int tid = threadIdx.x;
-  const int c0 = blockIdx.x * 2 * PB;
-  const int outer = blockIdx.y;
+  const int c0 = bx * 2 * PB;
+  const int outer = by;
   const int64_t base = int64_t(outer) * g.ld_outer + c0;
   const T scale = T(1.0 / sqrt(double(L)));
   const int slot = tid / LP;
@@ -698,6 +723,22 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (ColMinWaves<T, L
 // into registers before the current tile is transformed, so the memory
 // latency hides behind the FFTs.  Tile t covers columns (t % ntx) * C ... and
 // outer index t / ntx.
+// First tile of a persistent column block (tiles t, t + gridDim.x, ...).  The
+// hardware hands block b to XCD b mod 8; tiles narrower than a 128-byte line
+// share each line with the neighbouring tile, so such blocks are renumbered
+// (b mod 8) * (nb / 8) + b / 8 (a bijection on the first 8 * (nb / 8) blocks):
+// the blocks of one XCD then own a contiguous run of tiles, and a shared line
+// is fetched into one L2 instead of two.
+template <typename T, int PB>
+__device__ __forceinline__ int first_tile() {
+  int b = int(blockIdx.x);
+  if constexpr (2 * PB * int(sizeof(T)) < 128) {
+    const int q = int(gridDim.x) / 8;
+    if (b < 8 * q) b = (b % 8) * q + b / 8;
+  }
+  return b;
+}
+
 template <typename T, int L, int PB, int PPW>
 __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::value)) col_pipe(T* __restrict__ W, ColGeom g,
                                                                         const Cx<T>* tw, int ntx, int ntiles) {
@@ -727,7 +768,7 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
     return reinterpret_cast<Cx<T>*>(W + int64_t(outer) * g.ld_outer + tx * 2 * PB + m0 * ldl + 2 * tq);
   };
   Cx<T> pre[CIT];
-  int t = blockIdx.x;
+  int t = first_tile<T, PB>();
   if (t < ntiles) {
     const Cx<T>* gp = tile_ptr(t);
 #pragma unroll
@@ -808,7 +849,7 @@ __global__ void __launch_bounds__((PB / PPW * Line<T, L>::LP), (MinWaves<T, L>::
     return int64_t(lt / ntx) * g.ld_outer + ((lt % ntx) * 2 * PB + m0 * ldl + 2 * tq);
   };
   Cx<T> pw[CIT];
-  int t = blockIdx.x;
+  int t = first_tile<T, PB>();
   if (t < ntiles) {
     const Cx<T>* gw = reinterpret_cast<const Cx<T>*>(wbase(t) + offset(t));
 #pragma unroll
@@ -1055,8 +1096,10 @@ __global__ void __launch_bounds__((PB / PPW * FftShape<L>::LP), (PerMinWaves<T, 
   constexpr int CIT = (L + MS - 1) / MS;
   __shared__ Cx<T> lds[PB * BUF];
   const int tid = threadIdx.x;
-  const int c0 = blockIdx.x * 2 * PB;
-  const int outer = blockIdx.y;
+  int bx, by, bz;
+  tile_coords<T, PB>(bx, by, bz);
+  const int c0 = bx * 2 * PB;
+  const int outer = by;
   const int64_t base = int64_t(outer) * g.ld_outer + c0;
   const T s1 = T(1.0 / sqrt(double(L)));
   const int slot = tid / LP;

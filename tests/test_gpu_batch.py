@@ -85,6 +85,53 @@ def test_batch_long_column_classes_equal_single_grids_bitwise(stages):
     b.close()
 
 
+@pytest.mark.parametrize("var_col", [0, 1, 2, 3])
+def test_every_column_variant_equals_single_grids_bitwise(tmp_path, var_col):
+    """Each column-pass variant of the specialised lengths (two tile widths, one
+    tile per block or the persistent stage pass), forced through the tuning
+    cache, gives every instance its single grid's bits."""
+    inst = [(512, 512, 4e-4), (512, 512, 2.5e-3), (384, 384, 9e-4), (256, 256, 1e-3), (128, 128, 2e-3),
+            (192, 192, 1.6e-3)]
+    u0s = _inputs(inst, 400)
+    cache = tmp_path / "tune.json"
+    b0, _ = _batch_run(inst, u0s, 0.01, 1, 2, "f32", autotune=cache)
+    b0.close()
+    rec = json.loads(cache.read_text())
+    for key, val in rec.items():
+        if val[2] == 0 and val[3] == 0:  # a class of specialised lengths
+            val[1] = var_col
+    # the library reads one entry per line
+    cache.write_text("{\n" + ",\n".join(f'  "{k}": {json.dumps(v)}' for k, v in rec.items()) + "\n}\n")
+    b, outs = _batch_run(inst, u0s, 0.01, 3, 2, "f32", autotune=cache)
+    assert all(info[4] == var_col for info in b.class_info())
+    for (nx, ny, D), u0, got in zip(inst, u0s, outs):
+        ref = _single(nx, ny, D, u0, 0.01, 3, 2, "f32")
+        assert np.array_equal(got, ref), (nx, ny, D, var_col)
+    b.close()
+
+
+def test_autotune_ignores_invalid_cache_entries(tmp_path):
+    """Cache entries naming shapes a class cannot take are ignored and the class is tuned again."""
+    inst = [(128, 128, 2e-3), (96, 96, 1e-3), (40, 40, 1e-3)]
+    u0s = _inputs(inst, 500)
+    cache = tmp_path / "tune.json"
+    b0, ref = _batch_run(inst, u0s, 0.01, 2, 2, "f32", autotune=cache)
+    b0.close()
+    rec = json.loads(cache.read_text())
+    for key, val in rec.items():
+        if val[2] == 0 and val[3] == 0:
+            val[1] = 9  # no such column variant
+        else:
+            val[2], val[3] = 1000, 3  # too many pairs for the LDS; pairs that do not divide the pitch
+    cache.write_text("{\n" + ",\n".join(f'  "{k}": {json.dumps(v)}' for k, v in rec.items()) + "\n}\n")
+    b, outs = _batch_run(inst, u0s, 0.01, 2, 2, "f32", autotune=cache)
+    for info in b.class_info():
+        assert 0 <= info[3] <= 64 and 0 <= info[4] <= 64, info
+    for a, c in zip(ref, outs):
+        assert np.array_equal(a, c)
+    b.close()
+
+
 def test_batch_matches_oracle():
     inst = _mixed_instances()
     u0s = _inputs(inst, 7)

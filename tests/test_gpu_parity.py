@@ -413,3 +413,32 @@ def test_repeated_runs_are_bitwise_identical(dtype):
             outs.append(u)
         assert torch.equal(outs[0], outs[1]) and torch.equal(outs[1], outs[2]), N
         g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_step_out_equals_in_place_step(dtype):
+    """eife_step_out gives eife_step's result bit for bit in the output buffer and leaves
+    the input as it was; zero steps copy; input and output may be the same buffer."""
+    eife = _lib()
+    for N, bc in (([64, 48], eife.BC_DIRICHLET), ([512, 512], eife.BC_DIRICHLET), ([24, 16, 64], eife.BC_DIRICHLET),
+                  ([32, 64], eife.BC_PERIODIC)):
+        h = [1.0 / n for n in N]
+        g = eife.Grid(N, h, 1e-3, dtype, bc=bc)
+        g.set_phi(0.01, 2)
+        shape = [n + 1 for n in N] if bc == eife.BC_PERIODIC else N  # periodic: N nodes per axis
+        u0 = torch.tensor(seeded_inputs.uniform_field(78, shape), dtype=g.torch_dtype, device="cuda")
+        ref = u0.clone()
+        g.step(ref, 3, eife.F_ALLEN_CAHN, 0.25)
+        src = u0.clone()
+        dst = torch.full_like(u0, float("nan"))
+        g.step_out(src, dst, 3, eife.F_ALLEN_CAHN, 0.25)
+        same = u0.clone()
+        g.step_out(same, same, 3, eife.F_ALLEN_CAHN, 0.25)
+        zero = torch.zeros_like(u0)
+        g.step_out(src, zero, 0, eife.F_ALLEN_CAHN)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, ref) and torch.equal(same, ref), (N, bc)
+        assert torch.equal(src, u0) and torch.equal(zero, u0), (N, bc)
+        with pytest.raises(eife.EIFEError):
+            g.step_out(src, dst, -1, eife.F_ALLEN_CAHN)
+        g.close()
