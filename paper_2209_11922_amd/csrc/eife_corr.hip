@@ -643,23 +643,24 @@ __global__ void adam_update(float* __restrict__ p, const float* __restrict__ g, 
 // is that of conv_in_fwd and conv_patch (the same fragments, tap order and
 // roundings), so the result equals the layer-by-layer path bit for bit; nodes
 // outside the grid hold zeros, the zero padding of the next layer.
-// LDS (158 KB, one block per CU): activation buffers A (halo 5 region) and B
+// One 16-wave block per CU (4 waves per SIMD; 156 KB of LDS): activation
+// buffers A (halo 5 region) and B
 // (halo 4 region), each as four planes of 16 bytes per node (plane k holds
 // channels 8k .. 8k+7), so that 16 consecutive nodes of one plane are 256
 // contiguous bytes and a tap is a constant offset; the input region (u_c,
-// (u_c - u_n) / c_b), later the block's reduction rows; the current layer's
-// BF16 weights.
+// (u_c - u_n) / c_b), before it the RMS change's reduction rows and after it
+// the waves' indicator sums; the current layer's BF16 weights.
 //   FUSED_INFER  out = delta
 //   FUSED_APPLY  out = u_c + delta, block sums of delta^2, (u_c - u_n)^2 and
 //                max |out| in part[3 block ..] (block = tile + tiles * image)
 enum { FUSED_INFER = 0, FUSED_APPLY = 1 };
 constexpr int kFr = 16, kFx = 32;  // output tile: rows x nodes
-constexpr int kFthreads = 512;
+constexpr int kFthreads = 1024;
 constexpr int kFwaves = kFthreads / 64;
 constexpr int fused_nodes(int h) { return (kFr + 2 * h) * (kFx + 2 * h); }
 constexpr int kFnA = fused_nodes(5), kFnB = fused_nodes(4), kFnC = fused_nodes(6);
 constexpr int kFbytesA = kFnA * 64, kFbytesB = kFnB * 64;
-constexpr int kFbytesC = kFnC * 8 > 3 * kFthreads * 8 ? kFnC * 8 : 3 * kFthreads * 8;  // input region / reduction
+constexpr int kFbytesC = kFnC * 8 > kCsBlocks * 8 ? kFnC * 8 : kCsBlocks * 8;  // input region / reductions
 constexpr int kFbytesW = SZ_WM * 2;  // one 32 -> 32 layer, BF16
 constexpr int kFbytes = kFbytesA + kFbytesB + kFbytesC + kFbytesW;
 static_assert(kFbytes <= 160 * 1024, "fused network tile exceeds the LDS");
@@ -667,8 +668,14 @@ static_assert(kFbytesA % 16 == 0 && kFbytesB % 16 == 0 && kFbytesC % 16 == 0, "L
 
 // The next layer's weights in flight: loaded into registers before a layer's
 // products and written to LDS after them, so the load latency hides behind the
-// layer.
+// layer.  In LDS the 16-byte chunks are in fragment order: chunk i of the
+// [rows][32] layout (row r = i / 4 = tap x output channel, input channels
+// 8 (i mod 4) ...) goes to (r / 16) * 64 + (i mod 4) * 16 + r mod 16, so the
+// 64 lanes of a wave read one fragment (rows 16 b .. 16 b + 15, lane =
+// 16 q + row) as 1 KB of consecutive bytes instead of 16-byte pieces 64 bytes
+// apart (a 4-way LDS bank conflict).
 constexpr int kFwChunks = (kFbytesW / 16 + kFthreads - 1) / kFthreads;
+__device__ __forceinline__ int frag_chunk(int i) { return (i >> 6) * 64 + (i & 3) * 16 + ((i >> 2) & 15); }
 struct FusedW {
   bf16x8 v[kFwChunks];
   __device__ __forceinline__ void load(const __bf16* __restrict__ src, int bytes, int tid) {
@@ -682,7 +689,7 @@ struct FusedW {
 #pragma unroll
     for (int k = 0; k < kFwChunks; ++k) {
       const int i = tid + kFthreads * k;
-      if (i < bytes / 16) reinterpret_cast<bf16x8*>(dst)[i] = v[k];
+      if (i < bytes / 16) reinterpret_cast<bf16x8*>(dst)[frag_chunk(i)] = v[k];
     }
   }
 };
@@ -752,7 +759,7 @@ __global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict_
   // the RMS coarse change from change_partial's sums, by change_final's
   // fixed-order tree (the same value, bit for bit; the reduction rows are free
   // until the input region is written)
-  static_assert(kCsBlocks <= kFthreads && 3 * kFthreads * 8 <= kFbytesC, "reduction rows");
+  static_assert(kCsBlocks <= kFthreads && kCsBlocks * 8 <= kFbytesC && 3 * kFwaves * 8 <= kFbytesC, "reduction rows");
   if (tid < kCsBlocks) red[tid] = cpart[b * kCsBlocks + tid];
   __syncthreads();
   for (int k = kCsBlocks / 2; k > 0; k >>= 1) {
@@ -828,7 +835,7 @@ __global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict_
     for (int t = 0; t < 9; ++t)
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
-        wa[t][mt] = *reinterpret_cast<const bf16x8*>(wst + (t * 32 + mt * 16 + col) * C + 8 * q);
+        wa[t][mt] = *reinterpret_cast<const bf16x8*>(wst + ((t * 2 + mt) * 64 + lane) * 8);
     float bv[2][4];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
@@ -849,7 +856,7 @@ __global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict_
   // output layer (as conv_patch's output modes) from A over the tile
   bf16x8 w6[9];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) w6[t] = *reinterpret_cast<const bf16x8*>(wst + (t * 16 + col) * C + 8 * q);
+  for (int t = 0; t < 9; ++t) w6[t] = *reinterpret_cast<const bf16x8*>(wst + (t * 64 + lane) * 8);
   const float b6 = prm[OFF_L6 + SZ_W6];
   const float sc = s_out * csb;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -889,23 +896,30 @@ __global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict_
     }
   }
   if (MODE == FUSED_APPLY) {
-    red[tid] = s0;
-    red[kFthreads + tid] = s1;
-    red[2 * kFthreads + tid] = s2;
-    __syncthreads();
-    for (int k = kFthreads / 2; k > 0; k >>= 1) {
-      if (tid < k) {
-        red[tid] += red[tid + k];
-        red[kFthreads + tid] += red[kFthreads + tid + k];
-        red[2 * kFthreads + tid] = fmax(red[2 * kFthreads + tid], red[2 * kFthreads + tid + k]);
-      }
-      __syncthreads();
+    // the wave's sums by a fixed butterfly, then the waves' in wave order
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_xor(s0, o);
+      s1 += __shfl_xor(s1, o);
+      s2 = fmax(s2, __shfl_xor(s2, o));
     }
+    if (lane == 0) {
+      red[wave] = s0;
+      red[kFwaves + wave] = s1;
+      red[2 * kFwaves + wave] = s2;
+    }
+    __syncthreads();
     if (tid == 0) {
+      double a = 0.0, c = 0.0, m = 0.0;
+      for (int w = 0; w < kFwaves; ++w) {
+        a += red[w];
+        c += red[kFwaves + w];
+        m = fmax(m, red[2 * kFwaves + w]);
+      }
       const int64_t row = int64_t(b) * gridDim.x + blockIdx.x;
-      part[3 * row] = red[0];
-      part[3 * row + 1] = red[kFthreads];
-      part[3 * row + 2] = red[2 * kFthreads];
+      part[3 * row] = a;
+      part[3 * row + 1] = c;
+      part[3 * row + 2] = m;
     }
   }
 }
