@@ -30,6 +30,13 @@
 #include "eife_kernels.hpp"
 #include "eife_fast.hpp"
 #include "eife_gemm.hpp"
+
+// Kernel arguments are passed by value; every pass's argument block (the
+// geometry, forcing and diagonal structs plus at most eight pointers and ints)
+// stays far below the 4 KB kernel-argument segment.
+static_assert(sizeof(eife::RowGeom) + sizeof(eife::Forcing) + 8 * sizeof(void*) <= 1024, "row pass arguments");
+static_assert(sizeof(eife::ColGeom) + sizeof(eife::Diag) + 8 * sizeof(void*) <= 1024, "column pass arguments");
+static_assert(sizeof(eife::NormGeom) + 8 * sizeof(void*) <= 1024, "norm pass arguments");
 #include "eife_long.hpp"
 
 using namespace eife;
