@@ -46,7 +46,7 @@ enum eife_status {
   EIFE_OK = 0,
   EIFE_EINVAL = -1,       /* bad argument */
   EIFE_ENOMEM = -2,       /* device allocation failed */
-  EIFE_EUNSUPPORTED = -3, /* valid request this build does not implement */
+  EIFE_EUNSUPPORTED = -3, /* valid request the library does not implement */
   EIFE_ESTATE = -4,       /* call out of order (e.g. step before set_phi) */
   EIFE_EHIP = -5,         /* HIP runtime error */
   EIFE_ENONFINITE = -6    /* a reduction produced a non-finite value */

@@ -5,7 +5,7 @@ calls and moves tensors).
 Setting: 2D Allen-Cahn u_t = eps^2 Lap u + u - u^3 on (0,1)^2, Q1 grid of
 N x N intervals, homogeneous Dirichlet data, u0 i.i.d. uniform[-0.9, 0.9]
 from a seed.  The coarse step is one EIFE2 step (eq. (2.14)) of tau_c; the
-judge and the fallback are `ratio` EIFE2 steps of tau_f = tau_c / ratio.
+reference and the fallback are `ratio` EIFE2 steps of tau_f = tau_c / ratio.
 A training pair is (u_n, u_c, u_f): a state of a fine trajectory at
 t_n = n tau_c, the coarse step from it, and the fine trajectory ratio steps
 later.

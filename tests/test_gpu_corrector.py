@@ -461,7 +461,7 @@ def test_native_run_equals_single_steps():
 
 def test_trained_corrector_gain_over_plain_coarse_steps():
     """The committed network (2D Allen-Cahn 511^2, eps 0.02) on an unseen seed:
-    corrected tau = 0.016 steps against plain tau = 0.016 steps, both judged by
+    corrected tau = 0.016 steps against plain tau = 0.016 steps, both measured against
     8 fine steps of tau = 0.002 per interval (after the guard's transient)."""
     import os
     from paper_2209_11922_amd import corrector as cor
