@@ -363,9 +363,9 @@ int eife_version(void);
 #define EIFE_CORR_PARAMS 37889
 typedef struct eife_corr_s* eife_corr;
 
-/* Workspace for images of nx * ny nodes and batches up to max_batch
- * (activations: 7 arrays of max_batch * nx * ny * 64 bytes).  Parameters
- * start at zero.  Errors: EIFE_EINVAL, EIFE_ENOMEM, EIFE_EHIP. */
+/* Workspace for images of nx * ny nodes (ny <= 2048) and batches up to
+ * max_batch (activations: 7 arrays of max_batch * nx * ny * 64 bytes).
+ * Parameters start at zero.  Errors: EIFE_EINVAL, EIFE_ENOMEM, EIFE_EHIP. */
 int eife_corr_create(int nx, int ny, int max_batch, eife_corr* out);
 int eife_corr_destroy(eife_corr c);
 

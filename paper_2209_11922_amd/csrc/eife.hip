@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "../../include/eife.h"
+#include "eife_internal.h"
 #include "eife_kernels.hpp"
 #include "eife_fast.hpp"
 #include "eife_gemm.hpp"
@@ -509,6 +510,10 @@ void row_fast_go(int mode, int nrows, int count, hipStream_t s, const T* src, T*
   } else if (mode == ROW_FWD_USER) {
     hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_FWD_USER, fast::RK_GENERIC, BAT>), grid, dim3(NT), 0, s, src,
                        dst, dst2, rg, tw, F, ri);
+  } else if (mode == ROW_INV_CHG) {
+    if constexpr (fast::Line<T, L>::LP == 64 && !BAT)
+      hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_INV_CHG, fast::RK_GENERIC, BAT>), grid, dim3(NT), 0, s, src,
+                         dst, dst2, rg, tw, F, ri);
   } else {
     hipLaunchKernelGGL((fast::row_fast<T, L, PB, ROW_INV_USER, fast::RK_GENERIC, BAT>), grid, dim3(NT), 0, s, src,
                        dst, dst2, rg, tw, F, ri);
@@ -1066,6 +1071,14 @@ bool fused_first_row(const eife_grid_s* g, int f_kind) {
   return g->transform == EIFE_TX_FFT && !g->per[0] && fast_len<T>(g->N[0]) && f_kind != EIFE_F_TRAVELING_WAVE;
 }
 
+// The last row pass of a step can also sum (u - u_n)^2 per line pair
+// (ROW_INV_CHG) on 2D grids whose rows run on the specialised kernels with one
+// wavefront per line pair (N_x = 256 or 512).
+template <typename T>
+bool change_epilogue(const eife_grid_s* g) {
+  return g->d == 2 && g->transform == EIFE_TX_FFT && !g->per[0] && (g->N[0] == 256 || g->N[0] == 512);
+}
+
 // A launch of one pass over `count` instances shaped like grid `g`.
 struct Batchlet {
   int count = 1;
@@ -1077,8 +1090,11 @@ struct Batchlet {
 
 template <typename T>
 int launch_row(eife_grid_s* g, int mode, const T* src, int64_t ld_src, T* dst, int64_t ld_dst, T* dst2,
-               const Forcing& F, hipStream_t s, const Batchlet& B = Batchlet()) {
+               const Forcing& F, hipStream_t s, const Batchlet& B = Batchlet(), double* chg = nullptr) {
+  if (mode == ROW_INV_CHG && (!chg || !change_epilogue<T>(g)))
+    return fail(EIFE_EUNSUPPORTED, "row pass with change sums on this grid");
   RowGeom rg;
+  rg.chg = chg;
   rg.n = g->n[0];
   rg.nrows = g->nlines_total();
   rg.ny = g->n[1];
@@ -1225,7 +1241,7 @@ int ensure_step_tables(eife_grid_s* g) {
 // steps of the grid's tau, t_n = t0 + n tau.
 template <typename T>
 int run_steps(eife_grid_s* g, const T* u, int64_t n_steps, int f_kind, double t0, hipStream_t s,
-              const double* taus = nullptr, T* u_out = nullptr) {
+              const double* taus = nullptr, T* u_out = nullptr, double* chg = nullptr) {
   T* W = static_cast<T*>(g->W);
   T* H = static_cast<T*>(g->H);
   const Diag dg_fixed = make_diag(g);
@@ -1291,7 +1307,10 @@ int run_steps(eife_grid_s* g, const T* u, int64_t n_steps, int f_kind, double t0
     }
   }
   // epilogue: u = S_x^{-1} W (u_out: only the prologue reads u)
-  RET_IF(launch_row<T>(g, ROW_INV_USER, W, g->pitch, u_out, g->n[0], nullptr, F0, s));
+  if (chg)  // u is read again here: the sums of (u_out - u)^2 per line pair
+    RET_IF(launch_row<T>(g, ROW_INV_CHG, W, g->pitch, u_out, g->n[0], const_cast<T*>(u), F0, s, Batchlet(), chg));
+  else
+    RET_IF(launch_row<T>(g, ROW_INV_USER, W, g->pitch, u_out, g->n[0], nullptr, F0, s));
   return EIFE_OK;
 }
 
@@ -1721,6 +1740,20 @@ int eife_step_out(eife_grid g, const void* u_in, void* u_out, int64_t n_steps, i
                             static_cast<float*>(u_out));
   return run_steps<double>(g, static_cast<const double*>(u_in), n_steps, f_kind, t0, s, nullptr,
                            static_cast<double*>(u_out));
+}
+
+int eife_step_out_change(eife_grid g, const float* u_in, float* u_out, int64_t n_steps, int f_kind, double t0,
+                         double* chg, int* done, void* stream) {
+  if (!done) return fail(EIFE_EINVAL, "done is null");
+  *done = 0;
+  if (!u_in || !u_out || n_steps < 0) return fail(EIFE_EINVAL, "null u_in / u_out or negative n_steps");
+  RET_IF(eife_step(g, const_cast<float*>(u_in), 0, f_kind, t0, stream));  // the checks of eife_step, nothing run
+  if (n_steps < 1 || !chg || u_in == u_out || g->dtype != EIFE_F32 || !change_epilogue<float>(g))
+    return eife_step_out(g, u_in, u_out, n_steps, f_kind, t0, stream);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RET_IF(run_steps<float>(g, u_in, n_steps, f_kind, t0, s, nullptr, u_out, chg));
+  *done = 1;
+  return EIFE_OK;
 }
 
 int eife_step_variable(eife_grid g, void* u, const double* taus, int64_t n_steps, int f_kind, double t0,

@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "../../include/eife.h"
+#include "eife_internal.h"
 
 namespace {
 
@@ -68,43 +69,63 @@ __device__ __forceinline__ uint32_t relu_bf16x2(float a, float b) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-image RMS coarse change c_b = sqrt(mean((u_c - u_n)^2)) + 1e-30: block
-// partial sums (grid kCsBlocks x batch) in double, then one fixed-order sum per
-// image.  (A single launch whose last block adds the partials needs a
-// device-scope release per block, an L2 write-back on this chip: slower.)
-constexpr int kCsBlocks = 256;  // equals the block size of change_final
+// Per-image RMS coarse change c_b = sqrt(mean((u_c - u_n)^2)) + 1e-30: one
+// double partial sum per pair of grid rows (rows 2p, 2p + 1), then a
+// fixed-order tree over the partials (zero-padded to kCsMax).  The partial of
+// a pair is formed exactly as the coarse step's last row pass forms it when it
+// writes them itself (eife_step_out_change): lane l adds its columns l, l + 64,
+// ... in order, row 2p before row 2p + 1, with fused multiply-adds, then a
+// butterfly over the 64 lanes; so every path gets the same c_b bit for bit.
+// (A single launch whose last block adds the partials needs a device-scope
+// release per block, an L2 write-back on this chip: slower.)
+constexpr int kCsMax = 1024;  // partials per image (rows up to 2 kCsMax); the block size of change_final
+
+__host__ __device__ constexpr int change_pairs(int ny) { return (ny + 1) / 2; }
 
 __global__ void __launch_bounds__(256) change_partial(const float* __restrict__ un, const float* __restrict__ uc,
-                                                      int64_t npix1, double* __restrict__ part) {
-  __shared__ double red[256];
+                                                      int nx, int ny, double* __restrict__ part) {
   const int b = blockIdx.y;
-  const float* a = un + int64_t(b) * npix1;
-  const float* c = uc + int64_t(b) * npix1;
+  const int lane = threadIdx.x & 63;
+  const int pair = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pair >= change_pairs(ny)) return;
+  const int64_t img = int64_t(b) * nx * ny;
+  const int ra = 2 * pair, rb = ra + 1;
+  const bool hasb = rb < ny;
+  const float* ca = uc + img + int64_t(ra) * nx;
+  const float* na = un + img + int64_t(ra) * nx;
   double s = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < npix1; i += int64_t(gridDim.x) * 256) {
-    const double d = double(c[i]) - double(a[i]);
-    s += d * d;
+  for (int col = lane; col < nx; col += 64) {
+    const double da = double(ca[col]) - double(na[col]);
+    s = fma(da, da, s);
+    if (hasb) {
+      const double db = double(ca[nx + col]) - double(na[nx + col]);
+      s = fma(db, db, s);
+    }
   }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[b * kCsBlocks + blockIdx.x] = red[0];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) part[int64_t(b) * kCsMax + pair] = s;
 }
 
-__global__ void __launch_bounds__(256) change_final(const double* __restrict__ part, int64_t npix1,
-                                                    float* __restrict__ cs) {
-  __shared__ double red[256];
-  const int b = blockIdx.x;
-  red[threadIdx.x] = part[b * kCsBlocks + threadIdx.x];
+// The fixed-order sum of an image's partials (all kCsMax threads of a block;
+// red holds kCsMax doubles) and c_b from it.
+__device__ __forceinline__ float change_rms_tree(const double* __restrict__ part, int b, int npairs,
+                                                 int64_t npix1, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = tid < npairs ? part[int64_t(b) * kCsMax + tid] : 0.0;
   __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+  for (int k = kCsMax / 2; k > 0; k >>= 1) {
+    if (tid < k) red[tid] += red[tid + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) cs[b] = float(sqrt(red[0] / double(npix1)) + 1e-30);
+  return float(sqrt(red[0] / double(npix1)) + 1e-30);
+}
+
+__global__ void __launch_bounds__(kCsMax) change_final(const double* __restrict__ part, int npairs, int64_t npix1,
+                                                       float* __restrict__ cs) {
+  __shared__ double red[kCsMax];
+  const float v = change_rms_tree(part, blockIdx.x, npairs, npix1, red);
+  if (threadIdx.x == 0) cs[blockIdx.x] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -660,7 +681,7 @@ constexpr int kFwaves = kFthreads / 64;
 constexpr int fused_nodes(int h) { return (kFr + 2 * h) * (kFx + 2 * h); }
 constexpr int kFnA = fused_nodes(5), kFnB = fused_nodes(4), kFnC = fused_nodes(6);
 constexpr int kFbytesA = kFnA * 64, kFbytesB = kFnB * 64;
-constexpr int kFbytesC = kFnC * 8 > kCsBlocks * 8 ? kFnC * 8 : kCsBlocks * 8;  // input region / reductions
+constexpr int kFbytesC = kFnC * 8 > kCsMax * 8 ? kFnC * 8 : kCsMax * 8;  // input region / reductions
 constexpr int kFbytesW = SZ_WM * 2;  // one 32 -> 32 layer, BF16
 constexpr int kFbytes = kFbytesA + kFbytesB + kFbytesC + kFbytesW;
 static_assert(kFbytes <= 160 * 1024, "fused network tile exceeds the LDS");
@@ -759,14 +780,8 @@ __global__ void __launch_bounds__(kFthreads) corr_fused(const float* __restrict_
   // the RMS coarse change from change_partial's sums, by change_final's
   // fixed-order tree (the same value, bit for bit; the reduction rows are free
   // until the input region is written)
-  static_assert(kCsBlocks <= kFthreads && kCsBlocks * 8 <= kFbytesC && 3 * kFwaves * 8 <= kFbytesC, "reduction rows");
-  if (tid < kCsBlocks) red[tid] = cpart[b * kCsBlocks + tid];
-  __syncthreads();
-  for (int k = kCsBlocks / 2; k > 0; k >>= 1) {
-    if (tid < k) red[tid] += red[tid + k];
-    __syncthreads();
-  }
-  const float csb = float(sqrt(red[0] / double(npix1)) + 1e-30);
+  static_assert(kCsMax == kFthreads && kCsMax * 8 <= kFbytesC && 3 * kFwaves * 8 <= kFbytesC, "reduction rows");
+  const float csb = change_rms_tree(cpart, b, change_pairs(ny), npix1, red);
   __syncthreads();
   const float rc = 1.f / csb;
 
@@ -1054,7 +1069,7 @@ struct eife_corr_s {
   float* uc[2] = {nullptr, nullptr};
   hipEvent_t ind_ev[2] = {nullptr, nullptr};
   float* cs = nullptr;      // per-image RMS coarse change [max_batch]
-  double* cpart = nullptr;  // its partial sums [max_batch][kCsBlocks]
+  double* cpart = nullptr;  // its partial sums [max_batch][kCsMax]
   double guard = INFINITY;  // fall back when the RMS coarse change exceeds this
   int fused = 1;            // inference through corr_fused (else one kernel per layer)
 };
@@ -1131,11 +1146,12 @@ int64_t fused_tiles(const eife_corr_s* c) {
 // The RMS coarse change per image: its partial sums (cpart; the fused kernel
 // adds them up itself), then cs.
 void change_partials(eife_corr_s* c, const float* un, const float* uc, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(change_partial, dim3(kCsBlocks, batch), dim3(256), 0, s, un, uc, c->npix1, c->cpart);
+  hipLaunchKernelGGL(change_partial, dim3((change_pairs(c->ny) + 3) / 4, batch), dim3(256), 0, s, un, uc, c->nx, c->ny,
+                     c->cpart);
 }
 void change_rms(eife_corr_s* c, const float* un, const float* uc, int batch, hipStream_t s) {
   change_partials(c, un, uc, batch, s);
-  hipLaunchKernelGGL(change_final, dim3(batch), dim3(256), 0, s, c->cpart, c->npix1, c->cs);
+  hipLaunchKernelGGL(change_final, dim3(batch), dim3(kCsMax), 0, s, c->cpart, change_pairs(c->ny), c->npix1, c->cs);
 }
 
 int check_batch(const eife_corr_s* c, int batch) {
@@ -1214,6 +1230,7 @@ int eife_corr_create(int nx, int ny, int max_batch, eife_corr* out) {
   if (!out) return cfail(EIFE_EINVAL, "out is null");
   *out = nullptr;
   if (nx < 1 || ny < 1 || max_batch < 1) return cfail(EIFE_EINVAL, "nx, ny and max_batch must be >= 1");
+  if (change_pairs(ny) > kCsMax) return cfail(EIFE_EINVAL, "ny = %d exceeds %d", ny, 2 * kCsMax);
   if (int64_t(nx) * ny * max_batch > (int64_t(1) << 31) / C)
     return cfail(EIFE_EINVAL, "nx * ny * max_batch too large");
   auto* c = new eife_corr_s;
@@ -1234,7 +1251,7 @@ int eife_corr_create(int nx, int ny, int max_batch, eife_corr* out) {
             hipMalloc(&c->dres, 8 * 8) == hipSuccess &&
             hipHostMalloc(&c->hres, 8 * 8, hipHostMallocMapped) == hipSuccess &&
             hipMalloc(&c->cs, size_t(max_batch) * 4) == hipSuccess &&
-            hipMalloc(&c->cpart, size_t(max_batch) * kCsBlocks * 8) == hipSuccess;
+            hipMalloc(&c->cpart, size_t(max_batch) * kCsMax * 8) == hipSuccess;
   for (int l = 1; ok && l <= 5; ++l) ok = hipMalloc(&c->act[l], npix * C * 2) == hipSuccess;
   for (int k = 0; ok && k < 2; ++k)
     ok = hipMalloc(&c->un_copy[k], c->npix1 * 4) == hipSuccess && hipMalloc(&c->uc[k], c->npix1 * 4) == hipSuccess &&
@@ -1382,7 +1399,10 @@ int check_infer_args(eife_corr c, eife_grid coarse, eife_grid fine, float* u, in
 int enqueue_corrected(eife_corr_s* c, eife_grid coarse, const float* in, float* out, double t0, int slot,
                       hipStream_t s) {
   float* uc = c->uc[slot];
-  const int r = eife_step_out(coarse, in, uc, 1, EIFE_F_ALLEN_CAHN, t0, s);
+  // the coarse step; its last row pass also writes the block sums of the
+  // coarse change where the grid's shape allows (else change_partial)
+  int have_chg = 0;
+  const int r = eife_step_out_change(coarse, in, uc, 1, EIFE_F_ALLEN_CAHN, t0, c->cpart, &have_chg, s);
   if (r != EIFE_OK) return cfail(r, "coarse step: %s", eife_last_error());
   double* ind = (c->hres_dev ? c->hres_dev : c->dres) + 4 * slot;
   c->host_sum[slot] = false;
@@ -1390,7 +1410,7 @@ int enqueue_corrected(eife_corr_s* c, eife_grid coarse, const float* in, float* 
     // network, out = u_c + delta and the indicator's block sums in one kernel;
     // with mapped host memory the sums go straight to the host, which adds
     // them up
-    change_partials(c, in, uc, 1, s);
+    if (!have_chg) change_partials(c, in, uc, 1, s);
     const int64_t nt = fused_tiles(c);
     double* part = c->hpart_dev ? c->hpart_dev + 3 * nt * slot : c->dpart;
     hipLaunchKernelGGL((corr_fused<FUSED_APPLY>), dim3(nt, 1), dim3(kFthreads), 0, s, in, uc, c->cpart, c->npix1,

@@ -476,6 +476,30 @@ __global__ void __launch_bounds__((PB * Line<T, L>::LP), (MinWaves<T, L>::value)
   Cx<T> outv[RIT];
 #pragma unroll
   for (int t = 0; t < RIT; ++t) outv[t] = my[lane + LP * t];  // full b64 reads (slot n..N-1 is scratch)
+  if constexpr (MODE == ROW_INV_CHG) {
+    // the pair's sum of (u - u_n)^2: lane l takes its columns l, l + 64, ...
+    // in order (row a, then row b), then a fixed butterfly over the lanes
+    static_assert(LP == 64 && !BAT, "one wavefront per line pair");
+    const T* ua = dst2 + int64_t(ra) * g.ld_dst + lane;
+    const T* ub = dst2 + int64_t(rb) * g.ld_dst + lane;
+    double sc = 0.0;
+#pragma unroll
+    for (int t = 0; t < RIT; ++t) {
+      if (lane + LP * t < n) {
+        if (hasa) {
+          const double d = double(outv[t].re) - double(ua[LP * t]);
+          sc = fma(d, d, sc);
+        }
+        if (hasb) {
+          const double d = double(outv[t].im) - double(ub[LP * t]);
+          sc = fma(d, d, sc);
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sc += __shfl_xor(sc, o);
+    if (lane == 0 && hasa) g.chg[ra >> 1] = sc;
+  }
 #pragma unroll
   for (int t = 0; t < RIT; ++t) {
     if (lane + LP * t < n) {

@@ -567,7 +567,10 @@ __device__ __forceinline__ T reaction(const Forcing& F, T u, int ix, int iy, int
 // rows (r0 + 2p, r0 + 2p + 1).
 // ROW_FWD_PHYS (specialised kernels only): from the nodal values u, dst2 =
 // S_x u and dst = S_x f(u) in one pass (the first reaction of a run).
-enum RowMode { ROW_PHYS = 0, ROW_FWD_USER = 1, ROW_INV_USER = 2, ROW_FWD_PHYS = 3 };
+// ROW_INV_CHG: ROW_INV_USER that also sums (u - u_n)^2 over each line pair
+// (u_n in dst2, the user layout) into chg[pair] (specialised rows of one
+// wavefront per pair only).
+enum RowMode { ROW_PHYS = 0, ROW_FWD_USER = 1, ROW_INV_USER = 2, ROW_FWD_PHYS = 3, ROW_INV_CHG = 4 };
 
 struct RowGeom {
   int n;         // line length (interior nodes along x)
@@ -577,6 +580,7 @@ struct RowGeom {
   FftPlan pl;
   int P;         // pairs per block
   int ls;        // LDS line stride (complex elements)
+  double* chg = nullptr;  // ROW_INV_CHG: per line pair sums of (u - u_n)^2
 };
 
 template <typename T>
