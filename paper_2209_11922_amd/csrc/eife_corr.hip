@@ -1249,13 +1249,15 @@ int eife_corr_create(int nx, int ny, int max_batch, eife_corr* out) {
             hipMalloc(&c->dpart, size_t(std::max<int64_t>({grid1(npix, 256), 3 * fused_tiles(c), 4096})) * 8) ==
                 hipSuccess &&
             hipMalloc(&c->dres, 8 * 8) == hipSuccess &&
-            hipHostMalloc(&c->hres, 8 * 8, hipHostMallocMapped) == hipSuccess &&
+            hipHostMalloc(&c->hres, 8 * 8, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
             hipMalloc(&c->cs, size_t(max_batch) * 4) == hipSuccess &&
             hipMalloc(&c->cpart, size_t(max_batch) * kCsMax * 8) == hipSuccess;
   for (int l = 1; ok && l <= 5; ++l) ok = hipMalloc(&c->act[l], npix * C * 2) == hipSuccess;
   for (int k = 0; ok && k < 2; ++k)
     ok = hipMalloc(&c->un_copy[k], c->npix1 * 4) == hipSuccess && hipMalloc(&c->uc[k], c->npix1 * 4) == hipSuccess &&
-         hipEventCreateWithFlags(&c->ind_ev[k], hipEventDisableTiming) == hipSuccess;
+         // the indicator sums reach the host through coherent (uncached) host
+         // memory, so the event needs no system-scope cache write-back
+         hipEventCreateWithFlags(&c->ind_ev[k], hipEventDisableTiming | hipEventDisableSystemFence) == hipSuccess;
   if (!ok) {
     free_corr(c);
     return cfail(EIFE_ENOMEM, "corrector buffers allocation failed");
@@ -1264,7 +1266,7 @@ int eife_corr_create(int nx, int ny, int max_batch, eife_corr* out) {
     c->hres_dev = nullptr;  // not mapped: the indicator goes through a copy
     (void)hipGetLastError();
   }
-  if (hipHostMalloc(&c->hpart, size_t(6 * fused_tiles(c)) * 8, hipHostMallocMapped) != hipSuccess ||
+  if (hipHostMalloc(&c->hpart, size_t(6 * fused_tiles(c)) * 8, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer(reinterpret_cast<void**>(&c->hpart_dev), c->hpart, 0) != hipSuccess) {
     c->hpart_dev = nullptr;  // the block sums are reduced on the device instead
     (void)hipGetLastError();
