@@ -105,28 +105,42 @@ struct MinWaves {
   static constexpr int value = (L >= 1024 || sizeof(T) == 8 || (L & (L - 1)) != 0) ? 2 : 4;
 };
 
-// The twiddle factors one lane needs, loaded once per kernel.
+// The twiddle factors one lane needs, loaded once per kernel.  FP32 lanes keep
+// every factor in registers; FP64 lanes keep the two generators (16 registers
+// instead of 56) and form the powers for each stage as it starts (balanced
+// products, a few ulps of FP64), so that the FP64 passes fit more waves.
 template <typename T, int L>
 struct LaneTw {
   static constexpr int E = FftShape<L>::E;
   static constexpr int R2 = FftShape<L>::R2;
   static constexpr int NB2 = FftShape<L>::NB2;
   static constexpr int LP = FftShape<L>::LP;
-  Cx<T> s1[E];        // stage 2 (Ns = E): W_L^{q k (L / E^2)}, k = lane mod E
-  Cx<T> s2[NB2][R2];  // stage 3 (Ns = E^2): W_L^{q j}, j = lane + LP b
+  static constexpr bool POW = sizeof(T) == 8;
+  static constexpr int S1 = POW ? 1 : E;
+  static constexpr int S2 = POW ? 1 : R2;
+  Cx<T> s1[S1 > 1 ? S1 : 2];  // stage 2 (Ns = E): W_L^{q k (L / E^2)}, k = lane mod E (POW: q = 1 only)
+  Cx<T> s2[NB2][S2 > 1 ? S2 : 2];  // stage 3 (Ns = E^2): W_L^{q j}, j = lane + LP b (POW: q = 1 only)
   // tw[i] = exp(-2 pi i i / (L * stride)): the table of a line stride times as long
   __device__ __forceinline__ void load(const Cx<T>* __restrict__ tw, int lane, int stride = 1) {
     const int k = lane & (E - 1);
 #pragma unroll
-    for (int q = 1; q < E; ++q) s1[q] = tw[stride * (q * k) * (L / (E * E))];
+    for (int q = 1; q < (POW ? 2 : E); ++q) s1[q] = tw[stride * (q * k) * (L / (E * E))];
 #pragma unroll
     for (int b = 0; b < NB2; ++b) {
       const int j = lane + LP * b;
 #pragma unroll
-      for (int q = 1; q < R2; ++q) s2[b][q] = tw[stride * q * j];
+      for (int q = 1; q < (POW ? 2 : R2); ++q) s2[b][q] = tw[stride * q * j];
     }
   }
 };
+
+// Powers p[q] = g^q, q = 1 .. R - 1, by balanced products.
+template <typename T, int R>
+__device__ __forceinline__ void tw_powers(Cx<T> g, Cx<T> (&p)[R]) {
+  p[1] = g;
+#pragma unroll
+  for (int q = 2; q < R; ++q) p[q] = (q & 1) ? cmul(p[q - 1], g) : cmul(p[q / 2], p[q / 2]);
+}
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -194,11 +208,25 @@ __device__ __forceinline__ void fft_tail(Cx<T> (&v)[FftShape<L>::E], Cx<T>* buf,
   auto in2 = [&](int b, int q) -> Cx<T> {
     return rb[LP * b + (LP * b) / 8 + (L / R2) * q + (L / R2) * q / 8];
   };
-  auto tw1 = [&](int, int q) -> Cx<T> { return tw.s1[q]; };
-  auto tw2 = [&](int b, int q) -> Cx<T> { return tw.s2[b][q]; };
-  wstage<T, L, E, E, false>(v, in1, tw1, buf, lane);
-  wave_sync();
-  wstage<T, L, R2, E * E, true>(v, in2, tw2, buf, lane);
+  if constexpr (LaneTw<T, L>::POW) {
+    constexpr int NB2 = FftShape<L>::NB2;
+    Cx<T> p1[E];
+    tw_powers<T, E>(tw.s1[1], p1);
+    auto tw1 = [&](int, int q) -> Cx<T> { return p1[q]; };
+    wstage<T, L, E, E, false>(v, in1, tw1, buf, lane);
+    wave_sync();
+    Cx<T> p2[NB2][R2];
+#pragma unroll
+    for (int b = 0; b < NB2; ++b) tw_powers<T, R2>(tw.s2[b][1], p2[b]);
+    auto tw2 = [&](int b, int q) -> Cx<T> { return p2[b][q]; };
+    wstage<T, L, R2, E * E, true>(v, in2, tw2, buf, lane);
+  } else {
+    auto tw1 = [&](int, int q) -> Cx<T> { return tw.s1[q]; };
+    auto tw2 = [&](int b, int q) -> Cx<T> { return tw.s2[b][q]; };
+    wstage<T, L, E, E, false>(v, in1, tw1, buf, lane);
+    wave_sync();
+    wstage<T, L, R2, E * E, true>(v, in2, tw2, buf, lane);
+  }
 }
 
 // First stage of a length-L FFT on the inputs already in v (v[q] = input lane + LP q).
