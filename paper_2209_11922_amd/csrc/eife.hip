@@ -548,7 +548,10 @@ void col_fast_go(int mode, int pitch, int outer, int count, bool pipe, hipStream
   dim3 grid(pitch / (2 * PB), outer, count);
   if (!launch_shape_ok(grid, NT, size_t(PB) * fast::Line<T, L>::BUF * sizeof(Cx<T>))) return;
   if (mode == COL_PLAIN) {
-    if (pipe && !ci) {
+    // FP32: the persistent pass that prefetches each next tile; FP64 one tile
+    // per block (the prefetch registers would leave three waves per SIMD, one
+    // block per CU, where one tile per block fits two blocks: measured faster)
+    if (pipe && !ci && sizeof(T) == 4) {
       const int ntx = pitch / (2 * PB);
       const int ntiles = ntx * outer;
       constexpr int lds = PB * fast::Line<T, L>::BUF * int(sizeof(Cx<T>));
