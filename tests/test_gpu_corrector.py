@@ -514,3 +514,41 @@ def test_trainer_pipeline_small():
     theta, rs = cor.calibrate_theta(net, data, idx)
     assert guard > 0 and theta > 0 and len(rs) == idx.numel()
     net.close()
+
+
+@pytest.mark.parametrize("n, written", [(512, True), (256, True), (96, False)])
+def test_coarse_step_change_sums(n, written):
+    """The step that also writes, per pair of rows, the sum of (u_out - u_in)^2 (what the
+    corrected step's RMS change is formed from): its result equals eife_step_out bit for
+    bit, and the sums equal the same sums formed in FP64 on the host (to rounding order);
+    grids whose rows do not run one line pair per wavefront run the plain step (done = 0)."""
+    import ctypes
+    from paper_2209_11922_amd import binding
+    eife = _lib()
+    lib = binding.load_library()
+    lib.eife_step_out_change.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_int, ctypes.c_double, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_int), ctypes.c_void_p]
+    N, h = [n, n], [1.0 / n] * 2
+    g = eife.Grid(N, h, 4e-4, "f32")
+    g.set_phi(0.016, 2)
+    u0 = _dev(seeded_inputs.uniform_field(77, N))
+    ref = torch.empty_like(u0)
+    g.step_out(u0, ref, 1, eife.F_ALLEN_CAHN, 0.25)
+    out = torch.full_like(u0, float("nan"))
+    pairs = (n - 1 + 1) // 2
+    chg = torch.full((pairs,), float("nan"), dtype=torch.float64, device="cuda")
+    done = ctypes.c_int(-1)
+    rc = lib.eife_step_out_change(g._g, ctypes.c_void_p(u0.data_ptr()), ctypes.c_void_p(out.data_ptr()), 1,
+                                  eife.F_ALLEN_CAHN, 0.25, ctypes.c_void_p(chg.data_ptr()), ctypes.byref(done),
+                                  None)
+    torch.cuda.synchronize()
+    assert rc == 0 and done.value == int(written)
+    assert torch.equal(out, ref)
+    if written:
+        d = (out.double() - u0.double()).cpu().numpy()
+        rows = (d * d).sum(axis=1)
+        want = np.array([rows[2 * p:2 * p + 2].sum() for p in range(pairs)])
+        got = chg.cpu().numpy()
+        assert np.all(np.abs(got - want) <= 1e-12 * np.abs(want).max())
+    g.close()
