@@ -105,17 +105,18 @@ struct MinWaves {
   static constexpr int value = (L >= 1024 || sizeof(T) == 8 || (L & (L - 1)) != 0) ? 2 : 4;
 };
 
-// The twiddle factors one lane needs, loaded once per kernel.  FP32 lanes keep
-// every factor in registers; FP64 lanes keep the two generators (16 registers
-// instead of 56) and form the powers for each stage as it starts (balanced
-// products, a few ulps of FP64), so that the FP64 passes fit more waves.
+// The twiddle factors one lane needs, loaded once per kernel.  FP32 lanes of
+// lines up to 512 points keep every factor in registers; FP64 lanes and FP32
+// lanes of 1024-point lines keep the two generators only (FP64 512: 16
+// registers instead of 56) and form the powers for each stage as it starts
+// (balanced products, a few ulps), so that these passes fit more waves.
 template <typename T, int L>
 struct LaneTw {
   static constexpr int E = FftShape<L>::E;
   static constexpr int R2 = FftShape<L>::R2;
   static constexpr int NB2 = FftShape<L>::NB2;
   static constexpr int LP = FftShape<L>::LP;
-  static constexpr bool POW = sizeof(T) == 8;
+  static constexpr bool POW = sizeof(T) == 8 || L >= 1024;
   static constexpr int S1 = POW ? 1 : E;
   static constexpr int S2 = POW ? 1 : R2;
   Cx<T> s1[S1 > 1 ? S1 : 2];  // stage 2 (Ns = E): W_L^{q k (L / E^2)}, k = lane mod E (POW: q = 1 only)
