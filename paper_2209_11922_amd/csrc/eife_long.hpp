@@ -9,7 +9,10 @@
 // adds a final radix-2 stage) whose exchanges go through the pair's LDS buffer
 // with block barriers, and the last stage's outputs left in registers.  The
 // generic passes do every stage as a full LDS sweep; here the values stay in
-// registers between exchanges.
+// registers between exchanges.  Each thread loads its twiddle generators once
+// per kernel (two per radix-16 stage, one for the last stage) and forms the
+// powers for each stage by products at most three deep, so no stage waits on
+// a table load.
 #pragma once
 
 #include "eife_kernels.hpp"
@@ -38,20 +41,69 @@ struct LongWaves {
   static constexpr int value = (sizeof(T) == 4 && L == 8192) ? 4 : 1;
 };
 
+// Twiddle generators of one thread (tw[i] = exp(-2 pi i i / L)): for the
+// stage after Ns = 16 points (radix 16) and the one after Ns = 256 (radix 16,
+// or 8 when L = 2048), g = W_L^{k S} and g4 = W_L^{4 k S} with k = t mod Ns
+// and S = L / (Ns R); for the radix-2 stage after Ns = 4096 (L = 8192), W_L^t.
+template <typename T, int L>
+struct LongTw {
+  Cx<T> a1, a4, b1, b4, c1;
+  __device__ __forceinline__ LongTw(const Cx<T>* __restrict__ tw, int t) {
+    constexpr int SA = L / 256;
+    constexpr int RB = L == 2048 ? 8 : 16;
+    constexpr int SB = L / (256 * RB);
+    a1 = tw[(t & 15) * SA];
+    a4 = tw[4 * (t & 15) * SA];
+    b1 = tw[(t & 255) * SB];
+    b4 = tw[4 * (t & 255) * SB];
+    c1 = L == 8192 ? tw[t] : Cx<T>{T(1), T(0)};
+  }
+};
+
+// p[q] = g^q, q = 1 .. R - 1 (R = 2, 8 or 16), from g and g4 = g^4: q = 4a + c
+// as g4^a g^c.
+template <typename T, int R>
+__device__ __forceinline__ void gen_powers(Cx<T> g, Cx<T> g4, Cx<T> (&p)[R]) {
+  p[1] = g;
+  if constexpr (R > 2) {
+    p[2] = cmul(g, g);
+    p[3] = cmul(p[2], g);
+    p[4] = g4;
+  }
+  if constexpr (R > 8) {
+    p[8] = cmul(g4, g4);
+    p[12] = cmul(p[8], g4);
+  }
+#pragma unroll
+  for (int q = 5; q < R; ++q)
+    if (q & 3) p[q] = cmul(p[q & ~3], p[q & 3]);
+}
+
 // Twiddle, butterflies and (unless LAST) the Stockham write of one stage of
 // radix R after Ns points: butterfly j = t + NT b reads inputs j + (L/R) q,
-// multiplies input q by W_{Ns R}^{(j mod Ns) q} (tw[i] = exp(-2 pi i i / L)).
+// multiplies input q by W_{Ns R}^{(j mod Ns) q} = W_L^{(j mod Ns) q S}, S = L / (Ns R).
+// The thread's powers p[q] = W_L^{(t mod Ns) q S} come from its generators g,
+// g4; when NT < Ns, j mod Ns = t + NT b and the factor W_L^{NT b q S} is the
+// same for every thread (a table load from a uniform address).
 template <typename T, int L, int R, int Ns, bool LAST>
-__device__ __forceinline__ void stage(Cx<T> (&v)[16], Cx<T>* buf, const Cx<T>* __restrict__ tw, int t) {
+__device__ __forceinline__ void stage(Cx<T> (&v)[16], Cx<T>* buf, const Cx<T>* __restrict__ tw, Cx<T> g,
+                                      Cx<T> g4, int t) {
   constexpr int NT = Shape<L>::NT;
   constexpr int NB = 16 / R;
+  constexpr int S = L / (Ns * R);
+  Cx<T> p[R];
+  if constexpr (Ns > 1) gen_powers<T, R>(g, g4, p);
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int j = t + NT * b;
     if constexpr (Ns > 1) {
-      const int k = j & (Ns - 1);
+      static_assert(NT % Ns == 0 || NT * NB <= Ns, "stage shape");
 #pragma unroll
-      for (int q = 1; q < R; ++q) v[b * R + q] = cmul(v[b * R + q], tw[(k * q) * (L / (Ns * R))]);
+      for (int q = 1; q < R; ++q) {
+        Cx<T> w = p[q];
+        if constexpr (NT % Ns != 0)
+          if (b > 0) w = cmul(w, tw[(NT * b * q * S) & (L - 1)]);
+        v[b * R + q] = cmul(v[b * R + q], w);
+      }
     }
     DftN<T, R>::run(&v[b * R]);
   }
@@ -86,7 +138,7 @@ __device__ __forceinline__ void gather(Cx<T> (&v)[16], const Cx<T>* buf, int t) 
 // output t + NT b + q (L / RL).  Every thread of the block takes part.
 template <typename T, int L>
 __device__ __forceinline__ void odd_fft(Cx<T> (&v)[16], const Cx<T>* node, Cx<T>* buf,
-                                        const Cx<T>* __restrict__ tw, int t) {
+                                        const Cx<T>* __restrict__ tw, const LongTw<T, L>& gt, int t) {
   constexpr int NT = Shape<L>::NT;
   constexpr int N = L / 2;
 #pragma unroll
@@ -102,27 +154,27 @@ __device__ __forceinline__ void odd_fft(Cx<T> (&v)[16], const Cx<T>* node, Cx<T>
     }
   }
   __syncthreads();  // every node value is read before the buffer is written
-  stage<T, L, 16, 1, false>(v, buf, tw, t);
+  stage<T, L, 16, 1, false>(v, buf, tw, gt.a1, gt.a4, t);
   __syncthreads();
   gather<T, L, 16>(v, buf, t);
   __syncthreads();
-  stage<T, L, 16, 16, false>(v, buf, tw, t);
+  stage<T, L, 16, 16, false>(v, buf, tw, gt.a1, gt.a4, t);
   __syncthreads();
   if constexpr (L == 2048) {
     gather<T, L, 8>(v, buf, t);
-    stage<T, L, 8, 256, true>(v, buf, tw, t);
+    stage<T, L, 8, 256, true>(v, buf, tw, gt.b1, gt.b4, t);
     __syncthreads();  // the buffer may be rewritten next
     return;
   }
   gather<T, L, 16>(v, buf, t);
   if constexpr (L == 8192) {
     __syncthreads();
-    stage<T, L, 16, 256, false>(v, buf, tw, t);
+    stage<T, L, 16, 256, false>(v, buf, tw, gt.b1, gt.b4, t);
     __syncthreads();
     gather<T, L, 2>(v, buf, t);
-    stage<T, L, 2, 4096, true>(v, buf, tw, t);
+    stage<T, L, 2, 4096, true>(v, buf, tw, gt.c1, gt.c1, t);
   } else {
-    stage<T, L, 16, 256, true>(v, buf, tw, t);
+    stage<T, L, 16, 256, true>(v, buf, tw, gt.b1, gt.b4, t);
   }
   __syncthreads();  // the buffer may be rewritten next
 }
@@ -168,6 +220,7 @@ __global__ void __launch_bounds__((Shape<L>::NT), (LongWaves<T, L>::value))
   const int ra = blockIdx.x * 2, rb = ra + 1;
   const bool hasb = rb < g.nrows;
   const T scale = T(1.0 / sqrt(double(L)));
+  const LongTw<T, L> gt(tw, t);
   {
     const T* sa = src + int64_t(ra) * g.ld_src + t;
     const T* sb = src + int64_t(rb) * g.ld_src + t;
@@ -184,7 +237,7 @@ __global__ void __launch_bounds__((Shape<L>::NT), (LongWaves<T, L>::value))
   }
   __syncthreads();
   Cx<T> v[16];
-  odd_fft<T, L>(v, lds, lds, tw, t);
+  odd_fft<T, L>(v, lds, lds, tw, gt, t);
   if constexpr (MODE == ROW_PHYS) {
     const int iya = ra % g.ny, iza = ra / g.ny;
     const int iyb = rb % g.ny, izb = rb / g.ny;
@@ -193,7 +246,7 @@ __global__ void __launch_bounds__((Shape<L>::NT), (LongWaves<T, L>::value))
       lds[k - 1] = Cx<T>{fast::reaction_k<T, RK>(F, ua, k - 1, iya, iza), fast::reaction_k<T, RK>(F, ub, k - 1, iyb, izb)};
     });
     __syncthreads();
-    odd_fft<T, L>(v, lds, lds, tw, t);
+    odd_fft<T, L>(v, lds, lds, tw, gt, t);
   }
   outputs<T, L>(v, t, [&](int k, Cx<T> Z) { lds[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
   __syncthreads();
@@ -235,6 +288,7 @@ __global__ void __launch_bounds__((Shape<L>::NT), (LongWaves<T, L>::value))
   const int c0 = 2 * bx;
   const int64_t base = int64_t(outer) * g.ld_outer + c0;
   const T scale = T(1.0 / sqrt(double(L)));
+  const LongTw<T, L> gt(tw, t);
   Cx<T> hv[MODE == COL_PLAIN ? 1 : NO];
   if constexpr (MODE != COL_PLAIN) {
 #pragma unroll
@@ -251,7 +305,7 @@ __global__ void __launch_bounds__((Shape<L>::NT), (LongWaves<T, L>::value))
   }
   __syncthreads();
   Cx<T> v[16];
-  odd_fft<T, L>(v, lds, lds, tw, t);
+  odd_fft<T, L>(v, lds, lds, tw, gt, t);
   if constexpr (MODE != COL_PLAIN) {
     const double tau = dg.tau, D = dg.D;
     const double rtc2 = 1.0 / (tau * dg.c2);
@@ -273,7 +327,7 @@ __global__ void __launch_bounds__((Shape<L>::NT), (LongWaves<T, L>::value))
       lds[m] = Cx<T>{T(o0), T(o1)};
     }
     __syncthreads();
-    odd_fft<T, L>(v, lds, lds, tw, t);
+    odd_fft<T, L>(v, lds, lds, tw, gt, t);
   }
   outputs<T, L>(v, t, [&](int k, Cx<T> Z) { lds[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
   __syncthreads();
