@@ -60,6 +60,14 @@ struct LongTw {
   }
 };
 
+// Makes the generators opaque to the optimiser, so that a second transform
+// forms its powers again instead of keeping the first one's in registers.
+template <typename T, int L>
+__device__ __forceinline__ void refresh(LongTw<T, L>& gt) {
+  asm volatile("" : "+v"(gt.a1.re), "+v"(gt.a1.im), "+v"(gt.a4.re), "+v"(gt.a4.im), "+v"(gt.b1.re), "+v"(gt.b1.im),
+               "+v"(gt.b4.re), "+v"(gt.b4.im), "+v"(gt.c1.re), "+v"(gt.c1.im));
+}
+
 // p[q] = g^q, q = 1 .. R - 1 (R = 2, 8 or 16), from g and g4 = g^4: q = 4a + c
 // as g4^a g^c.
 template <typename T, int R>
@@ -220,7 +228,7 @@ __global__ void __launch_bounds__((Shape<L>::NT), (LongWaves<T, L>::value))
   const int ra = blockIdx.x * 2, rb = ra + 1;
   const bool hasb = rb < g.nrows;
   const T scale = T(1.0 / sqrt(double(L)));
-  const LongTw<T, L> gt(tw, t);
+  LongTw<T, L> gt(tw, t);
   {
     const T* sa = src + int64_t(ra) * g.ld_src + t;
     const T* sb = src + int64_t(rb) * g.ld_src + t;
@@ -246,6 +254,7 @@ __global__ void __launch_bounds__((Shape<L>::NT), (LongWaves<T, L>::value))
       lds[k - 1] = Cx<T>{fast::reaction_k<T, RK>(F, ua, k - 1, iya, iza), fast::reaction_k<T, RK>(F, ub, k - 1, iyb, izb)};
     });
     __syncthreads();
+    refresh(gt);
     odd_fft<T, L>(v, lds, lds, tw, gt, t);
   }
   outputs<T, L>(v, t, [&](int k, Cx<T> Z) { lds[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
@@ -288,7 +297,7 @@ __global__ void __launch_bounds__((Shape<L>::NT), (LongWaves<T, L>::value))
   const int c0 = 2 * bx;
   const int64_t base = int64_t(outer) * g.ld_outer + c0;
   const T scale = T(1.0 / sqrt(double(L)));
-  const LongTw<T, L> gt(tw, t);
+  LongTw<T, L> gt(tw, t);
   Cx<T> hv[MODE == COL_PLAIN ? 1 : NO];
   if constexpr (MODE != COL_PLAIN) {
 #pragma unroll
@@ -327,6 +336,7 @@ __global__ void __launch_bounds__((Shape<L>::NT), (LongWaves<T, L>::value))
       lds[m] = Cx<T>{T(o0), T(o1)};
     }
     __syncthreads();
+    refresh(gt);
     odd_fft<T, L>(v, lds, lds, tw, gt, t);
   }
   outputs<T, L>(v, t, [&](int k, Cx<T> Z) { lds[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
