@@ -154,6 +154,19 @@ struct Dft<T, 7> {
 // long lines hold 8).
 constexpr int kMaxElems = 32;
 
+// Multiplies input q of a butterfly by g^q, q = 1 .. R - 1 (g = W_L^{k L / (Ns R)}),
+// the powers formed by products at most four deep: one table load per
+// butterfly instead of R - 1.
+template <typename T, int R>
+__device__ __forceinline__ void twiddle_powers(Cx<T>* v, Cx<T> g) {
+  Cx<T> p[R];
+  p[1] = g;
+#pragma unroll
+  for (int q = 2; q < R; ++q) p[q] = (q & 1) ? cmul(p[q - 1], g) : cmul(p[q / 2], p[q / 2]);
+#pragma unroll
+  for (int q = 1; q < R; ++q) v[q] = cmul(v[q], p[q]);
+}
+
 // One radix-R stage on P lines of length L stored at lds + p * ls.  Ns is the
 // product of the radices already applied; tw[j] = exp(-2 pi i j / L).
 template <typename T, int R, int ME>
@@ -173,8 +186,7 @@ __device__ void stockham_stage(Cx<T>* lds, int ls, int L, int P, int Ns, const C
       const int k = j % Ns;
 #pragma unroll
       for (int q = 0; q < R; ++q) v[s][q] = line[j + q * nbf];
-#pragma unroll
-      for (int q = 1; q < R; ++q) v[s][q] = cmul(v[s][q], tw[q * k * tws]);
+      if (Ns > 1) twiddle_powers<T, R>(v[s], tw[k * tws]);
       Dft<T, R>::run(v[s]);
     }
   }
