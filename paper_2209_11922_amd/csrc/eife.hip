@@ -763,16 +763,30 @@ template <typename T, int L>
 void col_long_launch(int mode, int pitch, int outer, hipStream_t s, T* W, T* H, const ColGeom& cg, const Cx<T>* tw,
                      const Diag& dg) {
   constexpr int NT = lng::Shape<L>::NT;
-  const dim3 grid(pitch / 2, outer);
-  if (!launch_shape_ok(grid, NT, lng::Shape<L>::BUF * sizeof(Cx<T>))) return;
-  if (mode == COL_PLAIN)
-    hipLaunchKernelGGL((lng::col_long<T, L, COL_PLAIN>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
-  else if (mode == COL_STAGE_A)
-    hipLaunchKernelGGL((lng::col_long<T, L, COL_STAGE_A>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
-  else if (mode == COL_STAGE_B)
-    hipLaunchKernelGGL((lng::col_long<T, L, COL_STAGE_B>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
-  else
-    hipLaunchKernelGGL((lng::col_long<T, L, COL_ETD1>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+  if constexpr (sizeof(T) == 4) {
+    // two column pairs (16 bytes of a row) per block of 2 NT threads; the pitch is a multiple of 32
+    const dim3 grid(pitch / 4, outer);
+    if (!launch_shape_ok(grid, 2 * NT, 2 * lng::Shape<L>::BUF * sizeof(Cx<T>))) return;
+    if (mode == COL_PLAIN)
+      hipLaunchKernelGGL((lng::col_long4<T, L, COL_PLAIN>), grid, dim3(2 * NT), 0, s, W, H, cg, tw, dg);
+    else if (mode == COL_STAGE_A)
+      hipLaunchKernelGGL((lng::col_long4<T, L, COL_STAGE_A>), grid, dim3(2 * NT), 0, s, W, H, cg, tw, dg);
+    else if (mode == COL_STAGE_B)
+      hipLaunchKernelGGL((lng::col_long4<T, L, COL_STAGE_B>), grid, dim3(2 * NT), 0, s, W, H, cg, tw, dg);
+    else
+      hipLaunchKernelGGL((lng::col_long4<T, L, COL_ETD1>), grid, dim3(2 * NT), 0, s, W, H, cg, tw, dg);
+  } else {
+    const dim3 grid(pitch / 2, outer);
+    if (!launch_shape_ok(grid, NT, lng::Shape<L>::BUF * sizeof(Cx<T>))) return;
+    if (mode == COL_PLAIN)
+      hipLaunchKernelGGL((lng::col_long<T, L, COL_PLAIN>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+    else if (mode == COL_STAGE_A)
+      hipLaunchKernelGGL((lng::col_long<T, L, COL_STAGE_A>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+    else if (mode == COL_STAGE_B)
+      hipLaunchKernelGGL((lng::col_long<T, L, COL_STAGE_B>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+    else
+      hipLaunchKernelGGL((lng::col_long<T, L, COL_ETD1>), grid, dim3(NT), 0, s, W, H, cg, tw, dg);
+  }
 }
 
 template <typename T>

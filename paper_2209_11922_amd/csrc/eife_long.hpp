@@ -348,5 +348,89 @@ __global__ void __launch_bounds__((Shape<L>::NT), (LongWaves<T, L>::value))
   }
 }
 
+// FP32 column pass over two adjacent column pairs per block: columns c0 .. c0+3
+// of a row are read and written as one 16-byte access, which halves the memory
+// requests of the strided axis against one pair per block (an 8-byte piece of
+// each row).  Threads [0, NT) transform the first pair and [NT, 2 NT) the
+// second, each in its own LDS buffer; the diagonal stage runs row by row over
+// the sine coefficients both halves left in LDS, so H is read and written as
+// 16-byte rows as well.  Modes as col_long; blocks in XCD-contiguous order.
+template <typename T, int L, int MODE>
+__global__ void __launch_bounds__((2 * Shape<L>::NT), (LongWaves<T, L>::value))
+    col_long4(T* W, T* H, ColGeom g, const Cx<T>* __restrict__ tw, Diag dg) {
+  static_assert(sizeof(T) == 4, "four FP32 columns per 16-byte access");
+  constexpr int NT = Shape<L>::NT;
+  constexpr int N = L / 2;
+  constexpr int n = N - 1;
+  constexpr int RIT = (n + 2 * NT - 1) / (2 * NT);
+  __shared__ Cx<T> lds2[2][Shape<L>::BUF];
+  const int half = int(threadIdx.x) / NT;  // uniform per wavefront (NT is a multiple of 64)
+  const int t = int(threadIdx.x) - half * NT;
+  const int tb = int(threadIdx.x);
+  Cx<T>* lds = lds2[half];
+  int bx, outer;
+  xcd_block(bx, outer);
+  const int c0 = 4 * bx;
+  const int64_t base = int64_t(outer) * g.ld_outer + c0;
+  const T scale = T(1.0 / sqrt(double(L)));
+  LongTw<T, L> gt(tw, t);
+#pragma unroll
+  for (int i = 0; i < RIT; ++i) {
+    const int m = tb + 2 * NT * i;
+    if (m < n) {
+      const float4 w = *reinterpret_cast<const float4*>(W + base + int64_t(m) * g.ld_line);
+      lds2[0][m] = mask_pad(Cx<T>{w.x, w.y}, c0, g.ncols);
+      lds2[1][m] = mask_pad(Cx<T>{w.z, w.w}, c0 + 2, g.ncols);
+    }
+  }
+  __syncthreads();
+  Cx<T> v[16];
+  odd_fft<T, L>(v, lds, lds, tw, gt, t);
+  if constexpr (MODE != COL_PLAIN) {
+    outputs<T, L>(v, t, [&](int k, Cx<T> Z) { lds[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+    __syncthreads();
+    const double tau = dg.tau, D = dg.D;
+    const double rtc2 = 1.0 / (tau * dg.c2);
+    const Sep so = g.last_is_z ? sep_load(dg.ax[1], outer) : sep_load(dg.ax[2], 0);
+    const AxisTab line_tab = g.last_is_z ? dg.ax[2] : dg.ax[1];
+#pragma unroll
+    for (int i = 0; i < RIT; ++i) {
+      const int m = tb + 2 * NT * i;
+      if (m >= n) continue;
+      const float4 h = *reinterpret_cast<const float4*>(H + base + int64_t(m) * g.ld_line);
+      const Cx<T> a = lds2[0][m], b = lds2[1][m];
+      const Sep sl = sep_load(line_tab, m);
+      const T gin[4] = {a.re, a.im, b.re, b.im};
+      const T hin[4] = {h.x, h.y, h.z, h.w};
+      T o[4], nh[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double oq, nq;
+        fast::diag_fast<MODE>(sep_combine(sep_combine(sep_load(dg.ax[0], c0 + q), so), sl), D, tau, rtc2,
+                              double(gin[q]), double(hin[q]), &oq, &nq);
+        o[q] = T(oq);
+        nh[q] = T(nq);
+      }
+      const Cx<T> h0 = mask_pad(Cx<T>{nh[0], nh[1]}, c0, g.ncols), h1 = mask_pad(Cx<T>{nh[2], nh[3]}, c0 + 2, g.ncols);
+      *reinterpret_cast<float4*>(H + base + int64_t(m) * g.ld_line) = float4{h0.re, h0.im, h1.re, h1.im};
+      lds2[0][m] = Cx<T>{o[0], o[1]};
+      lds2[1][m] = Cx<T>{o[2], o[3]};
+    }
+    __syncthreads();
+    refresh(gt);
+    odd_fft<T, L>(v, lds, lds, tw, gt, t);
+  }
+  outputs<T, L>(v, t, [&](int k, Cx<T> Z) { lds[k - 1] = Cx<T>{-Z.im * scale, Z.re * scale}; });
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RIT; ++i) {
+    const int m = tb + 2 * NT * i;
+    if (m < n) {
+      const Cx<T> a = mask_pad(lds2[0][m], c0, g.ncols), b = mask_pad(lds2[1][m], c0 + 2, g.ncols);
+      *reinterpret_cast<float4*>(W + base + int64_t(m) * g.ld_line) = float4{a.re, a.im, b.re, b.im};
+    }
+  }
+}
+
 }  // namespace lng
 }  // namespace eife
