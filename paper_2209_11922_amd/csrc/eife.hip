@@ -763,8 +763,9 @@ template <typename T, int L>
 void col_long_launch(int mode, int pitch, int outer, hipStream_t s, T* W, T* H, const ColGeom& cg, const Cx<T>* tw,
                      const Diag& dg) {
   constexpr int NT = lng::Shape<L>::NT;
-  if constexpr (sizeof(T) == 4) {
-    // two column pairs (16 bytes of a row) per block of 2 NT threads; the pitch is a multiple of 32
+  if constexpr (2 * lng::Shape<L>::BUF * sizeof(Cx<T>) <= 160 * 1024) {
+    // two column pairs (a 16- or 32-byte row piece) per block of 2 NT threads (FP32, and FP64 up to
+    // 4096 points); the pitch is a multiple of 32
     const dim3 grid(pitch / 4, outer);
     if (!launch_shape_ok(grid, 2 * NT, 2 * lng::Shape<L>::BUF * sizeof(Cx<T>))) return;
     if (mode == COL_PLAIN)

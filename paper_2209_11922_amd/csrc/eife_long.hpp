@@ -348,17 +348,41 @@ __global__ void __launch_bounds__((Shape<L>::NT), (LongWaves<T, L>::value))
   }
 }
 
-// FP32 column pass over two adjacent column pairs per block: columns c0 .. c0+3
-// of a row are read and written as one 16-byte access, which halves the memory
-// requests of the strided axis against one pair per block (an 8-byte piece of
-// each row).  Threads [0, NT) transform the first pair and [NT, 2 NT) the
-// second, each in its own LDS buffer; the diagonal stage runs row by row over
-// the sine coefficients both halves left in LDS, so H is read and written as
-// 16-byte rows as well.  Modes as col_long; blocks in XCD-contiguous order.
+// Columns c .. c + 3 of one row: one 16-byte access (FP32) or two adjacent
+// 16-byte accesses (FP64).
+template <typename T>
+__device__ __forceinline__ void load4(const T* p, Cx<T>& a, Cx<T>& b) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 w = *reinterpret_cast<const float4*>(p);
+    a = Cx<T>{w.x, w.y};
+    b = Cx<T>{w.z, w.w};
+  } else {
+    a = reinterpret_cast<const Cx<T>*>(p)[0];
+    b = reinterpret_cast<const Cx<T>*>(p)[1];
+  }
+}
+template <typename T>
+__device__ __forceinline__ void store4(T* p, Cx<T> a, Cx<T> b) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = float4{a.re, a.im, b.re, b.im};
+  } else {
+    reinterpret_cast<Cx<T>*>(p)[0] = a;
+    reinterpret_cast<Cx<T>*>(p)[1] = b;
+  }
+}
+
+// Column pass over two adjacent column pairs per block: columns c0 .. c0+3 of
+// a row are read and written as one piece (16 bytes FP32, 32 bytes FP64),
+// which halves the memory requests of the strided axis against one pair per
+// block.  Threads [0, NT) transform the first pair and [NT, 2 NT) the second,
+// each in its own LDS buffer (two FP64 buffers fit up to 4096 points); the
+// diagonal stage runs row by row over the sine coefficients both halves left
+// in LDS, so H moves as whole row pieces as well.  Modes as col_long; blocks
+// in XCD-contiguous order.
 template <typename T, int L, int MODE>
 __global__ void __launch_bounds__((2 * Shape<L>::NT), (LongWaves<T, L>::value))
     col_long4(T* W, T* H, ColGeom g, const Cx<T>* __restrict__ tw, Diag dg) {
-  static_assert(sizeof(T) == 4, "four FP32 columns per 16-byte access");
+  static_assert(2 * Shape<L>::BUF * sizeof(Cx<T>) <= 160 * 1024, "two pair buffers per block");
   constexpr int NT = Shape<L>::NT;
   constexpr int N = L / 2;
   constexpr int n = N - 1;
@@ -378,9 +402,10 @@ __global__ void __launch_bounds__((2 * Shape<L>::NT), (LongWaves<T, L>::value))
   for (int i = 0; i < RIT; ++i) {
     const int m = tb + 2 * NT * i;
     if (m < n) {
-      const float4 w = *reinterpret_cast<const float4*>(W + base + int64_t(m) * g.ld_line);
-      lds2[0][m] = mask_pad(Cx<T>{w.x, w.y}, c0, g.ncols);
-      lds2[1][m] = mask_pad(Cx<T>{w.z, w.w}, c0 + 2, g.ncols);
+      Cx<T> a, b;
+      load4(W + base + int64_t(m) * g.ld_line, a, b);
+      lds2[0][m] = mask_pad(a, c0, g.ncols);
+      lds2[1][m] = mask_pad(b, c0 + 2, g.ncols);
     }
   }
   __syncthreads();
@@ -397,11 +422,12 @@ __global__ void __launch_bounds__((2 * Shape<L>::NT), (LongWaves<T, L>::value))
     for (int i = 0; i < RIT; ++i) {
       const int m = tb + 2 * NT * i;
       if (m >= n) continue;
-      const float4 h = *reinterpret_cast<const float4*>(H + base + int64_t(m) * g.ld_line);
+      Cx<T> ha, hb;
+      load4(H + base + int64_t(m) * g.ld_line, ha, hb);
       const Cx<T> a = lds2[0][m], b = lds2[1][m];
       const Sep sl = sep_load(line_tab, m);
       const T gin[4] = {a.re, a.im, b.re, b.im};
-      const T hin[4] = {h.x, h.y, h.z, h.w};
+      const T hin[4] = {ha.re, ha.im, hb.re, hb.im};
       T o[4], nh[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -412,7 +438,7 @@ __global__ void __launch_bounds__((2 * Shape<L>::NT), (LongWaves<T, L>::value))
         nh[q] = T(nq);
       }
       const Cx<T> h0 = mask_pad(Cx<T>{nh[0], nh[1]}, c0, g.ncols), h1 = mask_pad(Cx<T>{nh[2], nh[3]}, c0 + 2, g.ncols);
-      *reinterpret_cast<float4*>(H + base + int64_t(m) * g.ld_line) = float4{h0.re, h0.im, h1.re, h1.im};
+      store4(H + base + int64_t(m) * g.ld_line, h0, h1);
       lds2[0][m] = Cx<T>{o[0], o[1]};
       lds2[1][m] = Cx<T>{o[2], o[3]};
     }
@@ -426,8 +452,7 @@ __global__ void __launch_bounds__((2 * Shape<L>::NT), (LongWaves<T, L>::value))
   for (int i = 0; i < RIT; ++i) {
     const int m = tb + 2 * NT * i;
     if (m < n) {
-      const Cx<T> a = mask_pad(lds2[0][m], c0, g.ncols), b = mask_pad(lds2[1][m], c0 + 2, g.ncols);
-      *reinterpret_cast<float4*>(W + base + int64_t(m) * g.ld_line) = float4{a.re, a.im, b.re, b.im};
+      store4(W + base + int64_t(m) * g.ld_line, mask_pad(lds2[0][m], c0, g.ncols), mask_pad(lds2[1][m], c0 + 2, g.ncols));
     }
   }
 }

@@ -90,18 +90,20 @@ def test_long_lines_1024_thread_passes(N, dtype):
     assert err <= (1e-12 if dtype == "f64" else 1e-5)
 
 
-@pytest.mark.parametrize("N,stages", [([30, 4096], 2), ([4096, 4096], 2), ([10, 6, 2048], 2), ([14, 1024], 1),
-                                      ([60, 2048], 2)],
-                         ids=["8192pt-cols-ragged", "8192pt-4095sq", "4096pt-z-lines", "2048pt-cols-eife1",
-                              "4096pt-cols"])
-def test_long_columns_f32_four_column_blocks(N, stages):
-    """FP32 lines of 2048 to 8192 FFT points on the strided axis run two column pairs per block (16-byte
-    row pieces); the ragged cases leave one pair half padding and one whole pair of padding."""
+@pytest.mark.parametrize("N,stages,dtype", [([30, 4096], 2, "f32"), ([4096, 4096], 2, "f32"), ([10, 6, 2048], 2, "f32"),
+                                            ([14, 1024], 1, "f32"), ([60, 2048], 2, "f32"), ([30, 2048], 2, "f64"),
+                                            ([60, 1024], 1, "f64"), ([6, 10, 2048], 2, "f64")],
+                         ids=["f32-8192pt-cols-ragged", "f32-8192pt-4095sq", "f32-4096pt-z-lines", "f32-2048pt-cols-eife1",
+                              "f32-4096pt-cols", "f64-4096pt-cols-ragged", "f64-2048pt-cols-eife1", "f64-4096pt-z-lines"])
+def test_long_columns_two_pairs_per_block(N, stages, dtype):
+    """Lines of 2048 to 8192 FFT points on a strided axis with two column pairs per block (FP32, and FP64 up to
+    4096 points: 16- or 32-byte row pieces); the ragged cases leave one pair half padding and one whole pair of
+    padding."""
     u0 = seeded_inputs.uniform_field(9, N)
-    got, ref = _run_both(N, 0.01, u0, 0.01, 3, stages, 1, problems.allen_cahn(), "f32")
+    got, ref = _run_both(N, 0.01, u0, 0.01, 3, stages, 1, problems.allen_cahn(), dtype)
     err = _rel(got, ref)
-    print(f"long f32 columns {N} EIFE{stages}: {err:.2e}")
-    assert err <= 1e-5
+    print(f"long {dtype} columns {N} EIFE{stages}: {err:.2e}")
+    assert err <= (1e-12 if dtype == "f64" else 1e-5)
 
 
 def test_long_periodic_lines():
