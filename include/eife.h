@@ -83,8 +83,10 @@ enum eife_load {
   EIFE_LOAD_NODAL = 1   /* P_h f replaced by the interpolant of the nodal values f(t, u_i) */
 };
 
-/* Create a grid: d in {1,2,3}; N[a] >= 2 intervals on axis a (N[a] <= 4096
- * and of the form 2^i 3^j 5^k 7^l); h[a] > 0 the mesh width; D > 0 the diffusion
+/* Create a grid: d in {1,2,3}; N[a] >= 2 intervals on axis a (N[a] <= 4096;
+ * any N: prime factors of the FFT length above 7 run as direct-DFT stages of
+ * the generic passes, R multiply-adds per output for a factor R, so large prime
+ * factors are slow); h[a] > 0 the mesh width; D > 0 the diffusion
  * coefficient (eq. (1.1)); bc is EIFE_BC_DIRICHLET (unknowns: the N[a] - 1
  * interior nodes of each axis, the sine basis of Section 4) or
  * EIFE_BC_PERIODIC (the variant at the end of Section 4: unknowns at the

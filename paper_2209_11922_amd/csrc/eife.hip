@@ -83,7 +83,8 @@ int g_cus = 256;                     // compute units of the device (set at grid
 
 bool factor_plan(int L, FftPlan* pl) {
   pl->L = L;
-  pl->n8 = pl->n4 = pl->n2 = pl->n3 = pl->n5 = pl->n7 = 0;
+  pl->n8 = pl->n4 = pl->n2 = pl->n3 = pl->n5 = pl->n7 = pl->nd = 0;
+  pl->dr[0] = pl->dr[1] = pl->dr[2] = 0;
   int r = L;
   while (r % 8 == 0) {
     r /= 8;
@@ -108,6 +109,14 @@ bool factor_plan(int L, FftPlan* pl) {
   while (r % 7 == 0) {
     r /= 7;
     pl->n7++;
+  }
+  // the remaining prime factors (all above 7) run as direct-DFT stages
+  for (int p = 11; p <= r; p += 2) {
+    while (r % p == 0) {
+      if (pl->nd == 3) return false;
+      pl->dr[pl->nd++] = p;
+      r /= p;
+    }
   }
   return r == 1;
 }
@@ -1509,7 +1518,7 @@ int eife_create_grid(int d, const int32_t* N, const double* h, double D, int bc,
     if (!factor_plan(g->per[a] ? g->N[a] : 2 * g->N[a], &g->plan[a])) {
       const int bad = g->N[a];
       delete g;
-      return fail(EIFE_EUNSUPPORTED, "N = %d is not of the form 2^i 3^j 5^k 7^l", bad);
+      return fail(EIFE_EUNSUPPORTED, "N = %d: FFT length has more than three prime factors above 7", bad);
     }
   }
   g->pitch = ((g->n[0] + 31) / 32) * 32;

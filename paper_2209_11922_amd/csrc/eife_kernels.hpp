@@ -7,7 +7,8 @@
 // length L = 2N (z_m = c_m, z_{2N-m} = -c_m, z_0 = z_N = 0), a complex FFT of
 // length L gives Z_k = -2i (P a + i P b)_k, so the orthonormal transform
 // S = sqrt(2/N) P is (S a)_k = -Im Z_k / sqrt(2N), (S b)_k = Re Z_k / sqrt(2N).
-// The FFT is a mixed radix-8/4/2/3/5/7 Stockham autosort on lines held in LDS.
+// The FFT is a mixed radix-8/4/2/3/5/7 Stockham autosort on lines held in LDS
+// (prime factors above 7 take a direct-DFT stage each).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -210,7 +211,56 @@ __device__ void stockham_stage(Cx<T>* lds, int ls, int L, int P, int Ns, const C
 struct FftPlan {
   int L;      // FFT length (2N)
   int n8, n4, n2, n3, n5, n7;  // number of radix-8, -4, -2, -3, -5 and -7 stages
+  int nd;     // prime factors of L above 7 (at most 3 for L <= 8192), one direct-DFT stage each
+  int dr[3];
 };
+
+// One Stockham stage of a prime radix R > 7 as a direct R-point DFT: output m
+// of butterfly j (k = j mod Ns, nbf = L / R, S = L / (Ns R)) is
+//   sum_q line[j + q nbf] W_L^{q (k S + m nbf)},
+// the input twiddle and the DFT factor in one table entry per term.  The block
+// forms all its outputs in registers (sums in double) before the barrier and
+// writes them after it, so the stage runs in place.  R multiply-adds per
+// output: slow for a large prime, but it makes every N possible.
+template <typename T, int ME>
+__device__ void stockham_stage_dft(Cx<T>* lds, int ls, int L, int P, int Ns, int R, const Cx<T>* __restrict__ tw) {
+  const int nbf = L / R;
+  const int S = L / (Ns * R);
+  const int total = P * L;
+  Cx<T> out[ME];
+  int dst[ME];
+#pragma unroll
+  for (int s = 0; s < ME; ++s) {
+    const int i = int(threadIdx.x) + s * int(blockDim.x);
+    dst[s] = -1;
+    if (i < total) {
+      const int p = i / L;
+      const int r = i - p * L;
+      const int j = r % nbf;
+      const int m = r / nbf;
+      const int k = j % Ns;
+      const Cx<T>* line = lds + p * ls;
+      const int d = k * S + m * nbf;  // < L
+      double re = 0.0, im = 0.0;
+      int e = 0;
+      for (int q = 0; q < R; ++q) {
+        const Cx<T> x = line[j + q * nbf];
+        const Cx<T> w = tw[e];
+        re += double(x.re) * double(w.re) - double(x.im) * double(w.im);
+        im += double(x.re) * double(w.im) + double(x.im) * double(w.re);
+        e += d;
+        if (e >= L) e -= L;
+      }
+      out[s] = Cx<T>{T(re), T(im)};
+      dst[s] = p * ls + (j - k) * R + k + Ns * m;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < ME; ++s)
+    if (dst[s] >= 0) lds[dst[s]] = out[s];
+  __syncthreads();
+}
 
 // Forward FFT of P lines in LDS (natural order in and out).  Callers must
 // __syncthreads() before (inputs written) -- stages synchronise internally.
@@ -241,6 +291,10 @@ __device__ void fft_lines(Cx<T>* lds, int ls, int P, FftPlan pl, const Cx<T>* __
   for (int i = 0; i < pl.n7; ++i) {
     stockham_stage<T, 7, ME>(lds, ls, pl.L, P, Ns, tw);
     Ns *= 7;
+  }
+  for (int i = 0; i < pl.nd; ++i) {
+    stockham_stage_dft<T, ME>(lds, ls, pl.L, P, Ns, pl.dr[i], tw);
+    Ns *= pl.dr[i];
   }
 }
 

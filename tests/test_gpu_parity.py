@@ -265,7 +265,7 @@ def test_runs_on_a_side_stream():
 def test_abi_errors():
     eife = _lib()
     with pytest.raises(eife.EIFEError) as e:
-        eife.Grid([11, 8], [0.1, 0.1], 1.0)  # 2N = 22 has a factor 11
+        eife.Grid([4097, 8], [0.1, 0.1], 1.0)  # more than 4096 intervals
     assert e.value.code == -3
     with pytest.raises(eife.EIFEError) as e:
         eife.Grid([8, 8], [0.1, -0.1], 1.0)
@@ -274,8 +274,8 @@ def test_abi_errors():
         eife.Grid([8, 8], [0.1, 0.1], 1.0, bc=7)  # no such boundary condition
     assert e.value.code == -1
     with pytest.raises(eife.EIFEError) as e:
-        eife.Grid([22, 8], [0.1, 0.1], 1.0, bc=eife.BC_PERIODIC)  # periodic N = 22 has a factor 11
-    assert e.value.code == -3
+        eife.Grid([8, 1], [0.1, 0.1], 1.0, bc=eife.BC_PERIODIC)  # fewer than 2 intervals
+    assert e.value.code == -1
     g = eife.Grid([8, 8], [0.1, 0.1], 1.0)
     u = torch.zeros(7, 7, dtype=torch.float64, device="cuda")
     with pytest.raises(eife.EIFEError) as e:
